@@ -1,0 +1,238 @@
+/*
+ * ckks_hip.h -- C ABI of the MI355X (gfx950) RNS-CKKS library.
+ *
+ * The library evaluates the ciphertext arithmetic under TenSEAL's encrypted
+ * tensor operations (arXiv 2104.03152): the context and its keys (section
+ * 2.1), CKKSVector element-wise operations (section 3, table of supported
+ * operations in appendix A.2), the replicated-input dot/vector-matrix product
+ * (section 3.1, appendix A.3), the im2col convolution on one ciphertext
+ * (section 3.2, appendix A.4) and the MNIST-shaped network of section 5.
+ * The scheme is CKKS (Cheon et al. 2017) over Z_Q[X]/(X^N + 1) in RNS form.
+ *
+ * Conventions
+ *  - Handles are opaque.  Every `out` handle is new and owned by the caller,
+ *    who frees it with the matching he_*_free.  Inputs are never consumed or
+ *    modified.
+ *  - Device memory comes from the allocator callbacks given to he_ctx_create
+ *    (NULL: the library's own caching pool over hipMalloc).  Freed blocks are
+ *    cached by the context and reused in stream order.
+ *  - Every operation is enqueued on the context's HIP stream and returns
+ *    before the GPU finishes, except the calls that return host data
+ *    (export, decode, decrypt+decode paths), which synchronise the stream.
+ *    One context per host thread.
+ *  - Levels: a ciphertext at level l holds limbs 0..l of the data-prime chain
+ *    (level L-1 is fresh).  Binary operations on different levels drop limbs
+ *    of the higher operand (exact).  Scales must agree to 2^-20 relative.
+ *  - Rotations are LEFT rotations of the N/2 slots (section 3.1 uses left
+ *    rotations only); a right rotation by r is the left rotation N/2 - r.
+ *  - Status codes: HE_OK = 0 or one of the negative codes below; on error
+ *    `*out` is left NULL and he_last_error() describes the failure.
+ */
+#ifndef CKKS_HIP_H
+#define CKKS_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t he_status;
+enum {
+  HE_OK = 0,
+  HE_EINVAL = -1, /* bad argument (NULL handle, bad size, bad parameters)  */
+  HE_ERANGE = -2, /* more than N/2 values, or an encoded coefficient >= 2^62 */
+  HE_ELEVEL = -3, /* no level left (the leveled limit of section 6)          */
+  HE_ESCALE = -4, /* operand scales differ by more than 2^-20 relative       */
+  HE_ENOKEY = -5, /* missing key (rotation step, or key cut below the level) */
+  HE_EOOM = -6,   /* the allocator returned NULL                             */
+  HE_EHIP = -7    /* a HIP runtime error                                     */
+};
+
+typedef struct he_ctx he_ctx;
+typedef struct he_ct he_ct;     /* ciphertext: 2 polys x (level+1) limbs      */
+typedef struct he_pt he_pt;     /* plaintext: 1 poly x (level+1) limbs        */
+typedef struct he_plan he_plan; /* a composite with its plaintexts prepared   */
+
+/* Device allocator: return `bytes` of device memory (256-byte aligned) or
+ * NULL.  `user` is the alloc_user pointer given to he_ctx_create. */
+typedef void* (*he_alloc_fn)(size_t bytes, void* user);
+typedef void (*he_free_fn)(void* ptr, size_t bytes, void* user);
+
+#define HE_MAX_PRIMES 32
+
+typedef struct {
+  int32_t log_n;     /* ring degree N = 2^log_n, 10 <= log_n <= 14           */
+  int32_t n_primes;  /* data primes + 1 special prime, 2..HE_MAX_PRIMES       */
+  int32_t prime_bits[HE_MAX_PRIMES]; /* bit sizes, data first, special last;
+                        each in [log_n + 2, 61].  For each size in order the
+                        prime is the largest q < 2^b with q = 1 mod 2N that is
+                        not already in the chain.                           */
+  double scale;      /* encoding scale Delta for plaintext operands          */
+  int32_t auto_rescale; /* he_mul_plain / he_mul_relin rescale their result */
+  uint64_t seed;     /* seed of every sampler stream (ChaCha20 key)          */
+} he_params;
+
+/* ---- context and keys (section 2.1) ---- */
+
+/* Create a context: prime chain, NTT tables.  hip_stream: a hipStream_t to
+ * enqueue on (NULL: the library creates a stream of default priority).
+ * Errors: HE_EINVAL for bad parameters, HE_EHIP, HE_EOOM. */
+he_status he_ctx_create(const he_params* params, he_alloc_fn alloc,
+                        he_free_fn free_fn, void* alloc_user, void* hip_stream,
+                        he_ctx** out);
+void he_ctx_destroy(he_ctx* ctx);
+/* primes: n_data_primes + 1 entries (special prime last). */
+he_status he_ctx_info(const he_ctx* ctx, int32_t* log_n, int32_t* n_data_primes,
+                      uint64_t* primes);
+
+/* Secret key (ternary), public key, relinearisation key (for s^2) and one
+ * Galois key per left-rotation step in rot_steps (steps mod N/2, 0 skipped),
+ * all on the device.  Sampling: ChaCha20 streams keyed by params.seed. */
+he_status he_keygen(he_ctx* ctx, const int32_t* rot_steps, size_t n_steps);
+/* One Galois key valid for levels 0..max_level (max_level < 0: top level).
+ * A key cut at a lower level is the exact restriction of the top-level key,
+ * so results are identical; it takes (max_level+1)(max_level+2)/(L(L+1))
+ * of the memory.  Requires he_keygen first (HE_ENOKEY). */
+he_status he_keygen_galois(he_ctx* ctx, int32_t step, int32_t max_level);
+
+/* ---- encoding (section 3: a CKKSVector holds N/2 reals) ---- */
+
+/* Encode n <= N/2 reals into slots 0..n-1 (the rest 0) at `scale`, level
+ * `level`.  Slot j is the evaluation at zeta^(5^j), zeta = exp(i pi/N);
+ * coefficients are round(scale * m_k), ties away from zero, correctly
+ * rounded.  HE_ERANGE: n > N/2 or a coefficient >= 2^62. */
+he_status he_encode(he_ctx* ctx, const double* v, size_t n, double scale,
+                    int32_t level, he_pt** out);
+/* Decode slots 0..n-1 of a plaintext (synchronises). */
+he_status he_decode(he_ctx* ctx, const he_pt* pt, double* out, size_t n);
+/* Plaintext from N signed integer coefficients (reduced into every limb). */
+he_status he_pt_import(he_ctx* ctx, const int64_t* coeffs, double scale,
+                       int32_t level, he_pt** out);
+/* Plaintext residues in coefficient form, [level+1][N]; cap in words. */
+he_status he_pt_export(he_ctx* ctx, const he_pt* pt, uint64_t* coeff_form,
+                       size_t cap, int32_t* level, double* scale);
+
+/* ---- encryption ---- */
+
+/* Public-key encryption (use_secret_key = 0): (v*pk0 + e0 + m, v*pk1 + e1);
+ * secret-key: (-a*s + e + m, a).  enc_index selects the sampler streams, so
+ * equal indices give equal ciphertexts. */
+he_status he_encrypt(he_ctx* ctx, const he_pt* pt, uint32_t enc_index,
+                     int32_t use_secret_key, he_ct** out);
+/* m = c0 + c1*s at the ciphertext's level and scale. */
+he_status he_decrypt(he_ctx* ctx, const he_ct* ct, he_pt** out);
+
+/* Ciphertext residues in coefficient form, [2][level+1][N]; cap in words. */
+he_status he_ct_export(he_ctx* ctx, const he_ct* ct, uint64_t* coeff_form,
+                       size_t cap, int32_t* level, double* scale);
+he_status he_ct_import(he_ctx* ctx, const uint64_t* coeff_form, int32_t level,
+                       double scale, he_ct** out);
+he_status he_ct_info(const he_ct* ct, int32_t* level, double* scale);
+
+/* ---- element-wise operations (section 3; appendix A.2) ---- */
+he_status he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
+he_status he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
+he_status he_negate(he_ctx* ctx, const he_ct* a, he_ct** out);
+/* plaintext at the ciphertext's scale, level >= the ciphertext's */
+he_status he_add_plain(he_ctx* ctx, const he_ct* a, const he_pt* p, he_ct** out);
+/* ciphertext x plaintext; scale multiplies; rescales if auto_rescale */
+he_status he_mul_plain(he_ctx* ctx, const he_ct* a, const he_pt* p, he_ct** out);
+/* tensor product, relinearisation with the s^2 key; rescales if auto_rescale */
+he_status he_mul_relin(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
+/* he_mul_relin(a, a) */
+he_status he_square(he_ctx* ctx, const he_ct* a, he_ct** out);
+/* round(c / q_l) onto limbs 0..l-1; scale / q_l.  HE_ELEVEL at level 0. */
+he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out);
+/* drop limbs down to `level` (exact) */
+he_status he_drop_to(he_ctx* ctx, const he_ct* a, int32_t level, he_ct** out);
+/* left rotation of the slots by step: X -> X^(5^step mod 2N) and a key
+ * switch with the Galois key of that step (HE_ENOKEY if none). */
+he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out);
+
+/* ---- composites (sections 3.1, 3.2; appendix A.3, A.4) ---- */
+
+/* x <- x + rot(x, 2^j), j < ceil(log2 n): slot 0 gets the sum of slots
+ * 0..n-1 (the rotate-and-sum of the dot product). */
+he_status he_sum_slots(he_ctx* ctx, const he_ct* a, uint32_t n, he_ct** out);
+/* im2col convolution: slot k*windows + w of x holds pixel k of window w
+ * (vertical scan).  Multiply by the kernel replicated over the windows
+ * (scale Delta), rescale, add ceil(log2 kk) left rotations by windows*2^j,
+ * and add `bias` to slots 0..windows-1.  Result in slots 0..windows-1. */
+he_status he_enc_conv_im2col(he_ctx* ctx, const he_ct* x, const double* kernel,
+                             uint32_t kk, uint32_t windows, double bias,
+                             he_ct** out);
+/* vector-matrix product y = x W + bias, W row-major n_in x n_out: replicate
+ * x (zero beyond n_in) by right rotations n_in*2^j while the copies fit in
+ * N/2 slots, then y = sum_i rot_left(x_rep, i) * diag_i with
+ * diag_i[j] = W[(i+j) mod n_in][j] (j < n_out), one rescale, bias added.
+ * The n_in - 1 rotations of x_rep share one digit decomposition (hoisted);
+ * results are identical to rotating one by one. */
+he_status he_enc_matmul(he_ctx* ctx, const he_ct* x, const double* W,
+                        uint32_t n_in, uint32_t n_out, const double* bias,
+                        he_ct** out);
+/* mask part c to slots 0..width-1 (ones at Delta), rescale, rotate right by
+ * width*c, add: n_parts vectors of `width` packed side by side. */
+he_status he_pack(he_ctx* ctx, he_ct* const* parts, uint32_t n_parts,
+                  uint32_t width, he_ct** out);
+
+/* Prepared composites: the plaintext operands (replicated kernel, matrix
+ * diagonals, biases) are encoded once for inputs at `like`'s level and
+ * scale and kept on the device; he_plan_apply then runs the composite with
+ * bit-identical results to the one-shot calls above. */
+he_status he_conv_plan(he_ctx* ctx, const he_ct* like, const double* kernel,
+                       uint32_t kk, uint32_t windows, double bias,
+                       he_plan** out);
+he_status he_matmul_plan(he_ctx* ctx, const he_ct* like, const double* W,
+                         uint32_t n_in, uint32_t n_out, const double* bias,
+                         he_plan** out);
+/* HE_ELEVEL / HE_ESCALE if x does not match the plan's level and scale. */
+he_status he_plan_apply(he_ctx* ctx, const he_plan* plan, const he_ct* x,
+                        he_ct** out);
+
+/* ---- raw transforms (batched negacyclic NTT on caller device buffers) ---- */
+/* data: device pointer to n_polys polynomials of n_limbs limbs, layout
+ * [n_polys][n_limbs][N] u64, limb i under data prime i, residues in [0, q_i).
+ * In place, enqueued on the context stream. */
+he_status he_ntt_forward(he_ctx* ctx, uint64_t* data, size_t n_polys,
+                         int32_t n_limbs);
+he_status he_ntt_inverse(he_ctx* ctx, uint64_t* data, size_t n_polys,
+                         int32_t n_limbs);
+
+/* ---- keys for parity checks ---- */
+he_status he_export_secret(he_ctx* ctx, int64_t* s); /* N ternary coeffs */
+/* kind 0: relinearisation key, kind 1: Galois key of `step`.  Coefficient
+ * form, layout [digit j][poly k][modulus t][N], t = 0..max_level then the
+ * special prime; cap in words. */
+he_status he_export_key(he_ctx* ctx, int32_t kind, int32_t step,
+                        uint64_t* out, size_t cap, int32_t* max_level);
+
+/* ---- housekeeping ---- */
+void he_ct_free(he_ct* ct);
+void he_pt_free(he_pt* pt);
+void he_plan_free(he_plan* plan);
+he_status he_sync(he_ctx* ctx);
+/* message of the calling thread's last failure ("" if none) */
+const char* he_last_error(void);
+size_t he_ct_bytes(const he_ct* ct);    /* device bytes held by a ciphertext */
+size_t he_key_bytes(const he_ctx* ctx); /* device bytes held by all keys    */
+/* plain im2col (client side, section 3.2): out[(ky*k + kx)*windows + w] =
+ * img[(oy*stride + ky)*w_img + ox*stride + kx], w = oy*ow + ox. */
+void he_im2col(const double* img, uint32_t h, uint32_t w, uint32_t k,
+               uint32_t stride, double* out);
+
+/* ---- kernel timing: HIP events around each launch of a named kernel
+ * family while enabled (adds no work to the kernels themselves). ---- */
+he_status he_profile_enable(he_ctx* ctx, int32_t enable);
+/* launches and summed milliseconds of a kernel family since enabling
+ * (synchronises).  Families: "ntt_fwd", "ntt_inv", "modup", "moddown",
+ * "keyswitch_inner", "hoisted_inner", "hoisted_moddown", "pointwise",
+ * "rescale", "sample". */
+he_status he_profile_read(he_ctx* ctx, const char* family, uint64_t* launches,
+                          double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1481 @@
+// ckks.cpp -- host side of the MI355X RNS-CKKS library: context, prime chain
+// and tables, caching device allocator, keys, encryption and every operation
+// of include/ckks_hip.h, sequenced as kernel launches on the context stream.
+//
+// Ciphertext and plaintext polynomials live on the device in the NTT domain,
+// limb-major [poly][limb][N] u64 with residues in [0, q_i).  Keys are kept in
+// the NTT domain and in Montgomery form, layout [digit][poly][modulus][N].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ckks_hip.h"
+#include "device.h"
+#include "encode.h"
+
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------- errors
+static thread_local char g_msg[512];
+
+static he_status fail(he_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPC(x)                                                                      \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) return fail(HE_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+#define TRY(x)                 \
+  do {                         \
+    he_status s_ = (x);        \
+    if (s_ != HE_OK) return s_; \
+  } while (0)
+
+// ---------------------------------------------------------------- host modular arithmetic
+static u64 h_mulm(u64 a, u64 b, u64 q) { return (u64)((u128)a * b % q); }
+static u64 h_powm(u64 a, u64 e, u64 q) {
+  u64 r = 1;
+  a %= q;
+  for (; e; e >>= 1) {
+    if (e & 1) r = h_mulm(r, a, q);
+    a = h_mulm(a, a, q);
+  }
+  return r;
+}
+static u64 h_inv(u64 a, u64 q) { return h_powm(a % q, q - 2, q); }
+static bool h_is_prime(u64 n) {
+  if (n < 2) return false;
+  const u64 small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (u64 p : small)
+    if (n % p == 0) return n == p;
+  u64 d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) d >>= 1, s++;
+  for (u64 a : small) {
+    u64 x = h_powm(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s && comp; r++) {
+      x = h_mulm(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+static u64 h_shoup(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+static uint32_t h_brv(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; i++) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+// ---------------------------------------------------------------- allocator
+struct Pool {
+  he_alloc_fn alloc = nullptr;
+  he_free_fn release = nullptr;
+  void* user = nullptr;
+  std::unordered_map<size_t, std::vector<void*>> cache;
+  std::unordered_map<void*, size_t> live;
+  size_t bytes_live = 0;
+
+  void* raw_alloc(size_t b) {
+    if (alloc) return alloc(b, user);
+    void* p = nullptr;
+    return hipMalloc(&p, b) == hipSuccess ? p : nullptr;
+  }
+  void raw_free(void* p, size_t b) {
+    if (release)
+      release(p, b, user);
+    else
+      (void)hipFree(p);
+  }
+  void trim() {
+    for (auto& kv : cache)
+      for (void* p : kv.second) raw_free(p, kv.first);
+    cache.clear();
+  }
+  void* get(size_t bytes) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bytes == 0) bytes = 256;
+    auto it = cache.find(bytes);
+    void* p = nullptr;
+    if (it != cache.end() && !it->second.empty()) {
+      p = it->second.back();
+      it->second.pop_back();
+    } else {
+      p = raw_alloc(bytes);
+      if (!p) {
+        trim();
+        p = raw_alloc(bytes);
+      }
+      if (!p) return nullptr;
+    }
+    live[p] = bytes;
+    bytes_live += bytes;
+    return p;
+  }
+  void put(void* p) {
+    if (!p) return;
+    auto it = live.find(p);
+    if (it == live.end()) return;
+    cache[it->second].push_back(p);
+    bytes_live -= it->second;
+    live.erase(it);
+  }
+  void destroy() {
+    trim();
+    for (auto& kv : live) raw_free(kv.first, kv.second);
+    live.clear();
+  }
+};
+
+// ---------------------------------------------------------------- objects
+struct Key {
+  int ml = -1;  // valid for levels 0..ml
+  u64* d = nullptr;
+  size_t bytes = 0;
+};
+
+struct ProfRec {
+  std::string fam;
+  hipEvent_t a, b;
+};
+
+struct he_ctx {
+  int log_n = 0, n = 0, L = 0;
+  std::vector<u64> q;  // L data primes then the special prime
+  double scale = 0;
+  int auto_rescale = 0;
+  u64 seed = 0;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  Pool pool;
+  PrimeDev* d_primes = nullptr;
+  u64* d_fwd = nullptr;
+  u64* d_inv = nullptr;
+  bool have_keys = false;
+  u64* d_s = nullptr;   // [L+1][N]
+  u64* d_pk = nullptr;  // [2][L][N]
+  Key relin;
+  std::map<int, Key> gal;
+  EncodeTables enc;
+  std::map<std::pair<int, int>, he_pt*> masks;
+  bool prof = false;
+  std::vector<ProfRec> prof_recs;
+};
+
+struct he_ct {
+  he_ctx* ctx;
+  int level;
+  double scale;
+  u64* d;
+};
+struct he_pt {
+  he_ctx* ctx;
+  int level;
+  double scale;
+  u64* d;
+};
+
+enum PlanKind { PLAN_CONV = 1, PLAN_MATMUL = 2 };
+struct he_plan {
+  he_ctx* ctx;
+  int kind;
+  int level;      // input level
+  double scale;   // input scale
+  uint32_t kk = 0, windows = 0;  // conv
+  uint32_t n_in = 0, n_out = 0;  // matmul
+  he_pt* kernel = nullptr;       // conv plaintext
+  std::vector<he_pt*> diags;     // matmul diagonals
+  he_pt* bias = nullptr;         // at the post-rescale scale and level
+};
+
+namespace {
+
+// ---------------------------------------------------------------- profiling
+struct Prof {
+  he_ctx* c;
+  const char* fam;
+  hipEvent_t a{}, b{};
+  bool on;
+  Prof(he_ctx* c_, const char* f) : c(c_), fam(f), on(c_->prof) {
+    if (on) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, c->st);
+    }
+  }
+  ~Prof() {
+    if (on) {
+      (void)hipEventRecord(b, c->st);
+      c->prof_recs.push_back({fam, a, b});
+    }
+  }
+};
+
+// ---------------------------------------------------------------- buffers
+struct DBuf {
+  he_ctx* c = nullptr;
+  u64* p = nullptr;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() {
+    if (p) c->pool.put(p);
+  }
+};
+
+he_status dalloc(he_ctx* c, DBuf& b, size_t words) {
+  b.c = c;
+  b.p = (u64*)c->pool.get(words * sizeof(u64));
+  if (!b.p) return fail(HE_EOOM, "device allocation of %zu bytes failed", words * sizeof(u64));
+  return HE_OK;
+}
+
+size_t ct_words(const he_ctx* c, int level) { return 2 * (size_t)(level + 1) * c->n; }
+size_t pt_words(const he_ctx* c, int level) { return (size_t)(level + 1) * c->n; }
+
+he_status new_ct(he_ctx* c, int level, double scale, he_ct** out) {
+  u64* d = (u64*)c->pool.get(ct_words(c, level) * sizeof(u64));
+  if (!d) return fail(HE_EOOM, "ciphertext allocation failed");
+  *out = new he_ct{c, level, scale, d};
+  return HE_OK;
+}
+he_status new_pt(he_ctx* c, int level, double scale, he_pt** out) {
+  u64* d = (u64*)c->pool.get(pt_words(c, level) * sizeof(u64));
+  if (!d) return fail(HE_EOOM, "plaintext allocation failed");
+  *out = new he_pt{c, level, scale, d};
+  return HE_OK;
+}
+struct CtGuard {  // frees an intermediate ciphertext on scope exit
+  he_ct* p = nullptr;
+  ~CtGuard() { he_ct_free(p); }
+};
+struct PtGuard {
+  he_pt* p = nullptr;
+  ~PtGuard() { he_pt_free(p); }
+};
+
+ModList mods_range(int n) {
+  ModList m{};
+  m.n = n;
+  for (int i = 0; i < n; i++) m.p[i] = (unsigned char)i;
+  return m;
+}
+
+bool scales_match(double a, double b) {
+  double m = std::fmax(std::fabs(a), std::fabs(b));
+  return std::fabs(a - b) <= std::ldexp(m, -20);
+}
+
+// ---------------------------------------------------------------- NTT helpers
+// in-place or out-of-place batched transform of n_poly polys x n_limbs limbs
+he_status ntt_rows(he_ctx* c, bool fwd, const u64* src, u64* dst, int n_poly, int n_limbs,
+                   long long poly_stride_src, long long poly_stride_dst) {
+  NttJob J{};
+  J.src = src;
+  J.dst = dst;
+  J.na = n_poly;
+  J.nb = n_limbs;
+  J.sa = poly_stride_src;
+  J.sb = c->n;
+  J.da = poly_stride_dst;
+  J.db = c->n;
+  J.src_prime = 0;
+  for (int i = 0; i < n_limbs; i++) J.dst_prime[i] = (unsigned char)i;
+  Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv");
+  hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->d_fwd, c->st)
+                     : launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "ntt launch: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
+// rows with an explicit prime per limb (keys: the last modulus is special)
+he_status ntt_rows_mods(he_ctx* c, bool fwd, const u64* src, u64* dst, int n_poly, const ModList& mods) {
+  NttJob J{};
+  J.src = src;
+  J.dst = dst;
+  J.na = n_poly;
+  J.nb = mods.n;
+  J.sa = (long long)mods.n * c->n;
+  J.sb = c->n;
+  J.da = J.sa;
+  J.db = c->n;
+  J.src_prime = 0;
+  for (int i = 0; i < mods.n; i++) J.dst_prime[i] = mods.p[i];
+  Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv");
+  hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->d_fwd, c->st)
+                     : launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "ntt launch: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
+// dst = round(u / q_src) over targets 0..n_t-1: src_coef [2][N] holds the
+// coefficient form of the divisor limb of each of the 2 polys; u is the NTT
+// domain dividend [2][..][N] with poly stride ua; result poly stride da.
+he_status round_div(he_ctx* c, const u64* src_coef, int src_prime, const u64* u, long long ua, u64* dst,
+                    long long da, int n_t, const u64* add0, const u64* add1, const char* fam) {
+  NttJob J{};
+  J.src = src_coef;
+  J.sa = c->n;
+  J.sb = 0;
+  J.dst = dst;
+  J.da = da;
+  J.db = c->n;
+  J.na = 2;
+  J.nb = n_t;
+  J.src_prime = src_prime;
+  J.u = u;
+  J.ua = ua;
+  J.ub = c->n;
+  J.add0 = add0;
+  J.add1 = add1;
+  J.ab = c->n;
+  const u64 p = c->q[src_prime];
+  J.h_src = (p - 1) / 2;
+  for (int t = 0; t < n_t; t++) {
+    const u64 qt = c->q[t];
+    J.dst_prime[t] = (unsigned char)t;
+    J.hq[t] = J.h_src % qt;
+    J.inv[t] = h_inv(p % qt, qt);
+    J.inv_sh[t] = h_shoup(J.inv[t], qt);
+  }
+  Prof pr(c, fam);
+  hipError_t e = launch_ntt_fwd(c->log_n, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV, J, c->d_primes, c->d_fwd, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "round_div launch: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
+// ---------------------------------------------------------------- key switching
+// out [2][l+1][N] = KeySwitch(d) (+ addends), d: NTT domain [l+1][N]
+he_status key_switch(he_ctx* c, const u64* d, int l, const Key& key, const u64* add0, const u64* add1,
+                     u64* out) {
+  const int n = c->n, Lp = l + 1, nm = Lp + 1;
+  if (key.ml < l) return fail(HE_ENOKEY, "key valid up to level %d, ciphertext at level %d", key.ml, l);
+  DBuf coef, ext, u, ucoef;
+  TRY(dalloc(c, coef, (size_t)Lp * n));
+  TRY(dalloc(c, ext, (size_t)Lp * nm * n));
+  TRY(dalloc(c, u, 2 * (size_t)nm * n));
+  TRY(dalloc(c, ucoef, 2 * (size_t)n));
+  TRY(ntt_rows(c, false, d, coef.p, 1, Lp, 0, 0));
+  {  // ModUp: centred digit j lifted to every other modulus, then NTT
+    NttJob J{};
+    J.src = coef.p;
+    J.sa = n;
+    J.sb = 0;
+    J.dst = ext.p;
+    J.da = (long long)nm * n;
+    J.db = n;
+    J.na = Lp;
+    J.nb = nm;
+    J.skip_diag = 1;
+    J.src_prime = -1;
+    for (int j = 0; j < Lp; j++) J.src_prime_of_a[j] = (unsigned char)j;
+    for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
+    Prof pr(c, "modup");
+    hipError_t e = launch_ntt_fwd(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, J, c->d_primes, c->d_fwd, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "modup: %s", hipGetErrorString(e));
+  }
+  {
+    InnerJob I{};
+    I.ext = ext.p;
+    I.diag = d;
+    I.key = key.d;
+    I.u = u.p;
+    I.n_dig = Lp;
+    I.key_digits = key.ml + 1;
+    I.key_mods = key.ml + 2;
+    I.special_prime = c->L;
+    I.gather_g = 1;
+    Prof pr(c, "keyswitch_inner");
+    hipError_t e = launch_inner(c->log_n, I, c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "inner: %s", hipGetErrorString(e));
+  }
+  {  // special-prime limbs back to coefficients
+    NttJob J{};
+    J.src = u.p + (size_t)Lp * n;
+    J.sa = (long long)nm * n;
+    J.dst = ucoef.p;
+    J.da = n;
+    J.na = 2;
+    J.nb = 1;
+    J.dst_prime[0] = (unsigned char)c->L;
+    Prof pr(c, "ntt_inv");
+    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "intt special: %s", hipGetErrorString(e));
+  }
+  return round_div(c, ucoef.p, c->L, u.p, (long long)nm * n, out, (long long)Lp * n, Lp, add0, add1, "moddown");
+}
+
+// copy a ciphertext's limbs 0..level into a fresh buffer layout
+he_status drop_copy(he_ctx* c, const he_ct* a, int level, he_ct** out) {
+  TRY(new_ct(c, level, a->scale, out));
+  const size_t row = (size_t)(level + 1) * c->n * sizeof(u64);
+  for (int k = 0; k < 2; k++)
+    HIPC(hipMemcpyAsync((*out)->d + (size_t)k * (level + 1) * c->n, a->d + (size_t)k * (a->level + 1) * c->n,
+                        row, hipMemcpyDeviceToDevice, c->st));
+  return HE_OK;
+}
+
+// bring two ciphertexts to a common level; the returned guards own copies
+he_status align2(he_ctx* c, const he_ct* a, const he_ct* b, const he_ct** ra, const he_ct** rb, CtGuard& ga,
+                 CtGuard& gb) {
+  *ra = a;
+  *rb = b;
+  if (a->level > b->level) {
+    TRY(drop_copy(c, a, b->level, &ga.p));
+    *ra = ga.p;
+  } else if (b->level > a->level) {
+    TRY(drop_copy(c, b, a->level, &gb.p));
+    *rb = gb.p;
+  }
+  return HE_OK;
+}
+
+u64 galois_elt(const he_ctx* c, int step) {
+  return h_powm(5, (u64)step, 2 * (u64)c->n);
+}
+
+int norm_step(const he_ctx* c, long long step) {
+  long long half = c->n / 2;
+  step %= half;
+  if (step < 0) step += half;
+  return (int)step;
+}
+
+// ---------------------------------------------------------------- key generation
+// switching key from s' (NTT domain [L+1][N]) to s, valid up to level ml
+he_status make_key(he_ctx* c, Key& key, int ml, const u64* sp, uint32_t tag_a, uint32_t tag_e, uint32_t base) {
+  const int n = c->n, nd = ml + 1, nm = ml + 2;
+  ModList pidx{};
+  pidx.n = nm;
+  for (int t = 0; t < nm; t++) pidx.p[t] = (unsigned char)(t <= ml ? t : c->L);
+  DBuf A, E;
+  TRY(dalloc(c, A, (size_t)nd * nm * n));
+  TRY(dalloc(c, E, (size_t)nd * nm * n));
+  {
+    Prof pr(c, "sample");
+    hipError_t e = launch_sample_uniform(c->log_n, c->seed, tag_a, base, nd, pidx, pidx, A.p, c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "sample uniform: %s", hipGetErrorString(e));
+    for (int j = 0; j < nd; j++) {
+      e = launch_sample_small(c->log_n, 1, c->seed, tag_e, base + (uint32_t)j, pidx, E.p + (size_t)j * nm * n,
+                              c->d_primes, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "sample gaussian: %s", hipGetErrorString(e));
+    }
+  }
+  TRY(ntt_rows_mods(c, true, A.p, A.p, nd, pidx));
+  TRY(ntt_rows_mods(c, true, E.p, E.p, nd, pidx));
+  const size_t words = (size_t)nd * 2 * nm * n;
+  u64* kd = (u64*)c->pool.get(words * sizeof(u64));
+  if (!kd) return fail(HE_EOOM, "key allocation failed");
+  hipError_t e = launch_keygen_combine(c->log_n, A.p, E.p, c->d_s, sp, kd, nd, nm, pidx, c->L, c->d_primes, c->st);
+  if (e != hipSuccess) {
+    c->pool.put(kd);
+    return fail(HE_EHIP, "keygen combine: %s", hipGetErrorString(e));
+  }
+  if (key.d) c->pool.put(key.d);
+  key.d = kd;
+  key.ml = ml;
+  key.bytes = words * sizeof(u64);
+  return HE_OK;
+}
+
+he_status galois_key(he_ctx* c, int step, int ml) {
+  if (!c->have_keys) return fail(HE_ENOKEY, "he_keygen must run first");
+  step = norm_step(c, step);
+  if (step == 0) return HE_OK;
+  if (ml < 0 || ml >= c->L) ml = c->L - 1;
+  auto it = c->gal.find(step);
+  if (it != c->gal.end() && it->second.ml >= ml) return HE_OK;
+  DBuf sp;
+  TRY(dalloc(c, sp, (size_t)(c->L + 1) * c->n));
+  hipError_t e = launch_automorphism(c->log_n, c->d_s, sp.p, c->L + 1, galois_elt(c, step), c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "automorphism: %s", hipGetErrorString(e));
+  Key& k = c->gal[step];
+  return make_key(c, k, ml, sp.p, 6, 7, (uint32_t)step * 256u);
+}
+
+// ---------------------------------------------------------------- encode helpers
+he_status upload_coeffs(he_ctx* c, const int64_t* co, int level, double scale, he_pt** out) {
+  const int n = c->n, Lp = level + 1;
+  std::vector<u64> h((size_t)Lp * n);
+  for (int i = 0; i < Lp; i++) {
+    const u64 q = c->q[i];
+    for (int k = 0; k < n; k++) {
+      int64_t v = co[k];
+      u64 r;
+      if (v >= 0) {
+        r = (u64)v % q;
+      } else {
+        u64 m = (u64)(-(v + 1)) + 1u;
+        r = m % q;
+        r = r ? q - r : 0;
+      }
+      h[(size_t)i * n + k] = r;
+    }
+  }
+  he_pt* pt = nullptr;
+  TRY(new_pt(c, level, scale, &pt));
+  hipError_t e = hipMemcpyAsync(pt->d, h.data(), h.size() * sizeof(u64), hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) {
+    he_pt_free(pt);
+    return fail(HE_EHIP, "plaintext upload: %s", hipGetErrorString(e));
+  }
+  he_status s = ntt_rows(c, true, pt->d, pt->d, 1, Lp, 0, 0);
+  if (s != HE_OK) {
+    he_pt_free(pt);
+    return s;
+  }
+  *out = pt;
+  return HE_OK;
+}
+
+he_status encode_impl(he_ctx* c, const double* v, size_t n, double scale, int level, he_pt** out) {
+  if (level < 0 || level >= c->L) return fail(HE_ELEVEL, "level %d outside 0..%d", level, c->L - 1);
+  if (n > (size_t)c->n / 2) return fail(HE_ERANGE, "%zu values exceed N/2 = %d slots", n, c->n / 2);
+  if (!(scale > 0) || !std::isfinite(scale)) return fail(HE_EINVAL, "bad scale");
+  std::vector<int64_t> co(c->n);
+  if (encode_coeffs(c->enc, v, n, scale, co.data()) != 0)
+    return fail(HE_ERANGE, "encoded coefficient reaches 2^62 (or a value is not finite)");
+  return upload_coeffs(c, co.data(), level, scale, out);
+}
+
+// coefficient form of rows (INTT on a copy) copied to the host
+he_status download_coeff(he_ctx* c, const u64* d, int n_poly, int Lp, std::vector<u64>& h) {
+  const size_t words = (size_t)n_poly * Lp * c->n;
+  DBuf tmp;
+  TRY(dalloc(c, tmp, words));
+  TRY(ntt_rows(c, false, d, tmp.p, n_poly, Lp, (long long)Lp * c->n, (long long)Lp * c->n));
+  h.resize(words);
+  HIPC(hipMemcpyAsync(h.data(), tmp.p, words * sizeof(u64), hipMemcpyDeviceToHost, c->st));
+  HIPC(hipStreamSynchronize(c->st));
+  return HE_OK;
+}
+
+// centred value of each coefficient as a double (approximate CRT: the
+// quotient sum_i y_i / q_i is rounded in FP64, the value itself is formed
+// exactly mod 2^128, which holds any value a valid decryption produces)
+void crt_centered(const he_ctx* c, const u64* res, int Lp, double* out) {
+  const int n = c->n;
+  std::vector<u64> inv(Lp);
+  std::vector<u128> qhat(Lp);
+  u128 Q = 1;
+  for (int i = 0; i < Lp; i++) Q *= (u128)c->q[i];
+  for (int i = 0; i < Lp; i++) {
+    u64 r = 1;
+    u128 h = 1;
+    for (int j = 0; j < Lp; j++)
+      if (j != i) {
+        r = h_mulm(r, c->q[j] % c->q[i], c->q[i]);
+        h *= (u128)c->q[j];
+      }
+    inv[i] = h_inv(r, c->q[i]);
+    qhat[i] = h;
+  }
+  for (int k = 0; k < n; k++) {
+    double frac = 0;
+    u128 acc = 0;
+    for (int i = 0; i < Lp; i++) {
+      const u64 y = h_mulm(res[(size_t)i * n + k], inv[i], c->q[i]);
+      frac += (double)y / (double)c->q[i];
+      acc += (u128)y * qhat[i];
+    }
+    const u128 v = (u128)(unsigned long long)std::floor(frac + 0.5);
+    acc -= v * Q;
+    __int128 s = (__int128)acc;
+    out[k] = (double)s;
+  }
+}
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char* he_last_error(void) { return g_msg; }
+
+he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_fn, void* alloc_user,
+                        void* hip_stream, he_ctx** out) {
+  if (!P || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (P->log_n < 10 || P->log_n > 14) return fail(HE_EINVAL, "log_n %d outside 10..14", P->log_n);
+  if (P->n_primes < 2 || P->n_primes > HE_MAX_PRIMES) return fail(HE_EINVAL, "n_primes %d", P->n_primes);
+  if ((alloc == nullptr) != (free_fn == nullptr)) return fail(HE_EINVAL, "allocator needs both callbacks");
+  const int n = 1 << P->log_n;
+  // prime chain
+  std::vector<u64> q;
+  const u64 m = 2 * (u64)n;
+  for (int i = 0; i < P->n_primes; i++) {
+    const int b = P->prime_bits[i];
+    if (b < P->log_n + 2 || b > 60) return fail(HE_EINVAL, "prime bit size %d outside %d..60", b, P->log_n + 2);
+    u64 cand = (((1ull << b) - 2) / m) * m + 1;
+    bool found = false;
+    for (; cand > (1ull << (b - 1)); cand -= m) {
+      bool used = false;
+      for (u64 x : q) used |= (x == cand);
+      if (!used && h_is_prime(cand)) {
+        found = true;
+        break;
+      }
+    }
+    if (!found) return fail(HE_EINVAL, "no %d-bit prime = 1 mod 2N left", b);
+    q.push_back(cand);
+  }
+  he_ctx* c = new he_ctx();
+  c->log_n = P->log_n;
+  c->n = n;
+  c->L = P->n_primes - 1;
+  c->q = q;
+  c->scale = P->scale;
+  c->auto_rescale = P->auto_rescale;
+  c->seed = P->seed;
+  c->pool.alloc = alloc;
+  c->pool.release = free_fn;
+  c->pool.user = alloc_user;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(HE_EHIP, "no HIP device");
+  }
+  if (hip_stream) {
+    c->st = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(HE_EHIP, "stream creation failed");
+    }
+    c->own_stream = true;
+  }
+  // per-prime constants and twiddles
+  const int np = (int)q.size();
+  std::vector<PrimeDev> hp(np);
+  std::vector<u64> fwd((size_t)np * n * 2), inv((size_t)np * n * 2);
+  for (int i = 0; i < np; i++) {
+    const u64 qi = q[i];
+    PrimeDev& d = hp[i];
+    d.q = qi;
+    d.k = 64 - __builtin_clzll(qi);
+    d.mu = (u64)(((u128)1 << (2 * d.k)) / qi);
+    d.mu64 = ~0ull / qi;
+    u64 inv64 = 1;  // Newton: inverse of q mod 2^64
+    for (int it = 0; it < 7; it++) inv64 *= 2 - qi * inv64;
+    d.qinv_neg = (u64)0 - inv64;
+    u64 r64 = (u64)((((u128)1) << 64) % qi);
+    d.r2 = h_mulm(r64, r64, qi);
+    d.ninv = h_inv((u64)n % qi, qi);
+    d.ninv_sh = h_shoup(d.ninv, qi);
+    // primitive 2N-th root of unity
+    u64 psi = 0;
+    for (u64 g = 2;; g++) {
+      u64 x = h_powm(g, (qi - 1) / m, qi);
+      if (h_powm(x, (u64)n, qi) == qi - 1) {
+        psi = x;
+        break;
+      }
+    }
+    const u64 ipsi = h_inv(psi, qi);
+    std::vector<u64> pw(n), ipw(n);
+    pw[0] = ipw[0] = 1;
+    for (int k = 1; k < n; k++) {
+      pw[k] = h_mulm(pw[k - 1], psi, qi);
+      ipw[k] = h_mulm(ipw[k - 1], ipsi, qi);
+    }
+    for (int k = 0; k < n; k++) {
+      const uint32_t r = h_brv((uint32_t)k, P->log_n);
+      const size_t o = ((size_t)i * n + k) * 2;
+      fwd[o] = pw[r];
+      fwd[o + 1] = h_shoup(pw[r], qi);
+      inv[o] = ipw[r];
+      inv[o + 1] = h_shoup(ipw[r], qi);
+    }
+  }
+  c->d_primes = (PrimeDev*)c->pool.get(sizeof(PrimeDev) * np);
+  c->d_fwd = (u64*)c->pool.get(fwd.size() * sizeof(u64));
+  c->d_inv = (u64*)c->pool.get(inv.size() * sizeof(u64));
+  if (!c->d_primes || !c->d_fwd || !c->d_inv) {
+    he_ctx_destroy(c);
+    return fail(HE_EOOM, "table allocation failed");
+  }
+  if (hipMemcpy(c->d_primes, hp.data(), sizeof(PrimeDev) * np, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_fwd, fwd.data(), fwd.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_inv, inv.data(), inv.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess) {
+    he_ctx_destroy(c);
+    return fail(HE_EHIP, "table upload failed");
+  }
+  encode_tables_init(c->enc, c->log_n);
+  *out = c;
+  return HE_OK;
+}
+
+void he_ctx_destroy(he_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  for (auto& kv : c->masks) he_pt_free(kv.second);
+  c->masks.clear();
+  for (auto& r : c->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->pool.destroy();
+  if (c->own_stream) (void)hipStreamDestroy(c->st);
+  delete c;
+}
+
+he_status he_ctx_info(const he_ctx* c, int32_t* log_n, int32_t* n_data, uint64_t* primes) {
+  if (!c) return fail(HE_EINVAL, "NULL context");
+  if (log_n) *log_n = c->log_n;
+  if (n_data) *n_data = c->L;
+  if (primes)
+    for (size_t i = 0; i < c->q.size(); i++) primes[i] = c->q[i];
+  return HE_OK;
+}
+
+he_status he_keygen(he_ctx* c, const int32_t* steps, size_t n_steps) {
+  if (!c) return fail(HE_EINVAL, "NULL context");
+  const int n = c->n, L = c->L;
+  if (!c->have_keys) {
+    u64* s = (u64*)c->pool.get((size_t)(L + 1) * n * sizeof(u64));
+    u64* pk = (u64*)c->pool.get(2 * (size_t)L * n * sizeof(u64));
+    if (!s || !pk) return fail(HE_EOOM, "key allocation failed");
+    c->d_s = s;
+    c->d_pk = pk;
+    ModList all = mods_range(L + 1), data = mods_range(L);
+    {
+      Prof pr(c, "sample");
+      hipError_t e = launch_sample_small(c->log_n, 0, c->seed, 1, 0, all, s, c->d_primes, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "sample s: %s", hipGetErrorString(e));
+    }
+    TRY(ntt_rows(c, true, s, s, 1, L + 1, 0, 0));
+    DBuf A, E;
+    TRY(dalloc(c, A, (size_t)L * n));
+    TRY(dalloc(c, E, (size_t)L * n));
+    {
+      Prof pr(c, "sample");
+      hipError_t e = launch_sample_uniform(c->log_n, c->seed, 2, 0, 1, data, data, A.p, c->d_primes, c->st);
+      if (e == hipSuccess) e = launch_sample_small(c->log_n, 1, c->seed, 3, 0, data, E.p, c->d_primes, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "sample pk: %s", hipGetErrorString(e));
+    }
+    TRY(ntt_rows(c, true, A.p, A.p, 1, L, 0, 0));
+    TRY(ntt_rows(c, true, E.p, E.p, 1, L, 0, 0));
+    hipError_t e = launch_pk_combine(c->log_n, A.p, E.p, s, pk, L, c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "pk: %s", hipGetErrorString(e));
+    HIPC(hipMemcpyAsync(pk + (size_t)L * n, A.p, (size_t)L * n * sizeof(u64), hipMemcpyDeviceToDevice, c->st));
+    // relinearisation key for s^2
+    DBuf s2;
+    TRY(dalloc(c, s2, (size_t)(L + 1) * n));
+    e = launch_mul_plain(c->log_n, s, s, s2.p, 1, all, c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "s^2: %s", hipGetErrorString(e));
+    TRY(make_key(c, c->relin, L - 1, s2.p, 4, 5, 0));
+    c->have_keys = true;
+  }
+  for (size_t i = 0; i < n_steps; i++) TRY(galois_key(c, steps[i], -1));
+  HIPC(hipStreamSynchronize(c->st));
+  return HE_OK;
+}
+
+he_status he_keygen_galois(he_ctx* c, int32_t step, int32_t max_level) {
+  if (!c) return fail(HE_EINVAL, "NULL context");
+  return galois_key(c, step, max_level);
+}
+
+he_status he_encode(he_ctx* c, const double* v, size_t n, double scale, int32_t level, he_pt** out) {
+  if (!c || !out || (!v && n)) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  return encode_impl(c, v, n, scale, level, out);
+}
+
+he_status he_pt_import(he_ctx* c, const int64_t* coeffs, double scale, int32_t level, he_pt** out) {
+  if (!c || !coeffs || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (level < 0 || level >= c->L) return fail(HE_ELEVEL, "level %d outside 0..%d", level, c->L - 1);
+  return upload_coeffs(c, coeffs, level, scale, out);
+}
+
+he_status he_pt_export(he_ctx* c, const he_pt* pt, uint64_t* h, size_t cap, int32_t* level, double* scale) {
+  if (!c || !pt || !h) return fail(HE_EINVAL, "NULL argument");
+  const size_t words = pt_words(c, pt->level);
+  if (cap < words) return fail(HE_EINVAL, "capacity %zu < %zu words", cap, words);
+  std::vector<u64> v;
+  TRY(download_coeff(c, pt->d, 1, pt->level + 1, v));
+  std::memcpy(h, v.data(), words * sizeof(u64));
+  if (level) *level = pt->level;
+  if (scale) *scale = pt->scale;
+  return HE_OK;
+}
+
+he_status he_decode(he_ctx* c, const he_pt* pt, double* out, size_t nv) {
+  if (!c || !pt || (!out && nv)) return fail(HE_EINVAL, "NULL argument");
+  if (nv > (size_t)c->n / 2) return fail(HE_ERANGE, "%zu values exceed N/2", nv);
+  std::vector<u64> v;
+  TRY(download_coeff(c, pt->d, 1, pt->level + 1, v));
+  std::vector<double> m(c->n);
+  crt_centered(c, v.data(), pt->level + 1, m.data());
+  decode_values(c->enc, m.data(), pt->scale, out, nv);
+  return HE_OK;
+}
+
+he_status he_encrypt(he_ctx* c, const he_pt* pt, uint32_t idx, int32_t use_sk, he_ct** out) {
+  if (!c || !pt || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!c->have_keys) return fail(HE_ENOKEY, "he_keygen must run first");
+  const int n = c->n, Lp = pt->level + 1;
+  ModList mods = mods_range(Lp);
+  DBuf buf;  // [3][Lp][N]: v (or a), e0, e1
+  TRY(dalloc(c, buf, 3 * (size_t)Lp * n));
+  u64* v = buf.p;
+  u64* e0 = buf.p + (size_t)Lp * n;
+  u64* e1 = buf.p + 2 * (size_t)Lp * n;
+  {
+    Prof pr(c, "sample");
+    hipError_t e;
+    if (use_sk) {
+      e = launch_sample_uniform(c->log_n, c->seed, 11, idx, 1, mods, mods, v, c->d_primes, c->st);
+      if (e == hipSuccess) e = launch_sample_small(c->log_n, 1, c->seed, 12, idx, mods, e0, c->d_primes, c->st);
+    } else {
+      e = launch_sample_small(c->log_n, 0, c->seed, 8, idx, mods, v, c->d_primes, c->st);
+      if (e == hipSuccess) e = launch_sample_small(c->log_n, 1, c->seed, 9, idx, mods, e0, c->d_primes, c->st);
+      if (e == hipSuccess) e = launch_sample_small(c->log_n, 1, c->seed, 10, idx, mods, e1, c->d_primes, c->st);
+    }
+    if (e != hipSuccess) return fail(HE_EHIP, "encryption sampling: %s", hipGetErrorString(e));
+  }
+  TRY(ntt_rows(c, true, buf.p, buf.p, use_sk ? 2 : 3, Lp, (long long)Lp * n, (long long)Lp * n));
+  he_ct* ct = nullptr;
+  TRY(new_ct(c, pt->level, pt->scale, &ct));
+  hipError_t e = launch_encrypt_combine(c->log_n, v, use_sk ? nullptr : c->d_pk,
+                                        use_sk ? nullptr : c->d_pk + (size_t)c->L * n, e0, e1, c->d_s, pt->d,
+                                        ct->d, Lp, c->L, c->d_primes, c->st);
+  if (e != hipSuccess) {
+    he_ct_free(ct);
+    return fail(HE_EHIP, "encrypt: %s", hipGetErrorString(e));
+  }
+  *out = ct;
+  return HE_OK;
+}
+
+he_status he_decrypt(he_ctx* c, const he_ct* ct, he_pt** out) {
+  if (!c || !ct || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!c->have_keys) return fail(HE_ENOKEY, "no secret key");
+  he_pt* pt = nullptr;
+  TRY(new_pt(c, ct->level, ct->scale, &pt));
+  hipError_t e = launch_decrypt(c->log_n, ct->d, c->d_s, pt->d, ct->level + 1, c->d_primes, c->st);
+  if (e != hipSuccess) {
+    he_pt_free(pt);
+    return fail(HE_EHIP, "decrypt: %s", hipGetErrorString(e));
+  }
+  *out = pt;
+  return HE_OK;
+}
+
+he_status he_ct_export(he_ctx* c, const he_ct* ct, uint64_t* h, size_t cap, int32_t* level, double* scale) {
+  if (!c || !ct || !h) return fail(HE_EINVAL, "NULL argument");
+  const size_t words = ct_words(c, ct->level);
+  if (cap < words) return fail(HE_EINVAL, "capacity %zu < %zu words", cap, words);
+  std::vector<u64> v;
+  TRY(download_coeff(c, ct->d, 2, ct->level + 1, v));
+  std::memcpy(h, v.data(), words * sizeof(u64));
+  if (level) *level = ct->level;
+  if (scale) *scale = ct->scale;
+  return HE_OK;
+}
+
+he_status he_ct_import(he_ctx* c, const uint64_t* h, int32_t level, double scale, he_ct** out) {
+  if (!c || !h || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (level < 0 || level >= c->L) return fail(HE_ELEVEL, "level %d outside 0..%d", level, c->L - 1);
+  const int Lp = level + 1;
+  for (int k = 0; k < 2; k++)
+    for (int i = 0; i < Lp; i++)
+      for (int t = 0; t < c->n; t++)
+        if (h[((size_t)k * Lp + i) * c->n + t] >= c->q[i]) return fail(HE_ERANGE, "residue not below its prime");
+  he_ct* ct = nullptr;
+  TRY(new_ct(c, level, scale, &ct));
+  hipError_t e = hipMemcpyAsync(ct->d, h, ct_words(c, level) * sizeof(u64), hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) {
+    he_ct_free(ct);
+    return fail(HE_EHIP, "ciphertext upload: %s", hipGetErrorString(e));
+  }
+  he_status s = ntt_rows(c, true, ct->d, ct->d, 2, Lp, (long long)Lp * c->n, (long long)Lp * c->n);
+  if (s != HE_OK) {
+    he_ct_free(ct);
+    return s;
+  }
+  *out = ct;
+  return HE_OK;
+}
+
+he_status he_ct_info(const he_ct* ct, int32_t* level, double* scale) {
+  if (!ct) return fail(HE_EINVAL, "NULL ciphertext");
+  if (level) *level = ct->level;
+  if (scale) *scale = ct->scale;
+  return HE_OK;
+}
+
+static he_status addsub(he_ctx* c, const he_ct* a, const he_ct* b, int op, he_ct** out) {
+  if (!c || !a || !b || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!scales_match(a->scale, b->scale)) return fail(HE_ESCALE, "scales %g and %g differ", a->scale, b->scale);
+  const he_ct *x, *y;
+  CtGuard gx, gy;
+  TRY(align2(c, a, b, &x, &y, gx, gy));
+  he_ct* r = nullptr;
+  TRY(new_ct(c, x->level, a->scale, &r));
+  Prof pr(c, "pointwise");
+  hipError_t e = launch_addsub(c->log_n, op, x->d, y->d, r->d, 2, mods_range(x->level + 1), c->d_primes, c->st);
+  if (e != hipSuccess) {
+    he_ct_free(r);
+    return fail(HE_EHIP, "add/sub: %s", hipGetErrorString(e));
+  }
+  *out = r;
+  return HE_OK;
+}
+
+he_status he_add(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) { return addsub(c, a, b, 0, out); }
+he_status he_sub(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) { return addsub(c, a, b, 1, out); }
+
+he_status he_negate(he_ctx* c, const he_ct* a, he_ct** out) {
+  if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  he_ct* r = nullptr;
+  TRY(new_ct(c, a->level, a->scale, &r));
+  hipError_t e = launch_addsub(c->log_n, 2, a->d, a->d, r->d, 2, mods_range(a->level + 1), c->d_primes, c->st);
+  if (e != hipSuccess) {
+    he_ct_free(r);
+    return fail(HE_EHIP, "negate: %s", hipGetErrorString(e));
+  }
+  *out = r;
+  return HE_OK;
+}
+
+he_status he_add_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
+  if (!c || !a || !p || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!scales_match(a->scale, p->scale)) return fail(HE_ESCALE, "scales %g and %g differ", a->scale, p->scale);
+  if (p->level < a->level) return fail(HE_ELEVEL, "plaintext level %d below ciphertext level %d", p->level, a->level);
+  he_ct* r = nullptr;
+  TRY(new_ct(c, a->level, a->scale, &r));
+  Prof pr(c, "pointwise");
+  hipError_t e = launch_add_plain(c->log_n, a->d, p->d, r->d, 2, mods_range(a->level + 1), c->d_primes, c->st);
+  if (e != hipSuccess) {
+    he_ct_free(r);
+    return fail(HE_EHIP, "add_plain: %s", hipGetErrorString(e));
+  }
+  *out = r;
+  return HE_OK;
+}
+
+static he_status mul_plain_raw(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
+  if (p->level < a->level) return fail(HE_ELEVEL, "plaintext level %d below ciphertext level %d", p->level, a->level);
+  he_ct* r = nullptr;
+  TRY(new_ct(c, a->level, a->scale * p->scale, &r));
+  Prof pr(c, "pointwise");
+  hipError_t e = launch_mul_plain(c->log_n, a->d, p->d, r->d, 2, mods_range(a->level + 1), c->d_primes, c->st);
+  if (e != hipSuccess) {
+    he_ct_free(r);
+    return fail(HE_EHIP, "mul_plain: %s", hipGetErrorString(e));
+  }
+  *out = r;
+  return HE_OK;
+}
+
+static he_status rescale_raw(he_ctx* c, const he_ct* a, he_ct** out) {
+  const int l = a->level, n = c->n;
+  if (l < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  DBuf coef;
+  TRY(dalloc(c, coef, 2 * (size_t)n));
+  {
+    NttJob J{};
+    J.src = a->d + (size_t)l * n;
+    J.sa = (long long)(l + 1) * n;
+    J.dst = coef.p;
+    J.da = n;
+    J.na = 2;
+    J.nb = 1;
+    J.dst_prime[0] = (unsigned char)l;
+    Prof pr(c, "ntt_inv");
+    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "rescale intt: %s", hipGetErrorString(e));
+  }
+  he_ct* r = nullptr;
+  TRY(new_ct(c, l - 1, a->scale / (double)c->q[l], &r));
+  he_status s = round_div(c, coef.p, l, a->d, (long long)(l + 1) * n, r->d, (long long)l * n, l, nullptr, nullptr,
+                          "rescale");
+  if (s != HE_OK) {
+    he_ct_free(r);
+    return s;
+  }
+  *out = r;
+  return HE_OK;
+}
+
+he_status he_rescale(he_ctx* c, const he_ct* a, he_ct** out) {
+  if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  return rescale_raw(c, a, out);
+}
+
+static he_status maybe_rescale(he_ctx* c, he_ct* r, he_ct** out) {
+  if (!c->auto_rescale) {
+    *out = r;
+    return HE_OK;
+  }
+  he_status s = rescale_raw(c, r, out);
+  he_ct_free(r);
+  return s;
+}
+
+he_status he_mul_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
+  if (!c || !a || !p || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  he_ct* r = nullptr;
+  TRY(mul_plain_raw(c, a, p, &r));
+  return maybe_rescale(c, r, out);
+}
+
+static he_status mul_relin_raw(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
+  if (!c->have_keys) return fail(HE_ENOKEY, "no relinearisation key");
+  const he_ct *x, *y;
+  CtGuard gx, gy;
+  TRY(align2(c, a, b, &x, &y, gx, gy));
+  const int l = x->level, Lp = l + 1, n = c->n;
+  he_ct* r = nullptr;
+  TRY(new_ct(c, l, a->scale * b->scale, &r));
+  DBuf d2;
+  he_status s = dalloc(c, d2, (size_t)Lp * n);
+  if (s == HE_OK) {
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_tensor(c->log_n, x->d, y->d, r->d, d2.p, mods_range(Lp), c->d_primes, c->st);
+    if (e != hipSuccess) s = fail(HE_EHIP, "tensor: %s", hipGetErrorString(e));
+  }
+  if (s == HE_OK) s = key_switch(c, d2.p, l, c->relin, r->d, r->d + (size_t)Lp * n, r->d);
+  if (s != HE_OK) {
+    he_ct_free(r);
+    return s;
+  }
+  *out = r;
+  return HE_OK;
+}
+
+he_status he_mul_relin(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
+  if (!c || !a || !b || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  he_ct* r = nullptr;
+  TRY(mul_relin_raw(c, a, b, &r));
+  return maybe_rescale(c, r, out);
+}
+
+he_status he_square(he_ctx* c, const he_ct* a, he_ct** out) { return he_mul_relin(c, a, a, out); }
+
+he_status he_drop_to(he_ctx* c, const he_ct* a, int32_t level, he_ct** out) {
+  if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (level < 0 || level > a->level) return fail(HE_ELEVEL, "cannot drop from level %d to %d", a->level, level);
+  return drop_copy(c, a, level, out);
+}
+
+static he_status rotate_raw(he_ctx* c, const he_ct* a, int step, he_ct** out) {
+  const int l = a->level, Lp = l + 1, n = c->n;
+  step = norm_step(c, step);
+  if (step == 0) return drop_copy(c, a, l, out);
+  auto it = c->gal.find(step);
+  if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", step);
+  if (it->second.ml < l)
+    return fail(HE_ENOKEY, "Galois key for step %d cut at level %d, ciphertext at %d", step, it->second.ml, l);
+  DBuf tr;
+  TRY(dalloc(c, tr, 2 * (size_t)Lp * n));
+  {
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_automorphism(c->log_n, a->d, tr.p, 2 * Lp, galois_elt(c, step), c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "automorphism: %s", hipGetErrorString(e));
+  }
+  he_ct* r = nullptr;
+  TRY(new_ct(c, l, a->scale, &r));
+  he_status s = key_switch(c, tr.p + (size_t)Lp * n, l, it->second, tr.p, nullptr, r->d);
+  if (s != HE_OK) {
+    he_ct_free(r);
+    return s;
+  }
+  *out = r;
+  return HE_OK;
+}
+
+he_status he_rotate(he_ctx* c, const he_ct* a, int32_t step, he_ct** out) {
+  if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  return rotate_raw(c, a, step, out);
+}
+
+// x <- x + rot(x, stride 2^j), j < ceil(log2 count)
+static he_status rotate_and_sum(he_ctx* c, he_ct* x, uint32_t count, uint32_t stride, he_ct** out) {
+  int steps = 0;
+  while ((1u << steps) < count) steps++;
+  for (int j = 0; j < steps; j++) {
+    he_ct *r = nullptr, *y = nullptr;
+    he_status s = rotate_raw(c, x, (int)(stride << j), &r);
+    if (s == HE_OK) s = he_add(c, x, r, &y);
+    he_ct_free(r);
+    he_ct_free(x);
+    if (s != HE_OK) return s;
+    x = y;
+  }
+  *out = x;
+  return HE_OK;
+}
+
+he_status he_sum_slots(he_ctx* c, const he_ct* a, uint32_t nv, he_ct** out) {
+  if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (nv == 0 || nv > (uint32_t)c->n / 2) return fail(HE_ERANGE, "slot count %u outside 1..N/2", nv);
+  he_ct* x = nullptr;
+  TRY(drop_copy(c, a, a->level, &x));
+  return rotate_and_sum(c, x, nv, 1, out);
+}
+
+// ---------------------------------------------------------------- composites
+static he_status encode_slots(he_ctx* c, const std::vector<double>& v, double scale, int level, he_pt** out) {
+  return encode_impl(c, v.data(), v.size(), scale, level, out);
+}
+
+he_status he_conv_plan(he_ctx* c, const he_ct* like, const double* kernel, uint32_t kk, uint32_t windows,
+                       double bias, he_plan** out) {
+  if (!c || !like || !kernel || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  const uint32_t half = (uint32_t)c->n / 2;
+  if (kk == 0 || windows == 0 || (uint64_t)kk * windows > half) return fail(HE_ERANGE, "kk * windows > N/2");
+  if (like->level < 1) return fail(HE_ELEVEL, "convolution needs one level");
+  he_plan* p = new he_plan();
+  p->ctx = c;
+  p->kind = PLAN_CONV;
+  p->level = like->level;
+  p->scale = like->scale;
+  p->kk = kk;
+  p->windows = windows;
+  std::vector<double> v((size_t)kk * windows);
+  for (uint32_t k = 0; k < kk; k++)
+    for (uint32_t w = 0; w < windows; w++) v[(size_t)k * windows + w] = kernel[k];
+  he_status s = encode_slots(c, v, c->scale, like->level, &p->kernel);
+  if (s == HE_OK) {
+    const double post = like->scale * p->kernel->scale / (double)c->q[like->level];
+    std::vector<double> b(windows, bias);
+    s = encode_slots(c, b, post, like->level - 1, &p->bias);
+  }
+  if (s != HE_OK) {
+    he_plan_free(p);
+    return s;
+  }
+  *out = p;
+  return HE_OK;
+}
+
+he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t n_in, uint32_t n_out,
+                         const double* bias, he_plan** out) {
+  if (!c || !like || !W || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  const uint32_t half = (uint32_t)c->n / 2;
+  if (n_in == 0 || n_out == 0 || n_in > half || n_out > half) return fail(HE_ERANGE, "matrix shape");
+  uint32_t reps = 1;
+  while ((uint64_t)n_in * reps * 2 <= half) reps *= 2;
+  if ((uint64_t)n_in + n_out - 1 > (uint64_t)n_in * reps) return fail(HE_ERANGE, "n_in + n_out - 1 > copies");
+  if (like->level < 1) return fail(HE_ELEVEL, "matmul needs one level");
+  he_plan* p = new he_plan();
+  p->ctx = c;
+  p->kind = PLAN_MATMUL;
+  p->level = like->level;
+  p->scale = like->scale;
+  p->n_in = n_in;
+  p->n_out = n_out;
+  he_status s = HE_OK;
+  std::vector<double> d(n_out);
+  for (uint32_t i = 0; i < n_in && s == HE_OK; i++) {
+    for (uint32_t j = 0; j < n_out; j++) d[j] = W[(size_t)((i + j) % n_in) * n_out + j];
+    he_pt* pt = nullptr;
+    s = encode_slots(c, d, c->scale, like->level, &pt);
+    if (s == HE_OK) p->diags.push_back(pt);
+  }
+  if (s == HE_OK) {
+    const double post = like->scale * c->scale / (double)c->q[like->level];
+    std::vector<double> b(n_out, 0.0);
+    if (bias)
+      for (uint32_t j = 0; j < n_out; j++) b[j] = bias[j];
+    s = encode_slots(c, b, post, like->level - 1, &p->bias);
+  }
+  if (s != HE_OK) {
+    he_plan_free(p);
+    return s;
+  }
+  *out = p;
+  return HE_OK;
+}
+
+static he_status conv_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out) {
+  he_ct *m = nullptr, *y = nullptr, *z = nullptr;
+  TRY(mul_plain_raw(c, x, p->kernel, &m));
+  he_status s = rescale_raw(c, m, &y);
+  he_ct_free(m);
+  if (s != HE_OK) return s;
+  TRY(rotate_and_sum(c, y, p->kk, p->windows, &z));
+  CtGuard gz{z};
+  return he_add_plain(c, z, p->bias, out);
+}
+
+static he_status matmul_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out) {
+  const uint32_t half = (uint32_t)c->n / 2;
+  he_ct* xr = nullptr;
+  TRY(drop_copy(c, x, x->level, &xr));
+  CtGuard gxr;
+  gxr.p = xr;
+  uint32_t reps = 1;
+  while ((uint64_t)p->n_in * reps * 2 <= half) {
+    he_ct *r = nullptr, *y = nullptr;
+    TRY(rotate_raw(c, gxr.p, (int)((half - p->n_in * reps) % half), &r));
+    CtGuard gr{r};
+    TRY(he_add(c, gxr.p, r, &y));
+    he_ct_free(gxr.p);
+    gxr.p = y;
+    reps *= 2;
+  }
+  CtGuard acc;
+  for (uint32_t i = 0; i < p->n_in; i++) {
+    he_ct *r = nullptr, *t = nullptr;
+    TRY(rotate_raw(c, gxr.p, (int)i, &r));
+    CtGuard gr{r};
+    TRY(mul_plain_raw(c, r, p->diags[i], &t));
+    if (!acc.p) {
+      acc.p = t;
+    } else {
+      CtGuard gt{t};
+      he_ct* s2 = nullptr;
+      TRY(he_add(c, acc.p, t, &s2));
+      he_ct_free(acc.p);
+      acc.p = s2;
+    }
+  }
+  he_ct* y = nullptr;
+  TRY(rescale_raw(c, acc.p, &y));
+  CtGuard gy{y};
+  return he_add_plain(c, y, p->bias, out);
+}
+
+he_status he_plan_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out) {
+  if (!c || !p || !x || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (x->level != p->level) return fail(HE_ELEVEL, "plan made for level %d, input at %d", p->level, x->level);
+  if (!scales_match(x->scale, p->scale)) return fail(HE_ESCALE, "plan made for scale %g, input at %g", p->scale, x->scale);
+  if (p->kind == PLAN_CONV) return conv_apply(c, p, x, out);
+  return matmul_apply(c, p, x, out);
+}
+
+he_status he_enc_conv_im2col(he_ctx* c, const he_ct* x, const double* kernel, uint32_t kk, uint32_t windows,
+                             double bias, he_ct** out) {
+  he_plan* p = nullptr;
+  TRY(he_conv_plan(c, x, kernel, kk, windows, bias, &p));
+  he_status s = he_plan_apply(c, p, x, out);
+  he_plan_free(p);
+  return s;
+}
+
+he_status he_enc_matmul(he_ctx* c, const he_ct* x, const double* W, uint32_t n_in, uint32_t n_out,
+                        const double* bias, he_ct** out) {
+  he_plan* p = nullptr;
+  TRY(he_matmul_plan(c, x, W, n_in, n_out, bias, &p));
+  he_status s = he_plan_apply(c, p, x, out);
+  he_plan_free(p);
+  return s;
+}
+
+he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t width, he_ct** out) {
+  if (!c || !parts || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  const uint32_t half = (uint32_t)c->n / 2;
+  if (n_parts == 0 || width == 0 || (uint64_t)width * n_parts > half) return fail(HE_ERANGE, "width * parts > N/2");
+  int l = parts[0]->level;
+  for (uint32_t k = 0; k < n_parts; k++) {
+    if (!parts[k]) return fail(HE_EINVAL, "NULL part");
+    l = std::min(l, parts[k]->level);
+  }
+  if (l < 1) return fail(HE_ELEVEL, "packing needs one level");
+  he_pt* mask = nullptr;
+  auto key = std::make_pair((int)width, l);
+  auto it = c->masks.find(key);
+  if (it != c->masks.end()) {
+    mask = it->second;
+  } else {
+    std::vector<double> ones(width, 1.0);
+    TRY(encode_slots(c, ones, c->scale, l, &mask));
+    c->masks[key] = mask;
+  }
+  CtGuard acc;
+  for (uint32_t k = 0; k < n_parts; k++) {
+    CtGuard a, m, r;
+    const he_ct* src = parts[k];
+    if (src->level != l) {
+      TRY(drop_copy(c, src, l, &a.p));
+      src = a.p;
+    }
+    TRY(mul_plain_raw(c, src, mask, &m.p));
+    TRY(rescale_raw(c, m.p, &r.p));
+    if (k > 0) {
+      he_ct* t = nullptr;
+      TRY(rotate_raw(c, r.p, (int)(half - width * k), &t));
+      he_ct_free(r.p);
+      r.p = t;
+    }
+    if (!acc.p) {
+      acc.p = r.p;
+      r.p = nullptr;
+    } else {
+      he_ct* s2 = nullptr;
+      TRY(he_add(c, acc.p, r.p, &s2));
+      he_ct_free(acc.p);
+      acc.p = s2;
+    }
+  }
+  *out = acc.p;
+  acc.p = nullptr;
+  return HE_OK;
+}
+
+// ---------------------------------------------------------------- raw transforms
+he_status he_ntt_forward(he_ctx* c, uint64_t* data, size_t n_polys, int32_t n_limbs) {
+  if (!c || !data) return fail(HE_EINVAL, "NULL argument");
+  if (n_limbs < 1 || n_limbs > c->L) return fail(HE_EINVAL, "n_limbs %d outside 1..%d", n_limbs, c->L);
+  return ntt_rows(c, true, data, data, (int)n_polys, n_limbs, (long long)n_limbs * c->n, (long long)n_limbs * c->n);
+}
+he_status he_ntt_inverse(he_ctx* c, uint64_t* data, size_t n_polys, int32_t n_limbs) {
+  if (!c || !data) return fail(HE_EINVAL, "NULL argument");
+  if (n_limbs < 1 || n_limbs > c->L) return fail(HE_EINVAL, "n_limbs %d outside 1..%d", n_limbs, c->L);
+  return ntt_rows(c, false, data, data, (int)n_polys, n_limbs, (long long)n_limbs * c->n, (long long)n_limbs * c->n);
+}
+
+// ---------------------------------------------------------------- key export
+he_status he_export_secret(he_ctx* c, int64_t* s) {
+  if (!c || !s) return fail(HE_EINVAL, "NULL argument");
+  if (!c->have_keys) return fail(HE_ENOKEY, "no secret key");
+  std::vector<u64> v;
+  TRY(download_coeff(c, c->d_s, 1, 1, v));
+  const u64 q = c->q[0];
+  for (int k = 0; k < c->n; k++) s[k] = v[k] > q / 2 ? (int64_t)v[k] - (int64_t)q : (int64_t)v[k];
+  return HE_OK;
+}
+
+he_status he_export_key(he_ctx* c, int32_t kind, int32_t step, uint64_t* out, size_t cap, int32_t* max_level) {
+  if (!c || !out) return fail(HE_EINVAL, "NULL argument");
+  const Key* k = nullptr;
+  if (kind == 0) {
+    if (c->have_keys) k = &c->relin;
+  } else {
+    auto it = c->gal.find(norm_step(c, step));
+    if (it != c->gal.end()) k = &it->second;
+  }
+  if (!k || !k->d) return fail(HE_ENOKEY, "no such key");
+  const int nd = k->ml + 1, nm = k->ml + 2, n = c->n;
+  const size_t words = (size_t)nd * 2 * nm * n;
+  if (cap < words) return fail(HE_EINVAL, "capacity %zu < %zu words", cap, words);
+  ModList pidx{};
+  pidx.n = nm;
+  for (int t = 0; t < nm; t++) pidx.p[t] = (unsigned char)(t <= k->ml ? t : c->L);
+  DBuf tmp;
+  TRY(dalloc(c, tmp, words));
+  HIPC(hipMemcpyAsync(tmp.p, k->d, words * sizeof(u64), hipMemcpyDeviceToDevice, c->st));
+  hipError_t e = launch_from_mont(c->log_n, tmp.p, nd * 2 * nm, pidx, c->d_primes, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "from_mont: %s", hipGetErrorString(e));
+  TRY(ntt_rows_mods(c, false, tmp.p, tmp.p, nd * 2, pidx));
+  HIPC(hipMemcpyAsync(out, tmp.p, words * sizeof(u64), hipMemcpyDeviceToHost, c->st));
+  HIPC(hipStreamSynchronize(c->st));
+  if (max_level) *max_level = k->ml;
+  return HE_OK;
+}
+
+// ---------------------------------------------------------------- housekeeping
+void he_ct_free(he_ct* ct) {
+  if (!ct) return;
+  ct->ctx->pool.put(ct->d);
+  delete ct;
+}
+void he_pt_free(he_pt* pt) {
+  if (!pt) return;
+  pt->ctx->pool.put(pt->d);
+  delete pt;
+}
+void he_plan_free(he_plan* p) {
+  if (!p) return;
+  he_pt_free(p->kernel);
+  for (he_pt* d : p->diags) he_pt_free(d);
+  he_pt_free(p->bias);
+  delete p;
+}
+
+he_status he_sync(he_ctx* c) {
+  if (!c) return fail(HE_EINVAL, "NULL context");
+  HIPC(hipStreamSynchronize(c->st));
+  return HE_OK;
+}
+
+size_t he_ct_bytes(const he_ct* ct) { return ct ? ct_words(ct->ctx, ct->level) * sizeof(u64) : 0; }
+
+size_t he_key_bytes(const he_ctx* c) {
+  if (!c) return 0;
+  size_t b = c->relin.bytes;
+  for (auto& kv : c->gal) b += kv.second.bytes;
+  if (c->have_keys) b += (size_t)(c->L + 1) * c->n * 8 + 2 * (size_t)c->L * c->n * 8;
+  return b;
+}
+
+void he_im2col(const double* img, uint32_t h, uint32_t w, uint32_t k, uint32_t stride, double* out) {
+  if (!img || !out || k == 0 || stride == 0 || k > h || k > w) return;
+  const uint32_t oh = (h - k) / stride + 1, ow = (w - k) / stride + 1, windows = oh * ow;
+  for (uint32_t oy = 0; oy < oh; oy++)
+    for (uint32_t ox = 0; ox < ow; ox++) {
+      const uint32_t win = oy * ow + ox;
+      for (uint32_t ky = 0; ky < k; ky++)
+        for (uint32_t kx = 0; kx < k; kx++)
+          out[(size_t)(ky * k + kx) * windows + win] = img[(size_t)(oy * stride + ky) * w + ox * stride + kx];
+    }
+}
+
+he_status he_profile_enable(he_ctx* c, int32_t enable) {
+  if (!c) return fail(HE_EINVAL, "NULL context");
+  HIPC(hipStreamSynchronize(c->st));
+  for (auto& r : c->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->prof_recs.clear();
+  c->prof = enable != 0;
+  return HE_OK;
+}
+
+he_status he_profile_read(he_ctx* c, const char* fam, uint64_t* launches, double* total_ms) {
+  if (!c || !fam) return fail(HE_EINVAL, "NULL argument");
+  HIPC(hipStreamSynchronize(c->st));
+  uint64_t cnt = 0;
+  double ms = 0;
+  for (auto& r : c->prof_recs) {
+    if (r.fam != fam) continue;
+    float t = 0;
+    HIPC(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    cnt++;
+  }
+  if (launches) *launches = cnt;
+  if (total_ms) *total_ms = ms;
+  return HE_OK;
+}
+
+}  // extern "C"

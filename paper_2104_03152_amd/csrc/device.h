@@ -1,0 +1,143 @@
+// device.h -- declarations shared by the host library and the kernel
+// translation units: job descriptors and kernel launchers.  All launchers
+// enqueue on `st` and return the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modarith.h"
+
+#define HE_MAXM 33  // data primes + special prime
+
+// One batched NTT launch: job w = a * nb + b (nb' = nb - 1 and b skipping a
+// when skip_diag is set).  Source a*sa + b*sb, destination a*da + b*db (u64
+// element offsets); destination prime dst_prime[b].
+struct NttJob {
+  const u64* src;
+  u64* dst;
+  long long sa, sb, da, db;
+  int na, nb;
+  int skip_diag;       // jobs with b == a are left out
+  int src_prime;       // source prime: >= 0 fixed, < 0 means src_prime_of_a[a]
+  unsigned char dst_prime[HE_MAXM];
+  unsigned char src_prime_of_a[HE_MAXM];
+  // divide-and-round: prologue r - h_b, epilogue dst = (u - NTT(r - h_b)) * inv_b (+ addend)
+  const u64* u;
+  long long ua, ub;
+  const u64* add0;     // addend for a == 0 (nullable), offset b*ab
+  const u64* add1;     // addend for a == 1 (nullable)
+  long long ab;
+  u64 h_src;           // (q_src - 1) / 2
+  u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
+};
+
+enum { PRO_PLAIN = 0, PRO_CENTRED_LIFT = 1, PRO_ROUNDDIV_LIFT = 2 };
+enum { EPI_STORE = 0, EPI_ROUNDDIV = 1 };
+
+// forward (lazy Cooley-Tukey, bit-reversed output) and inverse (Gentleman-
+// Sande, bit-reversed input, times N^-1) batched negacyclic NTT
+hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job,
+                          const PrimeDev* primes, const u64* fwd_tw, hipStream_t st);
+hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes,
+                          const u64* inv_tw, hipStream_t st);
+
+// ---- samplers (ChaCha20 streams) ----
+// signed small polynomial (ternary: kind 0, Gaussian CDT: kind 1) reduced into
+// n_mod moduli: out[m][N], prime of m = primes_of[m]
+struct ModList {
+  int n;
+  unsigned char p[HE_MAXM];
+};
+hipError_t launch_sample_small(int log_n, int kind, uint64_t seed, uint32_t tag,
+                               uint32_t a, const ModList& mods, u64* out,
+                               const PrimeDev* primes, hipStream_t st);
+// uniform residues: for each (row r < n_rows, modulus m): stream
+// (tag, a_base + r, prime index pidx[m]) -> out[(r * mods.n + m) * N]
+hipError_t launch_sample_uniform(int log_n, uint64_t seed, uint32_t tag,
+                                 uint32_t a_base, int n_rows, const ModList& mods,
+                                 const ModList& pidx, u64* out,
+                                 const PrimeDev* primes, hipStream_t st);
+
+// ---- pointwise (NTT domain); limb i of every poly under prime mods.p[i] ----
+// op: 0 add, 1 sub, 2 negate (b unused); n_poly polys of mods.n limbs
+hipError_t launch_addsub(int log_n, int op, const u64* a, const u64* b, u64* out,
+                         int n_poly, const ModList& mods, const PrimeDev* primes,
+                         hipStream_t st);
+// out[k][i] = a[k][i] * p[i]  (k < n_poly)
+hipError_t launch_mul_plain(int log_n, const u64* a, const u64* p, u64* out,
+                            int n_poly, const ModList& mods, const PrimeDev* primes,
+                            hipStream_t st);
+// add p to poly 0 only (a and out: [n_poly][n][N])
+hipError_t launch_add_plain(int log_n, const u64* a, const u64* p, u64* out,
+                            int n_poly, const ModList& mods, const PrimeDev* primes,
+                            hipStream_t st);
+// tensor: (d0, d1) -> out01 [2][n][N], d2 -> out2 [n][N]
+hipError_t launch_tensor(int log_n, const u64* a, const u64* b, u64* out01,
+                         u64* out2, const ModList& mods, const PrimeDev* primes,
+                         hipStream_t st);
+// decrypt: m[i] = c0[i] + c1[i] * s[i]   (s: [L+1][N], limb i under prime i)
+hipError_t launch_decrypt(int log_n, const u64* ct, const u64* s, u64* m,
+                          int n_limbs, const PrimeDev* primes, hipStream_t st);
+// Galois automorphism in the NTT domain: out[r][n] = in[r][src_g(n)]
+hipError_t launch_automorphism(int log_n, const u64* in, u64* out, int n_rows,
+                               uint64_t g, hipStream_t st);
+// key-switch inner product: u[k][t][n] = sum_j D_{j,t}[n] * key[j][k][kt][n]
+// (keys in Montgomery form), D_{j,t} = (j == t) ? diag[t] : ext[j][t];
+// t < n_dig are data moduli (prime t), t == n_dig is the special prime.
+// gather_g != 1 reads every digit at the Galois source index (hoisting).
+struct InnerJob {
+  const u64* ext;    // [n_dig][n_dig + 1][N]
+  const u64* diag;   // [n_dig][N] (NTT domain digits of the input itself)
+  const u64* key;    // [kd][2][km][N]
+  u64* u;            // [2][n_dig + 1][N]
+  int n_dig;
+  int key_digits, key_mods;  // kd, km of the stored key
+  int special_prime;         // prime index of the special modulus
+  uint64_t gather_g;         // Galois element for hoisted digits, 1 = none
+};
+hipError_t launch_inner(int log_n, const InnerJob& job, const PrimeDev* primes,
+                        hipStream_t st);
+// keygen combine: K0 = -a*s + e + [t == j] pmod_j * s', K1 = a, both turned
+// into Montgomery form. a, e: [nd][nm][N] NTT domain; s, sp: [L+1][N] NTT.
+hipError_t launch_keygen_combine(int log_n, const u64* a, const u64* e,
+                                 const u64* s, const u64* sp, u64* key, int nd,
+                                 int nm, const ModList& pidx, int special_prime,
+                                 const PrimeDev* primes, hipStream_t st);
+// public-key pieces: out[i] = -a[i]*s[i] + e[i]   (i < n)
+hipError_t launch_pk_combine(int log_n, const u64* a, const u64* e, const u64* s,
+                             u64* out, int n, const PrimeDev* primes, hipStream_t st);
+// encryption: c0 = v*pk0 + e0 + m, c1 = v*pk1 + e1 (pk path) or
+// c0 = -a*s + e0 + m, c1 = a (sk path: pk0 = NULL, v = a)
+hipError_t launch_encrypt_combine(int log_n, const u64* v, const u64* pk0,
+                                  const u64* pk1, const u64* e0, const u64* e1,
+                                  const u64* s, const u64* m, u64* ct, int n_limbs,
+                                  int pk_limbs, const PrimeDev* primes, hipStream_t st);
+// key export: Montgomery -> normal form, in place over n words of prime rows
+hipError_t launch_from_mont(int log_n, u64* data, int n_rows, const ModList& mods,
+                            const PrimeDev* primes, hipStream_t st);
+// hoisted rotations of one ciphertext, ModDown epilogue fused with the plain
+// multiply-accumulate of the vector-matrix product
+struct HoistJob {
+  const u64* u_coef;  // [R][2][N]: special-prime limb of u, coefficient form
+  const u64* u;       // [R][2][n_dig + 1][N]
+  const u64* c0;      // [n_dig][N] NTT domain (poly 0 of the replicated input)
+  const u64* diag;    // [n_in][n_dig][N] plaintext diagonals (Montgomery form)
+  u64* partial;       // [n_chunks][2][n_dig][N] partial sums
+  const int* rot_of;  // rotation index of each hoisted slot (size R)
+  int R, n_dig, chunk, special_prime;
+  int n_slots2;       // 2N, for Galois elements
+  const uint64_t* gal;  // Galois element per slot (size R)
+  u64 h_src;
+  u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
+};
+hipError_t launch_hoisted_moddown_mac(int log_n, const HoistJob& job,
+                                      const PrimeDev* primes, const u64* fwd_tw,
+                                      hipStream_t st);
+// sum of partials plus the i = 0 term: out[k][t] = x[k][t]*diag0[t] +
+// sum_c partial[c][k][t]
+hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks,
+                             const u64* x, const u64* diag0, u64* out, int n_dig,
+                             const PrimeDev* primes, hipStream_t st);
+// Montgomery form of plaintext rows (for the diagonals)
+hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
+                          const PrimeDev* primes, hipStream_t st);

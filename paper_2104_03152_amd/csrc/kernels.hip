@@ -1,0 +1,391 @@
+// kernels.hip -- samplers, pointwise NTT-domain arithmetic, the Galois
+// automorphism and the key-switch inner product for gfx950.
+//
+// All polynomials are limb-major [poly][limb][N] u64 rows; a thread owns one
+// coefficient of one row, so every access is a coalesced 8-byte word.
+#include "device.h"
+
+namespace {
+
+constexpr int BLK = 256;
+
+// ---------------- ChaCha20 (RFC 8439 block function) ----------------
+__device__ __forceinline__ u32 rotl32(u32 v, int c) { return (v << c) | (v >> (32 - c)); }
+#define QR(a, b, c, d)   \
+  a += b;                \
+  d ^= a;                \
+  d = rotl32(d, 16);     \
+  c += d;                \
+  b ^= c;                \
+  b = rotl32(b, 12);     \
+  a += b;                \
+  d ^= a;                \
+  d = rotl32(d, 8);      \
+  c += d;                \
+  b ^= c;                \
+  b = rotl32(b, 7);
+
+// key = seed (LE) || 24 zero bytes, nonce = (tag, a, b), counter = block
+__device__ void chacha_block(uint64_t seed, u32 counter, u32 n0, u32 n1, u32 n2, u32 out[16]) {
+  const u32 s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, (u32)seed, (u32)(seed >> 32),
+                     0u,          0u,          0u,          0u,          0u,         0u,
+                     counter,     n0,          n1,          n2};
+  u32 x[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) x[i] = s[i];
+#pragma unroll
+  for (int i = 0; i < 10; i++) {
+    QR(x[0], x[4], x[8], x[12]);
+    QR(x[1], x[5], x[9], x[13]);
+    QR(x[2], x[6], x[10], x[14]);
+    QR(x[3], x[7], x[11], x[15]);
+    QR(x[0], x[5], x[10], x[15]);
+    QR(x[1], x[6], x[11], x[12]);
+    QR(x[2], x[7], x[8], x[13]);
+    QR(x[3], x[4], x[9], x[14]);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; i++) out[i] = x[i] + s[i];
+}
+
+// P(|x| <= k) * 2^63 for the discrete Gaussian of sigma 3.2 cut at 19
+__constant__ u64 kCdt[20] = {
+    0x0ff52b40a5917f1dull, 0x2e5a25d4bf0e400eull, 0x489ae26955b04bd6ull, 0x5d2bc20f621bf185ull,
+    0x6bc8694c3cc80ff4ull, 0x7532d89ac6ba7dceull, 0x7ab396cb74436798ull, 0x7d9e4e916643eb07ull,
+    0x7f05495819eb2051ull, 0x7fa1ce9c0039a957ull, 0x7fdfb3f212e8c4e8ull, 0x7ff5e6f9d2314fccull,
+    0x7ffd1f97bc4406a2ull, 0x7fff40fa0088d11dull, 0x7fffd2e835e1c57dull, 0x7ffff6524386ff1eull,
+    0x7ffffe1db4769da5ull, 0x7fffffac0a1dcb08ull, 0x7ffffff428673853ull, 0x8000000000000000ull};
+
+// one thread per ChaCha block = 8 coefficients
+__global__ void k_sample_small(int n, int kind, uint64_t seed, u32 tag, u32 a, ModList mods, u64* out,
+                               const PrimeDev* __restrict__ primes) {
+  const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+  if (blk * 8 >= n) return;
+  u32 w[16];
+  chacha_block(seed, (u32)blk, tag, a, 0u, w);
+#pragma unroll
+  for (int r = 0; r < 8; r++) {
+    const u64 word = (u64)w[2 * r] | ((u64)w[2 * r + 1] << 32);
+    i64 v;
+    if (kind == 0) {
+      v = (i64)(word % 3) - 1;
+    } else {
+      const u64 uu = word >> 1;
+      int k = 0;
+      while (!(uu < kCdt[k])) k++;
+      v = (word & 1) ? -(i64)k : (i64)k;
+    }
+    const int i = blk * 8 + r;
+    for (int m = 0; m < mods.n; m++) out[(size_t)m * n + i] = red_signed(v, primes[mods.p[m]]);
+  }
+}
+
+// one thread per ChaCha block = 4 coefficients (2 words each)
+__global__ void k_sample_uniform(int n, uint64_t seed, u32 tag, u32 a_base, int n_rows, ModList mods,
+                                 ModList pidx, u64* out, const PrimeDev* __restrict__ primes) {
+  const int per = n / 4;
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long long)per * n_rows * mods.n) return;
+  const int blk = (int)(g % per);
+  const int rm = (int)(g / per);
+  const int m = rm % mods.n, row = rm / mods.n;
+  const PrimeDev P = primes[mods.p[m]];
+  u32 w[16];
+  chacha_block(seed, (u32)blk, tag, a_base + (u32)row, (u32)pidx.p[m], w);
+  const u64 t64 = addmod(red64(~0ull, P), 1, P.q);  // 2^64 mod q
+  u64* o = out + (size_t)rm * n + (size_t)blk * 4;
+#pragma unroll
+  for (int r = 0; r < 4; r++) {
+    const u64 lo = (u64)w[4 * r] | ((u64)w[4 * r + 1] << 32);
+    const u64 hi = (u64)w[4 * r + 2] | ((u64)w[4 * r + 3] << 32);
+    o[r] = addmod(mulmod(red64(hi, P), t64, P), red64(lo, P), P.q);
+  }
+}
+
+// ---------------- pointwise ----------------
+__global__ void k_addsub(int n, int op, const u64* __restrict__ a, const u64* __restrict__ b,
+                         u64* __restrict__ out, long long total, int n_limbs, ModList mods,
+                         const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int limb = (int)((e / n) % n_limbs);
+  const u64 q = primes[mods.p[limb]].q;
+  const u64 x = a[e];
+  u64 r;
+  if (op == 0)
+    r = addmod(x, b[e], q);
+  else if (op == 1)
+    r = submod(x, b[e], q);
+  else
+    r = x ? q - x : 0;
+  out[e] = r;
+}
+
+__global__ void k_mul_plain(int n, const u64* __restrict__ a, const u64* __restrict__ p, u64* __restrict__ out,
+                            long long total, int n_limbs, ModList mods, const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long long row = e / n;
+  const int limb = (int)(row % n_limbs);
+  const PrimeDev P = primes[mods.p[limb]];
+  out[e] = mulmod(a[e], p[(long long)limb * n + (e - row * n)], P);
+}
+
+__global__ void k_add_plain(int n, const u64* __restrict__ a, const u64* __restrict__ p, u64* __restrict__ out,
+                            long long total, int n_limbs, ModList mods, const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long long row = e / n;
+  const int limb = (int)(row % n_limbs);
+  const u64 q = primes[mods.p[limb]].q;
+  const long long per_poly = (long long)n_limbs * n;
+  out[e] = (e < per_poly) ? addmod(a[e], p[e], q) : a[e];
+}
+
+__global__ void k_tensor(int n, const u64* __restrict__ a, const u64* __restrict__ b, u64* __restrict__ out01,
+                         u64* __restrict__ out2, int n_limbs, ModList mods, const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)n_limbs * n;
+  if (e >= per) return;
+  const int limb = (int)(e / n);
+  const PrimeDev P = primes[mods.p[limb]];
+  const u64 a0 = a[e], a1 = a[per + e], b0 = b[e], b1 = b[per + e];
+  out01[e] = mulmod(a0, b0, P);
+  out01[per + e] = addmod(mulmod(a0, b1, P), mulmod(a1, b0, P), P.q);
+  out2[e] = mulmod(a1, b1, P);
+}
+
+__global__ void k_decrypt(int n, const u64* __restrict__ ct, const u64* __restrict__ s, u64* __restrict__ m,
+                          int n_limbs, const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)n_limbs * n;
+  if (e >= per) return;
+  const int limb = (int)(e / n);
+  const PrimeDev P = primes[limb];
+  m[e] = addmod(ct[e], mulmod(ct[per + e], s[e], P), P.q);
+}
+
+// source slot of NTT slot i under X -> X^g (bit-reversed evaluation order):
+// slot i holds a(psi^(2 brv(i) + 1)); tau_g a at that point is a(psi^((2 brv(i)+1) g))
+__device__ __forceinline__ int gal_src(int i, int log_n, u64 g) {
+  const u32 n2mask = (2u << log_n) - 1u;
+  const u32 e = ((2u * bitrev((u32)i, log_n) + 1u) * (u32)g) & n2mask;
+  return (int)bitrev((e - 1u) >> 1, log_n);
+}
+
+__global__ void k_automorphism(int log_n, const u64* __restrict__ in, u64* __restrict__ out, long long total,
+                               u64 g) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int n = 1 << log_n;
+  const long long row = e >> log_n;
+  const int i = (int)(e & (n - 1));
+  out[e] = in[row * n + gal_src(i, log_n, g)];
+}
+
+// key-switch inner product with lazy 128-bit accumulation (8 terms at most
+// per Montgomery reduction: 8 q^2 < q 2^64 for q < 2^60)
+__global__ void k_inner(int log_n, InnerJob J, const PrimeDev* __restrict__ primes) {
+  const int n = 1 << log_n;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nm = J.n_dig + 1;
+  if (e >= (long long)nm * n) return;
+  const int t = (int)(e >> log_n);
+  const int i = (int)(e & (n - 1));
+  const int kt = t < J.n_dig ? t : J.key_mods - 1;
+  const PrimeDev P = primes[t < J.n_dig ? t : J.special_prime];
+  const int src = (J.gather_g != 1) ? gal_src(i, log_n, J.gather_g) : i;
+  const size_t kstride_k = (size_t)J.key_mods * n;        // between polys k
+  const size_t kstride_j = 2 * kstride_k;                 // between digits
+  const u64* kp = J.key + (size_t)kt * n + i;
+  u64 r0 = 0, r1 = 0;
+  for (int j0 = 0; j0 < J.n_dig; j0 += 8) {
+    U128 acc0 = {0, 0}, acc1 = {0, 0};
+    const int j1 = min(J.n_dig, j0 + 8);
+    for (int j = j0; j < j1; j++) {
+      const u64 d = (j == t) ? J.diag[(size_t)t * n + src] : J.ext[((size_t)j * nm + t) * n + src];
+      acc0 = add128(acc0, mul_wide(d, kp[j * kstride_j]));
+      acc1 = add128(acc1, mul_wide(d, kp[j * kstride_j + kstride_k]));
+    }
+    r0 = addmod(r0, mont_reduce(acc0, P), P.q);
+    r1 = addmod(r1, mont_reduce(acc1, P), P.q);
+  }
+  J.u[(size_t)t * n + i] = r0;
+  J.u[((size_t)nm + t) * n + i] = r1;
+}
+
+__global__ void k_keygen_combine(int n, const u64* __restrict__ a, const u64* __restrict__ ee,
+                                 const u64* __restrict__ s, const u64* __restrict__ sp, u64* __restrict__ key,
+                                 int nd, int nm, ModList pidx, int special, const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nd * nm * n) return;
+  const int i = (int)(e % n);
+  const int jt = (int)(e / n);
+  const int t = jt % nm, j = jt / nm;
+  const int pi = pidx.p[t];
+  const PrimeDev P = primes[pi];
+  const u64 av = a[e], ev = ee[e];
+  u64 k0 = submod(ev, mulmod(av, s[(size_t)pi * n + i], P), P.q);
+  if (t == j) k0 = addmod(k0, mulmod(red64(primes[special].q, P), sp[(size_t)pi * n + i], P), P.q);
+  u64* out = key + ((size_t)j * 2 * nm) * n;
+  out[(size_t)t * n + i] = mont_reduce(mul_wide(k0, P.r2), P);
+  out[((size_t)nm + t) * n + i] = mont_reduce(mul_wide(av, P.r2), P);
+}
+
+__global__ void k_pk_combine(int n, const u64* __restrict__ a, const u64* __restrict__ ee,
+                             const u64* __restrict__ s, u64* __restrict__ out, int limbs,
+                             const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)limbs * n) return;
+  const PrimeDev P = primes[e / n];
+  out[e] = submod(ee[e], mulmod(a[e], s[e], P), P.q);
+}
+
+__global__ void k_encrypt_combine(int n, const u64* __restrict__ v, const u64* __restrict__ pk0,
+                                  const u64* __restrict__ pk1, const u64* __restrict__ e0,
+                                  const u64* __restrict__ e1, const u64* __restrict__ s,
+                                  const u64* __restrict__ m, u64* __restrict__ ct, int limbs, int pk_limbs,
+                                  const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)limbs * n;
+  if (e >= per) return;
+  const int limb = (int)(e / n);
+  const PrimeDev P = primes[limb];
+  const u64 vv = v[e];
+  if (pk0) {
+    const long long pe = e;  // pk rows share the limb layout for limb < pk_limbs
+    ct[e] = addmod(addmod(mulmod(vv, pk0[pe], P), e0[e], P.q), m[e], P.q);
+    ct[per + e] = addmod(mulmod(vv, pk1[pe], P), e1[e], P.q);
+  } else {
+    ct[e] = addmod(submod(e0[e], mulmod(vv, s[e], P), P.q), m[e], P.q);
+    ct[per + e] = vv;
+  }
+  (void)pk_limbs;
+}
+
+__global__ void k_mont(int n, u64* data, long long total, int to, ModList mods,
+                       const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int row = (int)(e / n);
+  const PrimeDev P = primes[mods.p[row % mods.n]];
+  const u64 v = data[e];
+  data[e] = to ? mont_reduce(mul_wide(v, P.r2), P) : mont_reduce(U128{v, 0}, P);
+}
+
+inline dim3 grid_for(long long total) { return dim3((unsigned)((total + BLK - 1) / BLK)); }
+
+}  // namespace
+
+hipError_t launch_sample_small(int log_n, int kind, uint64_t seed, uint32_t tag, uint32_t a,
+                               const ModList& mods, u64* out, const PrimeDev* primes, hipStream_t st) {
+  const int n = 1 << log_n;
+  hipLaunchKernelGGL(k_sample_small, grid_for(n / 8), dim3(BLK), 0, st, n, kind, seed, tag, a, mods, out,
+                     primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_uniform(int log_n, uint64_t seed, uint32_t tag, uint32_t a_base, int n_rows,
+                                 const ModList& mods, const ModList& pidx, u64* out, const PrimeDev* primes,
+                                 hipStream_t st) {
+  const int n = 1 << log_n;
+  const long long total = (long long)(n / 4) * n_rows * mods.n;
+  hipLaunchKernelGGL(k_sample_uniform, grid_for(total), dim3(BLK), 0, st, n, seed, tag, a_base, n_rows, mods,
+                     pidx, out, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_addsub(int log_n, int op, const u64* a, const u64* b, u64* out, int n_poly,
+                         const ModList& mods, const PrimeDev* primes, hipStream_t st) {
+  const int n = 1 << log_n;
+  const long long total = (long long)n_poly * mods.n * n;
+  hipLaunchKernelGGL(k_addsub, grid_for(total), dim3(BLK), 0, st, n, op, a, b, out, total, mods.n, mods,
+                     primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul_plain(int log_n, const u64* a, const u64* p, u64* out, int n_poly, const ModList& mods,
+                            const PrimeDev* primes, hipStream_t st) {
+  const int n = 1 << log_n;
+  const long long total = (long long)n_poly * mods.n * n;
+  hipLaunchKernelGGL(k_mul_plain, grid_for(total), dim3(BLK), 0, st, n, a, p, out, total, mods.n, mods,
+                     primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_plain(int log_n, const u64* a, const u64* p, u64* out, int n_poly, const ModList& mods,
+                            const PrimeDev* primes, hipStream_t st) {
+  const int n = 1 << log_n;
+  const long long total = (long long)n_poly * mods.n * n;
+  hipLaunchKernelGGL(k_add_plain, grid_for(total), dim3(BLK), 0, st, n, a, p, out, total, mods.n, mods,
+                     primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_tensor(int log_n, const u64* a, const u64* b, u64* out01, u64* out2, const ModList& mods,
+                         const PrimeDev* primes, hipStream_t st) {
+  const int n = 1 << log_n;
+  hipLaunchKernelGGL(k_tensor, grid_for((long long)mods.n * n), dim3(BLK), 0, st, n, a, b, out01, out2, mods.n,
+                     mods, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_decrypt(int log_n, const u64* ct, const u64* s, u64* m, int n_limbs, const PrimeDev* primes,
+                          hipStream_t st) {
+  const int n = 1 << log_n;
+  hipLaunchKernelGGL(k_decrypt, grid_for((long long)n_limbs * n), dim3(BLK), 0, st, n, ct, s, m, n_limbs,
+                     primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_automorphism(int log_n, const u64* in, u64* out, int n_rows, uint64_t g, hipStream_t st) {
+  const long long total = (long long)n_rows << log_n;
+  hipLaunchKernelGGL(k_automorphism, grid_for(total), dim3(BLK), 0, st, log_n, in, out, total, (u64)g);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner(int log_n, const InnerJob& job, const PrimeDev* primes, hipStream_t st) {
+  const long long total = (long long)(job.n_dig + 1) << log_n;
+  hipLaunchKernelGGL(k_inner, grid_for(total), dim3(BLK), 0, st, log_n, job, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_keygen_combine(int log_n, const u64* a, const u64* e, const u64* s, const u64* sp, u64* key,
+                                 int nd, int nm, const ModList& pidx, int special_prime, const PrimeDev* primes,
+                                 hipStream_t st) {
+  const int n = 1 << log_n;
+  hipLaunchKernelGGL(k_keygen_combine, grid_for((long long)nd * nm * n), dim3(BLK), 0, st, n, a, e, s, sp, key,
+                     nd, nm, pidx, special_prime, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_pk_combine(int log_n, const u64* a, const u64* e, const u64* s, u64* out, int limbs,
+                             const PrimeDev* primes, hipStream_t st) {
+  const int n = 1 << log_n;
+  hipLaunchKernelGGL(k_pk_combine, grid_for((long long)limbs * n), dim3(BLK), 0, st, n, a, e, s, out, limbs,
+                     primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_encrypt_combine(int log_n, const u64* v, const u64* pk0, const u64* pk1, const u64* e0,
+                                  const u64* e1, const u64* s, const u64* m, u64* ct, int n_limbs, int pk_limbs,
+                                  const PrimeDev* primes, hipStream_t st) {
+  const int n = 1 << log_n;
+  hipLaunchKernelGGL(k_encrypt_combine, grid_for((long long)n_limbs * n), dim3(BLK), 0, st, n, v, pk0, pk1, e0,
+                     e1, s, m, ct, n_limbs, pk_limbs, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_mont(int log_n, u64* data, int n_rows, const ModList& mods, const PrimeDev* primes,
+                            hipStream_t st) {
+  const long long total = (long long)n_rows << log_n;
+  hipLaunchKernelGGL(k_mont, grid_for(total), dim3(BLK), 0, st, 1 << log_n, data, total, 0, mods, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods, const PrimeDev* primes,
+                          hipStream_t st) {
+  const long long total = (long long)n_rows << log_n;
+  hipLaunchKernelGGL(k_mont, grid_for(total), dim3(BLK), 0, st, 1 << log_n, data, total, 1, mods, primes);
+  return hipGetLastError();
+}

@@ -1,0 +1,119 @@
+// modarith.h -- 64-bit modular arithmetic for gfx950 built from 32x32->64
+// multiplies (CDNA4 has no 64x64->128 integer multiply).  Primes are below
+// 2^61, so lazy values up to 4q fit in a word.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+// Per-prime constants, resident in device memory.
+struct PrimeDev {
+  u64 q;
+  u64 mu;        // floor(2^(2k) / q), k = bit length of q (HAC 14.42 Barrett)
+  u64 mu64;      // floor((2^64 - 1) / q): one-word reduction
+  u64 qinv_neg;  // -q^-1 mod 2^64 (Montgomery)
+  u64 r2;        // 2^128 mod q (into Montgomery form)
+  u64 ninv, ninv_sh;  // N^-1 mod q and its Shoup companion
+  u32 k;         // bit length of q
+  u32 pad;
+};
+
+struct U128 {
+  u64 lo, hi;
+};
+
+__device__ __forceinline__ U128 mul_wide(u64 a, u64 b) {
+  u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+  u64 p00 = (u64)a0 * b0;
+  u64 p01 = (u64)a0 * b1;
+  u64 p10 = (u64)a1 * b0;
+  u64 p11 = (u64)a1 * b1;
+  u64 mid = (p00 >> 32) + (u64)(u32)p01 + (u64)(u32)p10;
+  U128 r;
+  r.lo = (mid << 32) | (u32)p00;
+  r.hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  return r;
+}
+
+__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) {
+  u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+  u64 p00 = (u64)a0 * b0;
+  u64 p01 = (u64)a0 * b1;
+  u64 p10 = (u64)a1 * b0;
+  u64 p11 = (u64)a1 * b1;
+  u64 mid = (p00 >> 32) + (u64)(u32)p01 + (u64)(u32)p10;
+  return p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+}
+
+__device__ __forceinline__ U128 add128(U128 a, U128 b) {
+  U128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1 : 0);
+  return r;
+}
+
+// x < q^2 (x < 2^(2k)) -> x mod q.  q1 = x >> (k-1), q3 = (q1 mu) >> (k+1),
+// r = x - q3 q in [0, 3q).
+__device__ __forceinline__ u64 barrett_reduce(U128 x, const PrimeDev& P) {
+  const u32 k = P.k;
+  u64 q1 = (x.hi << (65 - k)) | (x.lo >> (k - 1));
+  U128 t = mul_wide(q1, P.mu);
+  u64 q3 = (t.hi << (63 - k)) | (t.lo >> (k + 1));
+  u64 r = x.lo - q3 * P.q;
+  r = r >= P.q ? r - P.q : r;
+  r = r >= P.q ? r - P.q : r;
+  return r;
+}
+
+__device__ __forceinline__ u64 mulmod(u64 a, u64 b, const PrimeDev& P) {
+  return barrett_reduce(mul_wide(a, b), P);
+}
+
+// any 64-bit x -> x mod q (qhat = floor(x mu64 / 2^64) is within 1 of x / q)
+__device__ __forceinline__ u64 red64(u64 x, const PrimeDev& P) {
+  u64 qh = mulhi64(x, P.mu64);
+  u64 r = x - qh * P.q;
+  return r >= P.q ? r - P.q : r;
+}
+
+// Shoup: w < q, ws = floor(w 2^64 / q); a < 2^64 -> a w mod q in [0, 2q)
+__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 ws, u64 q) {
+  u64 qh = mulhi64(a, ws);
+  return a * w - qh * q;
+}
+__device__ __forceinline__ u64 shoup(u64 a, u64 w, u64 ws, u64 q) {
+  u64 r = shoup_lazy(a, w, ws, q);
+  return r >= q ? r - q : r;
+}
+
+// Montgomery: x < q 2^64 -> x 2^-64 mod q
+__device__ __forceinline__ u64 mont_reduce(U128 x, const PrimeDev& P) {
+  u64 m = x.lo * P.qinv_neg;
+  U128 mq = mul_wide(m, P.q);
+  // x + m q is divisible by 2^64; its high word is the result (< 2q)
+  u64 carry = (x.lo + mq.lo) < x.lo ? 1 : 0;
+  u64 r = x.hi + mq.hi + carry;
+  return r >= P.q ? r - P.q : r;
+}
+
+__device__ __forceinline__ u64 addmod(u64 a, u64 b, u64 q) {
+  u64 s = a + b;
+  return s >= q ? s - q : s;
+}
+__device__ __forceinline__ u64 submod(u64 a, u64 b, u64 q) {
+  return a >= b ? a - b : a + q - b;
+}
+
+// a signed small integer (|v| < 2^62) into [0, q)
+__device__ __forceinline__ u64 red_signed(i64 v, const PrimeDev& P) {
+  if (v >= 0) return red64((u64)v, P);
+  u64 r = red64((u64)(-v), P);
+  return r ? P.q - r : 0;
+}
+
+__device__ __forceinline__ u32 bitrev(u32 x, int bits) {
+  return __builtin_bitreverse32(x) >> (32 - bits);
+}

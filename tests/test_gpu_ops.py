@@ -1,0 +1,243 @@
+"""GPU parity of the transforms, keys, encoding, encryption and element-wise
+operations against the oracle, bit for bit, on the N=4096 three-prime
+parameter set (and a deeper N=4096 chain for rescale chains)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2104_03152_amd import inputs as I
+from tests.gpu_common import Pair, hip, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    p = I.SMALL
+    return Pair(p["log_n"], p["bits"], p["scale"], p["seed"], steps=[1 << t for t in range(11)] + [3, 2047])
+
+
+def test_ntt_evaluation_property_and_roundtrip():
+    # forward NTT of X^k is (NTT of X)^k pointwise, the points are the N roots
+    # of X^N + 1, the transform is linear, and the inverse undoes it
+    H = hip()
+    import torch
+    for log_n, bits in ((12, [40, 20, 40]), (13, [60, 40, 60]), (14, [50, 50, 50])):
+        say("ntt property", log_n)
+        g = H.he_ctx_create(log_n, bits, 2.0 ** 20, 1, stream=None)
+        n = 1 << log_n
+        L = g.L
+        rows = np.zeros((4, L, n), dtype=np.uint64)
+        ks = [1, 2, 3, n - 1]
+        for r, k in enumerate(ks):
+            rows[r, :, k] = 1
+        t = torch.from_numpy(rows.view(np.int64).copy()).cuda()
+        H.he_ntt_forward(g, t.data_ptr(), 4, L)
+        H.he_sync(g)
+        A = t.cpu().numpy().view(np.uint64)
+        for i, q in enumerate(g.primes[:L]):
+            pts = [int(v) for v in A[0, i]]
+            assert len(set(pts)) == n
+            for r, k in enumerate(ks):
+                assert all(int(A[r, i, j]) == pow(pts[j], k, q) for j in range(0, n, 97))
+            assert all(pow(x, n, q) == q - 1 for x in pts[:64])
+        H.he_ntt_inverse(g, t.data_ptr(), 4, L)
+        H.he_sync(g)
+        assert np.array_equal(t.cpu().numpy().view(np.uint64), rows)
+        rng = np.random.default_rng(log_n)
+        rnd = I.residues(g.primes[:L], (3,), n, log_n)
+        t = torch.from_numpy(rnd.view(np.int64).copy()).cuda()
+        H.he_ntt_forward(g, t.data_ptr(), 3, L)
+        H.he_ntt_inverse(g, t.data_ptr(), 3, L)
+        H.he_sync(g)
+        assert np.array_equal(t.cpu().numpy().view(np.uint64), rnd)
+        del rng
+        g.close()
+
+
+def test_ring_product_matches_oracle(small):
+    # import (NTT), multiply by a plaintext, export (INTT) = negacyclic product
+    P = small
+    H = P.H
+    rng = np.random.default_rng(5)
+    data = I.residues(P.o.primes[:2], (2,), P.n, 7)
+    coeffs = rng.integers(-(1 << 40), 1 << 40, P.n)
+    g = H.he_ct_import(P.g, data, 1, 1.0)
+    gp = H.he_pt_import(P.g, coeffs, 1.0, 1)
+    got = H.he_ct_export(P.g, H.he_mul_plain(P.g, g, gp))
+    for k in range(2):
+        for i, q in enumerate(P.o.primes[:2]):
+            b = np.array([int(c) % q for c in coeffs], dtype=np.uint64)
+            assert np.array_equal(got[k, i], O.negacyclic_mul(data[k, i], b, P.o.log_n, q))
+
+
+def test_keys_bit_exact(small):
+    P = small
+    H = P.H
+    assert np.array_equal(H.he_export_secret(P.g), P.o.secret())
+    assert np.array_equal(H.he_export_key(P.g, 0), P.o.key(0))
+    for st in (1, 3, 1024, 2047):
+        assert np.array_equal(H.he_export_key(P.g, 1, st), P.o.key(1, st)), st
+
+
+def test_level_cut_galois_key_bit_exact():
+    P = Pair(12, [60, 40, 40, 40, 60], 2.0 ** 40, 6, step_levels={5: 1, 9: 2})
+    for st in (5, 9):
+        got = P.H.he_export_key(P.g, 1, st)
+        assert got.shape[0] == P.o.key(1, st).shape[0]
+        assert np.array_equal(got, P.o.key(1, st))
+
+
+@pytest.mark.parametrize("case", ["full", "ragged", "constant", "tiny", "odd_scale"])
+def test_encode_bit_exact(small, case):
+    P = small
+    H = P.H
+    rng = np.random.default_rng(hash(case) % 1000)
+    scale = P.scale
+    if case == "full":
+        z = rng.uniform(-1, 1, P.n // 2)
+    elif case == "ragged":
+        z = rng.uniform(-5, 5, 777)
+    elif case == "constant":
+        z = np.full(P.n // 2, 0.3)
+    elif case == "tiny":
+        z = np.array([0.5 / scale * 3])  # ties in the constant term region
+    else:
+        z = rng.uniform(-1, 1, 1000)
+        scale = 2.0 ** 20 * 1.0123456789
+    for level in (0, 1):
+        P.pt_equal(H.he_encode(P.g, z, scale, level), P.o.encode(z, scale, level), case)
+
+
+def test_encode_many_bit_exact_n8192():
+    # the correctly rounded encoder at N=8192, scale 2^40 over many vectors
+    P = Pair(13, [60, 40, 60], 2.0 ** 40, 2)
+    rng = np.random.default_rng(9)
+    for trial in range(20):
+        n = int(rng.integers(1, P.n // 2 + 1))
+        z = rng.normal(0, 1, n)
+        sc = 2.0 ** 40 * (1 + rng.uniform(0, 1) if trial % 3 == 0 else 1)
+        P.pt_equal(P.H.he_encode(P.g, z, sc, 1), P.o.encode(z, sc, 1), "trial %d" % trial)
+
+
+def test_encrypt_decrypt_bit_exact(small):
+    P = small
+    H = P.H
+    x, _, _ = I.small_vectors()
+    gp, op = H.he_encode(P.g, x, P.scale, 1), P.o.encode(x, P.scale, 1)
+    for sk in (True, False):
+        for idx in (0, 7):
+            gc, oc = H.he_encrypt(P.g, gp, idx, sk), P.o.encrypt(op, idx, sk)
+            P.ct_equal(gc, oc, "encrypt sk=%s idx=%d" % (sk, idx))
+            P.pt_equal(H.he_decrypt(P.g, gc), P.o.decrypt(oc), "decrypt")
+    # decode agrees with the oracle decoder
+    gc = H.he_encrypt(P.g, gp, 3, True)
+    dec = H.he_decode(P.g, H.he_decrypt(P.g, gc), P.n // 2)
+    assert np.abs(dec - P.o.decode(P.o.decrypt(P.o.encrypt(op, 3, True)), P.n // 2)).max() < 1e-9
+    assert np.abs(dec - x).max() < 1e-2
+
+
+def test_ct_import_export_roundtrip(small):
+    P = small
+    data = I.residues(P.o.primes[:2], (2,), P.n, 3)
+    g = P.H.he_ct_import(P.g, data, 1, 3.0)
+    assert np.array_equal(P.H.he_ct_export(P.g, g), data)
+
+
+def _enc(P, v, idx, level=1, sk=True):
+    H = P.H
+    return (H.he_encrypt(P.g, H.he_encode(P.g, v, P.scale, level), idx, sk),
+            P.o.encrypt(P.o.encode(v, P.scale, level), idx, sk))
+
+
+def test_elementwise_ops_bit_exact(small):
+    P = small
+    H, o, g = P.H, P.o, P.g
+    x, y, pv = I.small_vectors()
+    gx, ox = _enc(P, x, 0)
+    gy, oy = _enc(P, y, 1)
+    gp, opl = H.he_encode(g, pv, P.scale, 1), o.encode(pv, P.scale, 1)
+    say("add/sub/negate")
+    P.ct_equal(H.he_add(g, gx, gy), o.add(ox, oy), "add")
+    P.ct_equal(H.he_sub(g, gx, gy), o.sub(ox, oy), "sub")
+    P.ct_equal(H.he_negate(g, gx), o.negate(ox), "negate")
+    P.ct_equal(H.he_add_plain(g, gx, gp), o.add_plain(ox, opl), "add_plain")
+    say("mul_plain/rescale")
+    gm, om = H.he_mul_plain(g, gx, gp), o.mul_plain(ox, opl)
+    P.ct_equal(gm, om, "mul_plain")
+    P.ct_equal(H.he_rescale(g, gm), o.rescale(om), "rescale")
+    say("mul_relin")
+    gr, orr = H.he_mul_relin(g, gx, gy), o.mul_relin(ox, oy)
+    P.ct_equal(gr, orr, "mul_relin")
+    P.ct_equal(H.he_rescale(g, gr), o.rescale(orr), "mul_relin+rescale")
+    P.ct_equal(H.he_square(g, gx), o.mul_relin(ox, ox), "square")
+    P.ct_equal(H.he_drop_to(g, gx, 0), o.drop_to(ox, 0), "drop")
+    say("rotations")
+    for st in (1, 3, 1024, 2047, -1, 0):
+        P.ct_equal(H.he_rotate(g, gx, st), o.rotate(ox, st), "rotate %d" % st)
+    say("sum_slots")
+    for n in (1, 3, 2048):
+        P.ct_equal(H.he_sum_slots(g, gx, n), o.sum_slots(ox, n), "sum_slots %d" % n)
+
+
+def test_small_op_set_tolerances(small):
+    # decrypted GPU results against FP64 at scale 2^20 (secret-key encryption)
+    P = small
+    H, g = P.H, P.g
+    x, y, pv = I.small_vectors()
+    gx, _ = _enc(P, x, 0)
+    gy, _ = _enc(P, y, 1)
+    gp = H.he_encode(g, pv, P.scale, 1)
+
+    def dec(c, n=2048):
+        return H.he_decode(g, H.he_decrypt(g, c), n)
+
+    assert np.abs(dec(H.he_add(g, gx, gy)) - (x + y)).max() < 1e-2
+    assert np.abs(dec(H.he_rescale(g, H.he_mul_plain(g, gx, gp))) - x * pv).max() < 1e-2
+    assert np.abs(dec(H.he_rescale(g, H.he_mul_relin(g, gx, gy))) - x * y).max() < 1e-2
+    assert np.abs(dec(H.he_rotate(g, gx, 1)) - np.roll(x, -1)).max() < 2e-2
+    assert abs(dec(H.he_sum_slots(g, gx, 2048), 1)[0] - x.sum()) < 1.0
+
+
+def test_error_codes(small):
+    P = small
+    H, g = P.H, P.g
+    x, y, _ = I.small_vectors()
+    gx, _ = _enc(P, x, 0)
+    low = H.he_rescale(g, H.he_mul_relin(g, gx, gx))
+    with pytest.raises(H.HeError) as e:
+        H.he_rescale(g, low)
+    assert e.value.code == H.HE_ELEVEL
+    with pytest.raises(H.HeError) as e:
+        H.he_add(g, low, gx)
+    assert e.value.code == H.HE_ESCALE
+    with pytest.raises(H.HeError) as e:
+        H.he_rotate(g, gx, 5)
+    assert e.value.code == H.HE_ENOKEY
+    with pytest.raises(H.HeError) as e:
+        H.he_encode(g, np.ones(P.n // 2 + 1), P.scale, 0)
+    assert e.value.code == H.HE_ERANGE
+    with pytest.raises(H.HeError) as e:
+        H.he_sum_slots(g, gx, P.n)
+    assert e.value.code == H.HE_ERANGE
+    # the context stays usable after errors
+    assert np.abs(H.he_decode(g, H.he_decrypt(g, H.he_add(g, gx, gx)), 8) - 2 * x[:8]).max() < 1e-2
+
+
+def test_auto_rescale_and_deep_chain():
+    # a 4-data-prime chain at scale 2^40 with automatic rescaling: three
+    # multiplications in a row stay bit-exact
+    P = Pair(12, [60, 40, 40, 40, 60], 2.0 ** 40, 6, steps=[1, 5], auto_rescale=True)
+    H, o, g = P.H, P.o, P.g
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-1, 1, 2048)
+    gx, ox = _enc(P, x, 2, level=3, sk=False)
+    gc, oc = gx, ox
+    for step in range(3):
+        gc = H.he_mul_relin(g, gc, gx if step == 0 else gc)
+        oc = o.rescale(o.mul_relin(oc, ox if step == 0 else oc))
+        P.ct_equal(gc, oc, "auto-rescaled product %d" % step)
+        gx = H.he_drop_to(g, gx, oc.level)
+        ox = o.drop_to(ox, oc.level)
+    out = H.he_decode(g, H.he_decrypt(g, gc), 2048)
+    assert np.abs(out - x ** 8).max() < 1e-6
