@@ -177,6 +177,7 @@ struct he_ctx {
   std::map<std::pair<int, int>, he_pt*> masks;
   bool prof = false;
   std::vector<ProfRec> prof_recs;
+  uint64_t key_epoch = 0;  // bumped whenever a key is (re)generated
 };
 
 struct he_ct {
@@ -201,8 +202,10 @@ struct he_plan {
   uint32_t kk = 0, windows = 0;  // conv
   uint32_t n_in = 0, n_out = 0;  // matmul
   he_pt* kernel = nullptr;       // conv plaintext
-  std::vector<he_pt*> diags;     // matmul diagonals
   he_pt* bias = nullptr;         // at the post-rescale scale and level
+  u64* diags = nullptr;          // matmul diagonals [n_in][level+1][N], NTT domain
+  HoistItem* items = nullptr;    // device table of the hoisted rotations
+  uint64_t items_epoch = ~0ull;
 };
 
 namespace {
@@ -361,6 +364,30 @@ he_status round_div(he_ctx* c, const u64* src_coef, int src_prime, const u64* u,
   return HE_OK;
 }
 
+// ModUp: centred digit j (coefficient form [Lp][N]) lifted to every other
+// modulus (data 0..Lp-1, then the special prime) and transformed; the
+// diagonal slots ext[j][j] are left out (they are the input limbs).
+he_status modup(he_ctx* c, const u64* coef, int Lp, u64* ext) {
+  const int n = c->n, nm = Lp + 1;
+  NttJob J{};
+  J.src = coef;
+  J.sa = n;
+  J.sb = 0;
+  J.dst = ext;
+  J.da = (long long)nm * n;
+  J.db = n;
+  J.na = Lp;
+  J.nb = nm;
+  J.skip_diag = 1;
+  J.src_prime = -1;
+  for (int j = 0; j < Lp; j++) J.src_prime_of_a[j] = (unsigned char)j;
+  for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
+  Prof pr(c, "modup");
+  hipError_t e = launch_ntt_fwd(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, J, c->d_primes, c->d_fwd, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "modup: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
 // ---------------------------------------------------------------- key switching
 // out [2][l+1][N] = KeySwitch(d) (+ addends), d: NTT domain [l+1][N]
 he_status key_switch(he_ctx* c, const u64* d, int l, const Key& key, const u64* add0, const u64* add1,
@@ -373,24 +400,7 @@ he_status key_switch(he_ctx* c, const u64* d, int l, const Key& key, const u64* 
   TRY(dalloc(c, u, 2 * (size_t)nm * n));
   TRY(dalloc(c, ucoef, 2 * (size_t)n));
   TRY(ntt_rows(c, false, d, coef.p, 1, Lp, 0, 0));
-  {  // ModUp: centred digit j lifted to every other modulus, then NTT
-    NttJob J{};
-    J.src = coef.p;
-    J.sa = n;
-    J.sb = 0;
-    J.dst = ext.p;
-    J.da = (long long)nm * n;
-    J.db = n;
-    J.na = Lp;
-    J.nb = nm;
-    J.skip_diag = 1;
-    J.src_prime = -1;
-    for (int j = 0; j < Lp; j++) J.src_prime_of_a[j] = (unsigned char)j;
-    for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
-    Prof pr(c, "modup");
-    hipError_t e = launch_ntt_fwd(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, J, c->d_primes, c->d_fwd, c->st);
-    if (e != hipSuccess) return fail(HE_EHIP, "modup: %s", hipGetErrorString(e));
-  }
+  TRY(modup(c, coef.p, Lp, ext.p));
   {
     InnerJob I{};
     I.ext = ext.p;
@@ -492,6 +502,7 @@ he_status make_key(he_ctx* c, Key& key, int ml, const u64* sp, uint32_t tag_a, u
   key.d = kd;
   key.ml = ml;
   key.bytes = words * sizeof(u64);
+  c->key_epoch++;
   return HE_OK;
 }
 
@@ -1193,6 +1204,7 @@ he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t
   while ((uint64_t)n_in * reps * 2 <= half) reps *= 2;
   if ((uint64_t)n_in + n_out - 1 > (uint64_t)n_in * reps) return fail(HE_ERANGE, "n_in + n_out - 1 > copies");
   if (like->level < 1) return fail(HE_ELEVEL, "matmul needs one level");
+  const int n = c->n, Lp = like->level + 1;
   he_plan* p = new he_plan();
   p->ctx = c;
   p->kind = PLAN_MATMUL;
@@ -1200,14 +1212,36 @@ he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t
   p->scale = like->scale;
   p->n_in = n_in;
   p->n_out = n_out;
-  he_status s = HE_OK;
+  // diagonals: diag_i[j] = W[(i + j) mod n_in][j], encoded at Delta, all in
+  // one device buffer [n_in][Lp][N] (coefficients uploaded, one batched NTT)
+  const size_t words = (size_t)n_in * Lp * n;
+  std::vector<u64> h(words);
   std::vector<double> d(n_out);
-  for (uint32_t i = 0; i < n_in && s == HE_OK; i++) {
+  std::vector<int64_t> co(n);
+  for (uint32_t i = 0; i < n_in; i++) {
     for (uint32_t j = 0; j < n_out; j++) d[j] = W[(size_t)((i + j) % n_in) * n_out + j];
-    he_pt* pt = nullptr;
-    s = encode_slots(c, d, c->scale, like->level, &pt);
-    if (s == HE_OK) p->diags.push_back(pt);
+    if (encode_coeffs(c->enc, d.data(), n_out, c->scale, co.data()) != 0) {
+      he_plan_free(p);
+      return fail(HE_ERANGE, "diagonal %u does not encode", i);
+    }
+    for (int t = 0; t < Lp; t++) {
+      const u64 q = c->q[t];
+      u64* row = h.data() + ((size_t)i * Lp + t) * n;
+      for (int k = 0; k < n; k++) {
+        const int64_t v = co[k];
+        u64 r = v >= 0 ? (u64)v % q : ((u64)(-(v + 1)) + 1u) % q;
+        row[k] = (v < 0 && r) ? q - r : r;
+      }
+    }
   }
+  p->diags = (u64*)c->pool.get(words * sizeof(u64));
+  he_status s = p->diags ? HE_OK : fail(HE_EOOM, "diagonal allocation failed");
+  if (s == HE_OK) {
+    hipError_t e = hipMemcpyAsync(p->diags, h.data(), words * sizeof(u64), hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) s = fail(HE_EHIP, "diagonal upload: %s", hipGetErrorString(e));
+  }
+  if (s == HE_OK) s = ntt_rows(c, true, p->diags, p->diags, (int)n_in, Lp, (long long)Lp * n, (long long)Lp * n);
   if (s == HE_OK) {
     const double post = like->scale * c->scale / (double)c->q[like->level];
     std::vector<double> b(n_out, 0.0);
@@ -1234,12 +1268,126 @@ static he_status conv_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct**
   return he_add_plain(c, z, p->bias, out);
 }
 
-static he_status matmul_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out) {
+// device table of the hoisted rotations 1..n_in-1 (rebuilt when keys change)
+static he_status hoist_items(he_ctx* c, he_plan* p, int level) {
+  const int R = (int)p->n_in - 1;
+  if (R <= 0) return HE_OK;
+  if (p->items && p->items_epoch == c->key_epoch) return HE_OK;
+  std::vector<HoistItem> h(R);
+  for (int r = 0; r < R; r++) {
+    const int step = norm_step(c, r + 1);
+    auto it = c->gal.find(step);
+    if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", step);
+    if (it->second.ml < level) return fail(HE_ENOKEY, "Galois key for step %d cut below level %d", step, level);
+    h[r].key = it->second.d;
+    h[r].g = galois_elt(c, step);
+    h[r].km = it->second.ml + 2;
+    h[r].diag = r + 1;
+  }
+  if (!p->items) {
+    p->items = (HoistItem*)c->pool.get(sizeof(HoistItem) * R);
+    if (!p->items) return fail(HE_EOOM, "item table allocation failed");
+  }
+  HIPC(hipMemcpyAsync(p->items, h.data(), sizeof(HoistItem) * R, hipMemcpyHostToDevice, c->st));
+  HIPC(hipStreamSynchronize(c->st));
+  p->items_epoch = c->key_epoch;
+  return HE_OK;
+}
+
+// acc = sum_i rot_left(x, i) * diag_i, the n_in - 1 rotations hoisted: one
+// ModUp of x's poly 1, one batched inner product, one batched ModDown NTT
+// fused with the multiply-accumulate (partial sums per chunk of rotations)
+static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
+  const int l = x->level, Lp = l + 1, nm = Lp + 1, n = c->n;
+  const int R = (int)p->n_in - 1;
+  TRY(hoist_items(c, p, l));
+  he_ct* acc = nullptr;
+  TRY(new_ct(c, l, x->scale * c->scale, &acc));
+  CtGuard gacc{acc};
+  int n_chunks = 0;
+  DBuf partial;
+  if (R > 0) {
+    DBuf coef, ext, u, ucoef;
+    TRY(dalloc(c, coef, (size_t)Lp * n));
+    TRY(dalloc(c, ext, (size_t)Lp * nm * n));
+    TRY(dalloc(c, u, (size_t)R * 2 * nm * n));
+    TRY(dalloc(c, ucoef, (size_t)R * 2 * n));
+    const u64* c1 = x->d + (size_t)Lp * n;
+    TRY(ntt_rows(c, false, c1, coef.p, 1, Lp, 0, 0));
+    TRY(modup(c, coef.p, Lp, ext.p));
+    {
+      HoistInner I{};
+      I.ext = ext.p;
+      I.c1 = c1;
+      I.items = p->items;
+      I.u = u.p;
+      I.R = R;
+      I.n_dig = Lp;
+      I.nm = nm;
+      I.t_begin = 0;
+      I.t_end = nm;
+      I.special_prime = c->L;
+      Prof pr(c, "hoisted_inner");
+      hipError_t e = launch_inner_hoisted(c->log_n, I, c->d_primes, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "hoisted inner: %s", hipGetErrorString(e));
+    }
+    {
+      NttJob J{};
+      J.src = u.p + (size_t)Lp * n;
+      J.sa = (long long)nm * n;
+      J.dst = ucoef.p;
+      J.da = n;
+      J.na = 2 * R;
+      J.nb = 1;
+      J.dst_prime[0] = (unsigned char)c->L;
+      Prof pr(c, "ntt_inv");
+      hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "hoisted intt: %s", hipGetErrorString(e));
+    }
+    // chunks of rotations so that chunks x 2 x Lp workgroups fill the chip
+    const int target = 512;
+    n_chunks = std::max(1, std::min(R, (target + 2 * Lp - 1) / (2 * Lp)));
+    const int chunk = (R + n_chunks - 1) / n_chunks;
+    n_chunks = (R + chunk - 1) / chunk;
+    TRY(dalloc(c, partial, (size_t)n_chunks * 2 * Lp * n));
+    HoistMac M{};
+    M.ucoef = ucoef.p;
+    M.u = u.p;
+    M.c0 = x->d;
+    M.diags = p->diags;
+    M.items = p->items;
+    M.partial = partial.p;
+    M.R = R;
+    M.n_dig = Lp;
+    M.nm = nm;
+    M.chunk = chunk;
+    M.special_prime = c->L;
+    const u64 sp = c->q[c->L];
+    M.h_src = (sp - 1) / 2;
+    for (int t = 0; t < Lp; t++) {
+      const u64 qt = c->q[t];
+      M.hq[t] = M.h_src % qt;
+      M.inv[t] = h_inv(sp % qt, qt);
+      M.inv_sh[t] = h_shoup(M.inv[t], qt);
+    }
+    Prof pr(c, "hoisted_moddown");
+    hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->d_fwd, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "hoisted moddown: %s", hipGetErrorString(e));
+  }
+  {
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_mac_finish(c->log_n, partial.p, n_chunks, x->d, p->diags, acc->d, Lp, c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "mac finish: %s", hipGetErrorString(e));
+  }
+  *out = acc;
+  gacc.p = nullptr;
+  return HE_OK;
+}
+
+static he_status matmul_apply(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
   const uint32_t half = (uint32_t)c->n / 2;
-  he_ct* xr = nullptr;
-  TRY(drop_copy(c, x, x->level, &xr));
   CtGuard gxr;
-  gxr.p = xr;
+  TRY(drop_copy(c, x, x->level, &gxr.p));
   uint32_t reps = 1;
   while ((uint64_t)p->n_in * reps * 2 <= half) {
     he_ct *r = nullptr, *y = nullptr;
@@ -1251,21 +1399,7 @@ static he_status matmul_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct
     reps *= 2;
   }
   CtGuard acc;
-  for (uint32_t i = 0; i < p->n_in; i++) {
-    he_ct *r = nullptr, *t = nullptr;
-    TRY(rotate_raw(c, gxr.p, (int)i, &r));
-    CtGuard gr{r};
-    TRY(mul_plain_raw(c, r, p->diags[i], &t));
-    if (!acc.p) {
-      acc.p = t;
-    } else {
-      CtGuard gt{t};
-      he_ct* s2 = nullptr;
-      TRY(he_add(c, acc.p, t, &s2));
-      he_ct_free(acc.p);
-      acc.p = s2;
-    }
-  }
+  TRY(hoisted_mac(c, p, gxr.p, &acc.p));
   he_ct* y = nullptr;
   TRY(rescale_raw(c, acc.p, &y));
   CtGuard gy{y};
@@ -1278,7 +1412,7 @@ he_status he_plan_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out
   if (x->level != p->level) return fail(HE_ELEVEL, "plan made for level %d, input at %d", p->level, x->level);
   if (!scales_match(x->scale, p->scale)) return fail(HE_ESCALE, "plan made for scale %g, input at %g", p->scale, x->scale);
   if (p->kind == PLAN_CONV) return conv_apply(c, p, x, out);
-  return matmul_apply(c, p, x, out);
+  return matmul_apply(c, const_cast<he_plan*>(p), x, out);
 }
 
 he_status he_enc_conv_im2col(he_ctx* c, const he_ct* x, const double* kernel, uint32_t kk, uint32_t windows,
@@ -1416,8 +1550,9 @@ void he_pt_free(he_pt* pt) {
 void he_plan_free(he_plan* p) {
   if (!p) return;
   he_pt_free(p->kernel);
-  for (he_pt* d : p->diags) he_pt_free(d);
   he_pt_free(p->bias);
+  if (p->diags) p->ctx->pool.put(p->diags);
+  if (p->items) p->ctx->pool.put(p->items);
   delete p;
 }
 

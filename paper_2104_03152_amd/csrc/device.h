@@ -115,29 +115,46 @@ hipError_t launch_encrypt_combine(int log_n, const u64* v, const u64* pk0,
 // key export: Montgomery -> normal form, in place over n words of prime rows
 hipError_t launch_from_mont(int log_n, u64* data, int n_rows, const ModList& mods,
                             const PrimeDev* primes, hipStream_t st);
-// hoisted rotations of one ciphertext, ModDown epilogue fused with the plain
-// multiply-accumulate of the vector-matrix product
-struct HoistJob {
-  const u64* u_coef;  // [R][2][N]: special-prime limb of u, coefficient form
-  const u64* u;       // [R][2][n_dig + 1][N]
-  const u64* c0;      // [n_dig][N] NTT domain (poly 0 of the replicated input)
-  const u64* diag;    // [n_in][n_dig][N] plaintext diagonals (Montgomery form)
-  u64* partial;       // [n_chunks][2][n_dig][N] partial sums
-  const int* rot_of;  // rotation index of each hoisted slot (size R)
-  int R, n_dig, chunk, special_prime;
-  int n_slots2;       // 2N, for Galois elements
-  const uint64_t* gal;  // Galois element per slot (size R)
+// ---- hoisted rotations of one ciphertext (vector-matrix product) ----
+// item r: left rotation with Galois element gal[r] and key keys[r] (km[r]
+// moduli stored), multiplied by diagonal diag_idx[r].
+struct HoistItem {
+  const u64* key;
+  u64 g;
+  int km;
+  int diag;
+};
+// u[r][k][t][n] = sum_j D_{j,t}[src_r(n)] * key_r[j][k][kt][n]  (t < nm)
+struct HoistInner {
+  const u64* ext;   // [n_dig][nm][N] ModUp digits (diagonal slots unused)
+  const u64* c1;    // [n_dig][N] poly 1 of the input (NTT domain)
+  const HoistItem* items;
+  u64* u;           // [R][2][nm][N]
+  int R, n_dig, nm, t_begin, t_end, special_prime;
+};
+hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev* primes,
+                                hipStream_t st);
+// ModDown of every item fused with the diagonal multiply-accumulate: WG
+// (chunk c, poly k, modulus t) sums over its items r:
+//   ((u[r][k][t] - NTT(r_r - h)) p^-1 + [k == 0] c0[t][src_r]) * diag[r][t]
+// into partial[c][k][t].
+struct HoistMac {
+  const u64* ucoef;  // [R][2][N] special-prime limb of u, coefficient form
+  const u64* u;      // [R][2][nm][N]
+  const u64* c0;     // [n_dig][N] poly 0 of the input (NTT domain)
+  const u64* diags;  // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
+  const HoistItem* items;
+  u64* partial;      // [n_chunks][2][n_dig][N]
+  int R, n_dig, nm, chunk, special_prime;
   u64 h_src;
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
 };
-hipError_t launch_hoisted_moddown_mac(int log_n, const HoistJob& job,
-                                      const PrimeDev* primes, const u64* fwd_tw,
-                                      hipStream_t st);
-// sum of partials plus the i = 0 term: out[k][t] = x[k][t]*diag0[t] +
-// sum_c partial[c][k][t]
-hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks,
-                             const u64* x, const u64* diag0, u64* out, int n_dig,
-                             const PrimeDev* primes, hipStream_t st);
-// Montgomery form of plaintext rows (for the diagonals)
+hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const PrimeDev* primes,
+                                      const u64* fwd_tw, hipStream_t st);
+// out[k][t] = x[k][t] * diag0[t] + sum_c partial[c][k][t]
+hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const u64* x,
+                             const u64* diag0, u64* out, int n_dig, const PrimeDev* primes,
+                             hipStream_t st);
+// Montgomery form of plaintext rows
 hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
                           const PrimeDev* primes, hipStream_t st);

@@ -165,14 +165,6 @@ __global__ void k_decrypt(int n, const u64* __restrict__ ct, const u64* __restri
   m[e] = addmod(ct[e], mulmod(ct[per + e], s[e], P), P.q);
 }
 
-// source slot of NTT slot i under X -> X^g (bit-reversed evaluation order):
-// slot i holds a(psi^(2 brv(i) + 1)); tau_g a at that point is a(psi^((2 brv(i)+1) g))
-__device__ __forceinline__ int gal_src(int i, int log_n, u64 g) {
-  const u32 n2mask = (2u << log_n) - 1u;
-  const u32 e = ((2u * bitrev((u32)i, log_n) + 1u) * (u32)g) & n2mask;
-  return (int)bitrev((e - 1u) >> 1, log_n);
-}
-
 __global__ void k_automorphism(int log_n, const u64* __restrict__ in, u64* __restrict__ out, long long total,
                                u64 g) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -271,6 +263,54 @@ __global__ void k_mont(int n, u64* data, long long total, int to, ModList mods,
   const PrimeDev P = primes[mods.p[row % mods.n]];
   const u64 v = data[e];
   data[e] = to ? mont_reduce(mul_wide(v, P.r2), P) : mont_reduce(U128{v, 0}, P);
+}
+
+// batched inner product of hoisted rotations: every item reads the shared
+// ModUp digits at its own Galois source index
+__global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restrict__ primes) {
+  const int n = 1 << log_n;
+  const int nt = J.t_end - J.t_begin;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)J.R * nt * n) return;
+  const int i = (int)(e & (n - 1));
+  const long long rt = e >> log_n;
+  const int t = J.t_begin + (int)(rt % nt);
+  const int r = (int)(rt / nt);
+  const HoistItem it = J.items[r];
+  const int src = gal_src(i, log_n, it.g);
+  const int kt = t < J.n_dig ? t : it.km - 1;
+  const PrimeDev P = primes[t < J.n_dig ? t : J.special_prime];
+  const size_t ks_k = (size_t)it.km * n, ks_j = 2 * ks_k;
+  const u64* kp = it.key + (size_t)kt * n + i;
+  u64 r0 = 0, r1 = 0;
+  for (int j0 = 0; j0 < J.n_dig; j0 += 8) {
+    U128 acc0 = {0, 0}, acc1 = {0, 0};
+    const int j1 = min(J.n_dig, j0 + 8);
+    for (int j = j0; j < j1; j++) {
+      const u64 d = (j == t) ? J.c1[(size_t)t * n + src] : J.ext[((size_t)j * J.nm + t) * n + src];
+      acc0 = add128(acc0, mul_wide(d, kp[j * ks_j]));
+      acc1 = add128(acc1, mul_wide(d, kp[j * ks_j + ks_k]));
+    }
+    r0 = addmod(r0, mont_reduce(acc0, P), P.q);
+    r1 = addmod(r1, mont_reduce(acc1, P), P.q);
+  }
+  J.u[(((size_t)r * 2 + 0) * J.nm + t) * n + i] = r0;
+  J.u[(((size_t)r * 2 + 1) * J.nm + t) * n + i] = r1;
+}
+
+__global__ void k_mac_finish(int log_n, const u64* __restrict__ partial, int n_chunks, const u64* __restrict__ x,
+                             const u64* __restrict__ diag0, u64* __restrict__ out, int n_dig,
+                             const PrimeDev* __restrict__ primes) {
+  const int n = 1 << log_n;
+  const long long per = 2LL * n_dig * n;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= per) return;
+  const int t = (int)((e >> log_n) % n_dig);
+  const int i = (int)(e & (n - 1));
+  const PrimeDev P = primes[t];
+  u64 s = mulmod(x[e], diag0[(size_t)t * n + i], P);
+  for (int c = 0; c < n_chunks; c++) s = addmod(s, partial[(size_t)c * per + e], P.q);
+  out[e] = s;
 }
 
 inline dim3 grid_for(long long total) { return dim3((unsigned)((total + BLK - 1) / BLK)); }
@@ -387,5 +427,20 @@ hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
                           hipStream_t st) {
   const long long total = (long long)n_rows << log_n;
   hipLaunchKernelGGL(k_mont, grid_for(total), dim3(BLK), 0, st, 1 << log_n, data, total, 1, mods, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev* primes, hipStream_t st) {
+  const long long total = ((long long)job.R * (job.t_end - job.t_begin)) << log_n;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inner_hoisted, grid_for(total), dim3(BLK), 0, st, log_n, job, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const u64* x, const u64* diag0, u64* out,
+                             int n_dig, const PrimeDev* primes, hipStream_t st) {
+  const long long total = (2LL * n_dig) << log_n;
+  hipLaunchKernelGGL(k_mac_finish, grid_for(total), dim3(BLK), 0, st, log_n, partial, n_chunks, x, diag0, out,
+                     n_dig, primes);
   return hipGetLastError();
 }

@@ -117,3 +117,14 @@ __device__ __forceinline__ u64 red_signed(i64 v, const PrimeDev& P) {
 __device__ __forceinline__ u32 bitrev(u32 x, int bits) {
   return __builtin_bitreverse32(x) >> (32 - bits);
 }
+
+// NTT slot i holds a(psi^(2 brv(i) + 1)) (bit-reversed evaluation order), so
+// X -> X^g reads slot brv(((2 brv(i) + 1) g mod 2N - 1) / 2).  For 64
+// consecutive aligned slots the sources are a permutation of one aligned
+// 64-slot block (the map is affine in the reversed index), so the gather
+// stays coalesced.
+__device__ __forceinline__ int gal_src(int i, int log_n, u64 g) {
+  const u32 n2mask = (2u << log_n) - 1u;
+  const u32 e = ((2u * bitrev((u32)i, log_n) + 1u) * (u32)g) & n2mask;
+  return (int)bitrev((e - 1u) >> 1, log_n);
+}

@@ -268,6 +268,93 @@ k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
   }
 }
 
+// Hoisted rotations: ModDown of each item (an NTT of its special-prime limb,
+// lifted) with the plaintext multiply-accumulate of the vector-matrix
+// product in the epilogue.  Workgroup (chunk, k, t) loops over its items,
+// keeping the running sums in registers.
+template <int LOGN>
+__global__ void __launch_bounds__(Cfg<LOGN>::T)
+k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __restrict__ tw) {
+  using C = Cfg<LOGN>;
+  constexpr int N = C::N;
+  constexpr int R0 = C::bits(0), LO0 = LOGN - R0, G0 = 16 >> R0;
+  constexpr int RF = C::bits(C::NP - 1), GF = 16 >> RF;
+  extern __shared__ u64 lds[];
+  const int tid = threadIdx.x;
+  const int pairs = 2 * J.n_dig;
+  const int chunk = blockIdx.x / pairs;
+  const int kt = blockIdx.x - chunk * pairs;
+  const int k = kt / J.n_dig, t = kt - k * J.n_dig;
+  const PrimeDev P = primes[t];
+  const u64 q = P.q, q2 = q << 1;
+  const ulonglong2* W = reinterpret_cast<const ulonglong2*>(tw) + (size_t)t * N;
+  const u64 sq = primes[J.special_prime].q, sh = J.h_src;
+  const u64 hq = J.hq[t], inv = J.inv[t], inv_sh = J.inv_sh[t];
+  u64 acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; e++) acc[e] = 0;
+  const int rb = chunk * J.chunk, re = min(J.R, rb + J.chunk);
+  for (int r = rb; r < re; r++) {
+    const HoistItem it = J.items[r];
+    const u64* __restrict__ src = J.ucoef + ((size_t)r * 2 + k) * N;
+    u64 x[16];
+#pragma unroll
+    for (int u = 0; u < G0; u++) {
+      const int gi = tid + C::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R0); c++) {
+        u64 v = src[(c << LO0) | gi] + sh;
+        v = v >= sq ? v - sq : v;
+        x[u * (1 << R0) + c] = submod(red64(v, P), hq, q);
+      }
+    }
+    fwd_passes<LOGN, 0>(x, lds, W, q, tid);
+    const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
+    const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
+    const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
+#pragma unroll
+    for (int u = 0; u < GF; u++) {
+      const int gi = tid + C::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << RF); c++) {
+        u64 v = x[u * (1 << RF) + c];
+        v = v >= q2 ? v - q2 : v;
+        v = v >= q ? v - q : v;
+        const int idx = (gi << RF) | c;
+        u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+        if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
+        acc[u * (1 << RF) + c] = addmod(acc[u * (1 << RF) + c], mulmod(ks, dg[idx], P), q);
+      }
+    }
+    __syncthreads();
+  }
+  u64* __restrict__ out = J.partial + (((size_t)chunk * 2 + k) * J.n_dig + t) * N;
+#pragma unroll
+  for (int u = 0; u < GF; u++) {
+    const int gi = tid + C::T * u;
+#pragma unroll
+    for (int c = 0; c < (1 << RF); c++) out[(gi << RF) | c] = acc[u * (1 << RF) + c];
+  }
+}
+
+template <int LOGN>
+hipError_t hoist_launch(const HoistMac& J, const PrimeDev* primes, const u64* tw, hipStream_t st) {
+  using C = Cfg<LOGN>;
+  const size_t shm = sizeof(u64) * C::lds_words();
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_hoist_mac<LOGN>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int n_chunks = (J.R + J.chunk - 1) / J.chunk;
+  const int blocks = n_chunks * 2 * J.n_dig;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_hoist_mac<LOGN>), dim3(blocks), dim3(C::T), shm, st, J, primes, tw);
+  return hipGetLastError();
+}
+
 int n_jobs(const NttJob& J) { return J.na * (J.skip_diag ? J.nb - 1 : J.nb); }
 
 template <int LOGN, int PRO, int EPI>
@@ -337,6 +424,18 @@ hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes, 
     case 12: return inv_launch<12>(job, primes, inv_tw, st);
     case 13: return inv_launch<13>(job, primes, inv_tw, st);
     case 14: return inv_launch<14>(job, primes, inv_tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const PrimeDev* primes, const u64* fwd_tw,
+                                      hipStream_t st) {
+  switch (log_n) {
+    case 10: return hoist_launch<10>(job, primes, fwd_tw, st);
+    case 11: return hoist_launch<11>(job, primes, fwd_tw, st);
+    case 12: return hoist_launch<12>(job, primes, fwd_tw, st);
+    case 13: return hoist_launch<13>(job, primes, fwd_tw, st);
+    case 14: return hoist_launch<14>(job, primes, fwd_tw, st);
     default: return hipErrorInvalidValue;
   }
 }
