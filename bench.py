@@ -35,7 +35,7 @@ def build_network(H, g, x, d):
     s_ = __import__("paper_2104_03152_amd.inputs", fromlist=["CNN_SHAPE"]).CNN_SHAPE
     conv = [H.he_conv_plan(g, x, d["conv_k"][c], s_["windows"], d["conv_b"][c])
             for c in range(s_["channels"])]
-    parts = [H.he_plan_apply(g, p, x) for p in conv]
+    parts = H.he_plan_apply_many(g, conv, x)
     s1 = H.he_square(g, H.he_pack(g, parts, s_["windows"]))
     fc1 = H.he_matmul_plan(g, s1, d["w1"], d["b1"])
     s2 = H.he_square(g, H.he_plan_apply(g, fc1, s1))
@@ -45,7 +45,7 @@ def build_network(H, g, x, d):
 
 def step(H, g, net, x, width, stamp=None):
     conv, fc1, fc2 = net
-    parts = [H.he_plan_apply(g, p, x) for p in conv]
+    parts = H.he_plan_apply_many(g, conv, x)
     if stamp:
         stamp("conv")
     p = H.he_pack(g, parts, width)

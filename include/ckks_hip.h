@@ -190,6 +190,12 @@ he_status he_matmul_plan(he_ctx* ctx, const he_ct* like, const double* W,
 /* HE_ELEVEL / HE_ESCALE if x does not match the plan's level and scale. */
 he_status he_plan_apply(he_ctx* ctx, const he_plan* plan, const he_ct* x,
                         he_ct** out);
+/* n plans on the same input, outs[0..n-1].  Convolution plans that share
+ * (kk, windows) run in lock step: their channels' rotations go out as one
+ * batched key switch per step (the section 5 network's 4 channels).  Results
+ * are identical to n calls of he_plan_apply; on error every outs[i] is NULL. */
+he_status he_plan_apply_many(he_ctx* ctx, const he_plan* const* plans,
+                             uint32_t n, const he_ct* x, he_ct** outs);
 
 /* ---- raw transforms (batched negacyclic NTT on caller device buffers) ---- */
 /* data: device pointer to n_polys polynomials of n_limbs limbs, layout

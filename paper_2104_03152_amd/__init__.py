@@ -72,6 +72,7 @@ _SIGS = {
     "he_conv_plan": (C.c_int32, [_vp, _vp, _dp, C.c_uint32, C.c_uint32, C.c_double, _pvp]),
     "he_matmul_plan": (C.c_int32, [_vp, _vp, _dp, C.c_uint32, C.c_uint32, _dp, _pvp]),
     "he_plan_apply": (C.c_int32, [_vp, _vp, _vp, _pvp]),
+    "he_plan_apply_many": (C.c_int32, [_vp, _pvp, C.c_uint32, _vp, _pvp]),
     "he_ntt_forward": (C.c_int32, [_vp, _vp, C.c_size_t, C.c_int32]),
     "he_ntt_inverse": (C.c_int32, [_vp, _vp, C.c_size_t, C.c_int32]),
     "he_export_secret": (C.c_int32, [_vp, _i64p]),
@@ -346,6 +347,14 @@ def he_matmul_plan(ctx, like, W, bias=None):
 
 def he_plan_apply(ctx, plan, x):
     return _new(Ct, ctx, lib().he_plan_apply, "he_plan_apply", ctx.ptr, plan.ptr, x.ptr)
+
+
+def he_plan_apply_many(ctx, plans, x):
+    n = len(plans)
+    arr = (C.c_void_p * n)(*[p.ptr for p in plans])
+    outs = (C.c_void_p * n)()
+    _chk(lib().he_plan_apply_many(ctx.ptr, arr, n, x.ptr, outs), "he_plan_apply_many")
+    return [Ct(ctx, outs[i]) for i in range(n)]
 
 
 def he_ntt_forward(ctx, dev_ptr, n_polys, n_limbs):

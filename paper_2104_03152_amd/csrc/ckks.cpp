@@ -328,11 +328,28 @@ he_status ntt_rows_mods(he_ctx* c, bool fwd, const u64* src, u64* dst, int n_pol
   return HE_OK;
 }
 
-// dst = round(u / q_src) over targets 0..n_t-1: src_coef [2][N] holds the
-// coefficient form of the divisor limb of each of the 2 polys; u is the NTT
-// domain dividend [2][..][N] with poly stride ua; result poly stride da.
-he_status round_div(he_ctx* c, const u64* src_coef, int src_prime, const u64* u, long long ua, u64* dst,
-                    long long da, int n_t, const u64* add0, const u64* add1, const char* fam) {
+u64 galois_elt(const he_ctx* c, int step) {
+  return h_powm(5, (u64)step, 2 * (u64)c->n);
+}
+
+int norm_step(const he_ctx* c, long long step) {
+  long long half = c->n / 2;
+  step %= half;
+  if (step < 0) step += half;
+  return (int)step;
+}
+
+// dst = round(u / q_src) over targets 0..n_t-1 for n_poly polynomials:
+// src_coef [n_poly][N] holds the coefficient form of each divisor limb; u is
+// the NTT-domain dividend, poly a at u + a*ua; result poly a at dst + a*da;
+// optional addend at add + a*aa + t*N (every poly, or even polys only).
+struct Addend {
+  const u64* p = nullptr;
+  long long aa = 0;
+  int even_only = 0;
+};
+he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, const u64* u, long long ua,
+                    u64* dst, long long da, int n_t, Addend add, const char* fam) {
   NttJob J{};
   J.src = src_coef;
   J.sa = c->n;
@@ -340,15 +357,16 @@ he_status round_div(he_ctx* c, const u64* src_coef, int src_prime, const u64* u,
   J.dst = dst;
   J.da = da;
   J.db = c->n;
-  J.na = 2;
+  J.na = n_poly;
   J.nb = n_t;
   J.src_prime = src_prime;
   J.u = u;
   J.ua = ua;
   J.ub = c->n;
-  J.add0 = add0;
-  J.add1 = add1;
+  J.add = add.p;
+  J.aa = add.aa;
   J.ab = c->n;
+  J.add_even_only = add.even_only;
   const u64 p = c->q[src_prime];
   J.h_src = (p - 1) / 2;
   for (int t = 0; t < n_t; t++) {
@@ -364,10 +382,11 @@ he_status round_div(he_ctx* c, const u64* src_coef, int src_prime, const u64* u,
   return HE_OK;
 }
 
-// ModUp: centred digit j (coefficient form [Lp][N]) lifted to every other
-// modulus (data 0..Lp-1, then the special prime) and transformed; the
-// diagonal slots ext[j][j] are left out (they are the input limbs).
-he_status modup(he_ctx* c, const u64* coef, int Lp, u64* ext) {
+// ModUp of B items: centred digit j of item b (coefficient form, [B][Lp][N])
+// lifted to every other modulus (data 0..Lp-1, then the special prime) and
+// transformed into ext [B][Lp][nm][N]; the diagonal slots ext[b][j][j] are
+// left out (they are the input limbs themselves).
+he_status modup(he_ctx* c, const u64* coef, int B, int Lp, u64* ext) {
   const int n = c->n, nm = Lp + 1;
   NttJob J{};
   J.src = coef;
@@ -376,11 +395,11 @@ he_status modup(he_ctx* c, const u64* coef, int Lp, u64* ext) {
   J.dst = ext;
   J.da = (long long)nm * n;
   J.db = n;
-  J.na = Lp;
+  J.na = B * Lp;
   J.nb = nm;
   J.skip_diag = 1;
   J.src_prime = -1;
-  for (int j = 0; j < Lp; j++) J.src_prime_of_a[j] = (unsigned char)j;
+  J.amod = Lp;
   for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
   Prof pr(c, "modup");
   hipError_t e = launch_ntt_fwd(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, J, c->d_primes, c->d_fwd, c->st);
@@ -389,29 +408,35 @@ he_status modup(he_ctx* c, const u64* coef, int Lp, u64* ext) {
 }
 
 // ---------------------------------------------------------------- key switching
-// out [2][l+1][N] = KeySwitch(d) (+ addends), d: NTT domain [l+1][N]
-he_status key_switch(he_ctx* c, const u64* d, int l, const Key& key, const u64* add0, const u64* add1,
+// Key switch of B polynomials at level l: item b's input d + b*ds (NTT domain
+// [l+1][N]) with keys[b]; out [B][2][l+1][N] = KeySwitch(d_b) + addend.
+he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const Key* const* keys, Addend add,
                      u64* out) {
   const int n = c->n, Lp = l + 1, nm = Lp + 1;
-  if (key.ml < l) return fail(HE_ENOKEY, "key valid up to level %d, ciphertext at level %d", key.ml, l);
+  if (B < 1 || B > HE_MAX_BATCH) return fail(HE_EINVAL, "key-switch batch of %d", B);
+  for (int b = 0; b < B; b++)
+    if (keys[b]->ml < l)
+      return fail(HE_ENOKEY, "key valid up to level %d, ciphertext at level %d", keys[b]->ml, l);
   DBuf coef, ext, u, ucoef;
-  TRY(dalloc(c, coef, (size_t)Lp * n));
-  TRY(dalloc(c, ext, (size_t)Lp * nm * n));
-  TRY(dalloc(c, u, 2 * (size_t)nm * n));
-  TRY(dalloc(c, ucoef, 2 * (size_t)n));
-  TRY(ntt_rows(c, false, d, coef.p, 1, Lp, 0, 0));
-  TRY(modup(c, coef.p, Lp, ext.p));
+  TRY(dalloc(c, coef, (size_t)B * Lp * n));
+  TRY(dalloc(c, ext, (size_t)B * Lp * nm * n));
+  TRY(dalloc(c, u, (size_t)B * 2 * nm * n));
+  TRY(dalloc(c, ucoef, (size_t)B * 2 * n));
+  TRY(ntt_rows(c, false, d, coef.p, B, Lp, ds, (long long)Lp * n));
+  TRY(modup(c, coef.p, B, Lp, ext.p));
   {
     InnerJob I{};
     I.ext = ext.p;
     I.diag = d;
-    I.key = key.d;
+    I.diag_stride = ds;
     I.u = u.p;
+    I.B = B;
     I.n_dig = Lp;
-    I.key_digits = key.ml + 1;
-    I.key_mods = key.ml + 2;
     I.special_prime = c->L;
-    I.gather_g = 1;
+    for (int b = 0; b < B; b++) {
+      I.key[b] = keys[b]->d;
+      I.km[b] = keys[b]->ml + 2;
+    }
     Prof pr(c, "keyswitch_inner");
     hipError_t e = launch_inner(c->log_n, I, c->d_primes, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "inner: %s", hipGetErrorString(e));
@@ -422,14 +447,68 @@ he_status key_switch(he_ctx* c, const u64* d, int l, const Key& key, const u64* 
     J.sa = (long long)nm * n;
     J.dst = ucoef.p;
     J.da = n;
-    J.na = 2;
+    J.na = 2 * B;
     J.nb = 1;
     J.dst_prime[0] = (unsigned char)c->L;
     Prof pr(c, "ntt_inv");
     hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "intt special: %s", hipGetErrorString(e));
   }
-  return round_div(c, ucoef.p, c->L, u.p, (long long)nm * n, out, (long long)Lp * n, Lp, add0, add1, "moddown");
+  return round_div(c, 2 * B, ucoef.p, c->L, u.p, (long long)nm * n, out, (long long)Lp * n, Lp, add, "moddown");
+}
+
+// Left rotations of B ciphertexts stored contiguously ([B][2][l+1][N] at in)
+// by steps[b]: tau_g on both polys, then one batched key switch of the
+// rotated poly 1 with tau_g(c0) as addend.  out: [B][2][l+1][N].
+he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps, u64* out) {
+  const int n = c->n, Lp = l + 1;
+  const Key* keys[HE_MAX_BATCH];
+  AutJob A{};
+  A.B = B;
+  A.rows_per_item = 2 * Lp;
+  for (int b = 0; b < B; b++) {
+    auto it = c->gal.find(steps[b]);
+    if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", steps[b]);
+    if (it->second.ml < l)
+      return fail(HE_ENOKEY, "Galois key for step %d cut at level %d, ciphertext at %d", steps[b], it->second.ml, l);
+    keys[b] = &it->second;
+    A.g[b] = galois_elt(c, steps[b]);
+  }
+  DBuf tr;
+  TRY(dalloc(c, tr, (size_t)B * 2 * Lp * n));
+  {
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_automorphism(c->log_n, in, tr.p, A, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "automorphism: %s", hipGetErrorString(e));
+  }
+  Addend add;
+  add.p = tr.p;
+  add.aa = (long long)Lp * n;
+  add.even_only = 1;
+  return key_switch(c, B, tr.p + (size_t)Lp * n, 2LL * Lp * n, l, keys, add, out);
+}
+
+// rescale of n_ct contiguous ciphertexts [n_ct][2][l+1][N] -> [n_ct][2][l][N]
+he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
+  const int n = c->n;
+  if (l < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  DBuf coef;
+  TRY(dalloc(c, coef, 2 * (size_t)n_ct * n));
+  {
+    NttJob J{};
+    J.src = in + (size_t)l * n;
+    J.sa = (long long)(l + 1) * n;
+    J.dst = coef.p;
+    J.da = n;
+    J.na = 2 * n_ct;
+    J.nb = 1;
+    J.dst_prime[0] = (unsigned char)l;
+    Prof pr(c, "ntt_inv");
+    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "rescale intt: %s", hipGetErrorString(e));
+  }
+  return round_div(c, 2 * n_ct, coef.p, l, in, (long long)(l + 1) * n, out, (long long)l * n, l, Addend(),
+                   "rescale");
 }
 
 // copy a ciphertext's limbs 0..level into a fresh buffer layout
@@ -457,16 +536,6 @@ he_status align2(he_ctx* c, const he_ct* a, const he_ct* b, const he_ct** ra, co
   return HE_OK;
 }
 
-u64 galois_elt(const he_ctx* c, int step) {
-  return h_powm(5, (u64)step, 2 * (u64)c->n);
-}
-
-int norm_step(const he_ctx* c, long long step) {
-  long long half = c->n / 2;
-  step %= half;
-  if (step < 0) step += half;
-  return (int)step;
-}
 
 // ---------------------------------------------------------------- key generation
 // switching key from s' (NTT domain [L+1][N]) to s, valid up to level ml
@@ -515,7 +584,11 @@ he_status galois_key(he_ctx* c, int step, int ml) {
   if (it != c->gal.end() && it->second.ml >= ml) return HE_OK;
   DBuf sp;
   TRY(dalloc(c, sp, (size_t)(c->L + 1) * c->n));
-  hipError_t e = launch_automorphism(c->log_n, c->d_s, sp.p, c->L + 1, galois_elt(c, step), c->st);
+  AutJob A{};
+  A.B = 1;
+  A.rows_per_item = c->L + 1;
+  A.g[0] = galois_elt(c, step);
+  hipError_t e = launch_automorphism(c->log_n, c->d_s, sp.p, A, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "automorphism: %s", hipGetErrorString(e));
   Key& k = c->gal[step];
   return make_key(c, k, ml, sp.p, 6, 7, (uint32_t)step * 256u);
@@ -1006,27 +1079,11 @@ static he_status mul_plain_raw(he_ctx* c, const he_ct* a, const he_pt* p, he_ct*
 }
 
 static he_status rescale_raw(he_ctx* c, const he_ct* a, he_ct** out) {
-  const int l = a->level, n = c->n;
+  const int l = a->level;
   if (l < 1) return fail(HE_ELEVEL, "no level left to rescale");
-  DBuf coef;
-  TRY(dalloc(c, coef, 2 * (size_t)n));
-  {
-    NttJob J{};
-    J.src = a->d + (size_t)l * n;
-    J.sa = (long long)(l + 1) * n;
-    J.dst = coef.p;
-    J.da = n;
-    J.na = 2;
-    J.nb = 1;
-    J.dst_prime[0] = (unsigned char)l;
-    Prof pr(c, "ntt_inv");
-    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
-    if (e != hipSuccess) return fail(HE_EHIP, "rescale intt: %s", hipGetErrorString(e));
-  }
   he_ct* r = nullptr;
   TRY(new_ct(c, l - 1, a->scale / (double)c->q[l], &r));
-  he_status s = round_div(c, coef.p, l, a->d, (long long)(l + 1) * n, r->d, (long long)l * n, l, nullptr, nullptr,
-                          "rescale");
+  he_status s = rescale_multi(c, a->d, 1, l, r->d);
   if (s != HE_OK) {
     he_ct_free(r);
     return s;
@@ -1074,7 +1131,13 @@ static he_status mul_relin_raw(he_ctx* c, const he_ct* a, const he_ct* b, he_ct*
     hipError_t e = launch_tensor(c->log_n, x->d, y->d, r->d, d2.p, mods_range(Lp), c->d_primes, c->st);
     if (e != hipSuccess) s = fail(HE_EHIP, "tensor: %s", hipGetErrorString(e));
   }
-  if (s == HE_OK) s = key_switch(c, d2.p, l, c->relin, r->d, r->d + (size_t)Lp * n, r->d);
+  if (s == HE_OK) {
+    const Key* kp = &c->relin;
+    Addend add;
+    add.p = r->d;
+    add.aa = (long long)Lp * n;
+    s = key_switch(c, 1, d2.p, 0, l, &kp, add, r->d);
+  }
   if (s != HE_OK) {
     he_ct_free(r);
     return s;
@@ -1101,23 +1164,12 @@ he_status he_drop_to(he_ctx* c, const he_ct* a, int32_t level, he_ct** out) {
 }
 
 static he_status rotate_raw(he_ctx* c, const he_ct* a, int step, he_ct** out) {
-  const int l = a->level, Lp = l + 1, n = c->n;
+  const int l = a->level;
   step = norm_step(c, step);
   if (step == 0) return drop_copy(c, a, l, out);
-  auto it = c->gal.find(step);
-  if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", step);
-  if (it->second.ml < l)
-    return fail(HE_ENOKEY, "Galois key for step %d cut at level %d, ciphertext at %d", step, it->second.ml, l);
-  DBuf tr;
-  TRY(dalloc(c, tr, 2 * (size_t)Lp * n));
-  {
-    Prof pr(c, "pointwise");
-    hipError_t e = launch_automorphism(c->log_n, a->d, tr.p, 2 * Lp, galois_elt(c, step), c->st);
-    if (e != hipSuccess) return fail(HE_EHIP, "automorphism: %s", hipGetErrorString(e));
-  }
   he_ct* r = nullptr;
   TRY(new_ct(c, l, a->scale, &r));
-  he_status s = key_switch(c, tr.p + (size_t)Lp * n, l, it->second, tr.p, nullptr, r->d);
+  he_status s = rotate_multi(c, a->d, 1, l, &step, r->d);
   if (s != HE_OK) {
     he_ct_free(r);
     return s;
@@ -1257,15 +1309,60 @@ he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t
   return HE_OK;
 }
 
+// n convolution plans on the same input in lock step: the n channel
+// ciphertexts live side by side ([n][2][l+1][N]) so every rotation step is one
+// batched key switch.  Same operations, same results as n single applies.
+static he_status conv_apply_many(he_ctx* c, const he_plan* const* plans, int nb, const he_ct* x, he_ct** outs) {
+  const int n = c->n, l = x->level, Lp = l + 1;
+  const size_t ct_w = 2 * (size_t)Lp * n, ct_w1 = 2 * (size_t)l * n;
+  DBuf M, Y, R;
+  TRY(dalloc(c, M, nb * ct_w));
+  TRY(dalloc(c, Y, nb * ct_w1));
+  TRY(dalloc(c, R, nb * ct_w1));
+  {
+    Prof pr(c, "pointwise");
+    for (int b = 0; b < nb; b++) {
+      hipError_t e = launch_mul_plain(c->log_n, x->d, plans[b]->kernel->d, M.p + b * ct_w, 2, mods_range(Lp),
+                                      c->d_primes, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "mul_plain: %s", hipGetErrorString(e));
+    }
+  }
+  TRY(rescale_multi(c, M.p, nb, l, Y.p));
+  const double scale = x->scale * plans[0]->kernel->scale / (double)c->q[l];
+  int steps = 0;
+  while ((1u << steps) < plans[0]->kk) steps++;
+  std::vector<int> st(nb);
+  for (int j = 0; j < steps; j++) {
+    for (int b = 0; b < nb; b++) st[b] = norm_step(c, (long long)plans[0]->windows << j);
+    if (st[0] == 0) {  // rotation by a multiple of N/2: x + x
+      Prof pr(c, "pointwise");
+      hipError_t e = launch_addsub(c->log_n, 0, Y.p, Y.p, Y.p, 2 * nb, mods_range(l), c->d_primes, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "add: %s", hipGetErrorString(e));
+      continue;
+    }
+    TRY(rotate_multi(c, Y.p, nb, l - 1, st.data(), R.p));
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_addsub(c->log_n, 0, Y.p, R.p, Y.p, 2 * nb, mods_range(l), c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "add: %s", hipGetErrorString(e));
+  }
+  for (int b = 0; b < nb; b++) {
+    if (!scales_match(scale, plans[b]->bias->scale)) return fail(HE_ESCALE, "bias scale");
+    he_ct* r = nullptr;
+    TRY(new_ct(c, l - 1, scale, &r));
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_add_plain(c->log_n, Y.p + b * ct_w1, plans[b]->bias->d, r->d, 2, mods_range(l),
+                                    c->d_primes, c->st);
+    if (e != hipSuccess) {
+      he_ct_free(r);
+      return fail(HE_EHIP, "add_plain: %s", hipGetErrorString(e));
+    }
+    outs[b] = r;
+  }
+  return HE_OK;
+}
+
 static he_status conv_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out) {
-  he_ct *m = nullptr, *y = nullptr, *z = nullptr;
-  TRY(mul_plain_raw(c, x, p->kernel, &m));
-  he_status s = rescale_raw(c, m, &y);
-  he_ct_free(m);
-  if (s != HE_OK) return s;
-  TRY(rotate_and_sum(c, y, p->kk, p->windows, &z));
-  CtGuard gz{z};
-  return he_add_plain(c, z, p->bias, out);
+  return conv_apply_many(c, &p, 1, x, out);
 }
 
 // device table of the hoisted rotations 1..n_in-1 (rebuilt when keys change)
@@ -1314,7 +1411,7 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
     TRY(dalloc(c, ucoef, (size_t)R * 2 * n));
     const u64* c1 = x->d + (size_t)Lp * n;
     TRY(ntt_rows(c, false, c1, coef.p, 1, Lp, 0, 0));
-    TRY(modup(c, coef.p, Lp, ext.p));
+    TRY(modup(c, coef.p, 1, Lp, ext.p));
     {
       HoistInner I{};
       I.ext = ext.p;
@@ -1415,6 +1512,33 @@ he_status he_plan_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out
   return matmul_apply(c, const_cast<he_plan*>(p), x, out);
 }
 
+he_status he_plan_apply_many(he_ctx* c, const he_plan* const* plans, uint32_t nb, const he_ct* x,
+                             he_ct** outs) {
+  if (!c || !plans || !x || !outs) return fail(HE_EINVAL, "NULL argument");
+  for (uint32_t b = 0; b < nb; b++) outs[b] = nullptr;
+  if (nb == 0) return HE_OK;
+  bool lockstep = nb <= HE_MAX_BATCH;
+  for (uint32_t b = 0; b < nb; b++) {
+    if (!plans[b]) return fail(HE_EINVAL, "NULL plan");
+    if (x->level != plans[b]->level) return fail(HE_ELEVEL, "plan made for level %d, input at %d", plans[b]->level, x->level);
+    if (!scales_match(x->scale, plans[b]->scale)) return fail(HE_ESCALE, "plan scale differs from the input's");
+    lockstep = lockstep && plans[b]->kind == PLAN_CONV && plans[b]->kk == plans[0]->kk &&
+               plans[b]->windows == plans[0]->windows && plans[b]->kernel->scale == plans[0]->kernel->scale;
+  }
+  he_status s = HE_OK;
+  if (lockstep) {
+    s = conv_apply_many(c, plans, (int)nb, x, outs);
+  } else {
+    for (uint32_t b = 0; b < nb && s == HE_OK; b++) s = he_plan_apply(c, plans[b], x, &outs[b]);
+  }
+  if (s != HE_OK)
+    for (uint32_t b = 0; b < nb; b++) {
+      he_ct_free(outs[b]);
+      outs[b] = nullptr;
+    }
+  return s;
+}
+
 he_status he_enc_conv_im2col(he_ctx* c, const he_ct* x, const double* kernel, uint32_t kk, uint32_t windows,
                              double bias, he_ct** out) {
   he_plan* p = nullptr;
@@ -1438,7 +1562,8 @@ he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t wid
   *out = nullptr;
   const uint32_t half = (uint32_t)c->n / 2;
   if (n_parts == 0 || width == 0 || (uint64_t)width * n_parts > half) return fail(HE_ERANGE, "width * parts > N/2");
-  int l = parts[0]->level;
+  if (n_parts > HE_MAX_BATCH + 1) return fail(HE_ERANGE, "more than %d parts", HE_MAX_BATCH + 1);
+  int l = parts[0] ? parts[0]->level : 0;
   for (uint32_t k = 0; k < n_parts; k++) {
     if (!parts[k]) return fail(HE_EINVAL, "NULL part");
     l = std::min(l, parts[k]->level);
@@ -1454,34 +1579,45 @@ he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t wid
     TRY(encode_slots(c, ones, c->scale, l, &mask));
     c->masks[key] = mask;
   }
-  CtGuard acc;
-  for (uint32_t k = 0; k < n_parts; k++) {
-    CtGuard a, m, r;
+  const int n = c->n, Lp = l + 1, np = (int)n_parts;
+  const size_t ct_w = 2 * (size_t)Lp * n, ct_w1 = 2 * (size_t)l * n;
+  DBuf M, Y;
+  TRY(dalloc(c, M, np * ct_w));
+  TRY(dalloc(c, Y, np * ct_w1));
+  for (int k = 0; k < np; k++) {
+    CtGuard a;
     const he_ct* src = parts[k];
     if (src->level != l) {
       TRY(drop_copy(c, src, l, &a.p));
       src = a.p;
     }
-    TRY(mul_plain_raw(c, src, mask, &m.p));
-    TRY(rescale_raw(c, m.p, &r.p));
-    if (k > 0) {
-      he_ct* t = nullptr;
-      TRY(rotate_raw(c, r.p, (int)(half - width * k), &t));
-      he_ct_free(r.p);
-      r.p = t;
-    }
-    if (!acc.p) {
-      acc.p = r.p;
-      r.p = nullptr;
-    } else {
-      he_ct* s2 = nullptr;
-      TRY(he_add(c, acc.p, r.p, &s2));
-      he_ct_free(acc.p);
-      acc.p = s2;
-    }
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_mul_plain(c->log_n, src->d, mask->d, M.p + k * ct_w, 2, mods_range(Lp), c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "mul_plain: %s", hipGetErrorString(e));
   }
-  *out = acc.p;
-  acc.p = nullptr;
+  TRY(rescale_multi(c, M.p, np, l, Y.p));
+  const double scale0 = parts[0]->scale * mask->scale / (double)c->q[l];
+  for (int k = 1; k < np; k++)
+    if (!scales_match(parts[k]->scale * mask->scale / (double)c->q[l], scale0))
+      return fail(HE_ESCALE, "part scales differ");
+  DBuf R;
+  if (np > 1) {
+    TRY(dalloc(c, R, (np - 1) * ct_w1));
+    std::vector<int> st(np - 1);
+    for (int k = 1; k < np; k++) st[k - 1] = norm_step(c, (long long)half - (long long)width * k);
+    TRY(rotate_multi(c, Y.p + ct_w1, np - 1, l - 1, st.data(), R.p));
+  }
+  he_ct* r = nullptr;
+  TRY(new_ct(c, l - 1, scale0, &r));
+  CtGuard gr{r};
+  HIPC(hipMemcpyAsync(r->d, Y.p, ct_w1 * sizeof(u64), hipMemcpyDeviceToDevice, c->st));
+  for (int k = 1; k < np; k++) {
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_addsub(c->log_n, 0, r->d, R.p + (k - 1) * ct_w1, r->d, 2, mods_range(l), c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "add: %s", hipGetErrorString(e));
+  }
+  *out = r;
+  gr.p = nullptr;
   return HE_OK;
 }
 

@@ -9,28 +9,31 @@
 
 #define HE_MAXM 33  // data primes + special prime
 
-// One batched NTT launch: job w = a * nb + b (nb' = nb - 1 and b skipping a
-// when skip_diag is set).  Source a*sa + b*sb, destination a*da + b*db (u64
-// element offsets); destination prime dst_prime[b].
+// One batched NTT launch: job w = a * nb + b, or, with skip_diag, over
+// nb - 1 targets per a skipping b == (a mod amod).  Source a*sa + b*sb,
+// destination a*da + b*db (u64 element offsets); destination prime
+// dst_prime[b]; source prime src_prime, or (a mod amod) when src_prime < 0.
 struct NttJob {
   const u64* src;
   u64* dst;
   long long sa, sb, da, db;
   int na, nb;
-  int skip_diag;       // jobs with b == a are left out
-  int src_prime;       // source prime: >= 0 fixed, < 0 means src_prime_of_a[a]
+  int skip_diag;
+  int src_prime;
+  int amod;
   unsigned char dst_prime[HE_MAXM];
-  unsigned char src_prime_of_a[HE_MAXM];
-  // divide-and-round: prologue r - h_b, epilogue dst = (u - NTT(r - h_b)) * inv_b (+ addend)
+  // divide-and-round: prologue r - h_b, epilogue dst = (u - NTT(r - h_b)) * inv_b
+  // plus the addend add[a*aa + b*ab] (for every a, or even a only)
   const u64* u;
   long long ua, ub;
-  const u64* add0;     // addend for a == 0 (nullable), offset b*ab
-  const u64* add1;     // addend for a == 1 (nullable)
-  long long ab;
-  u64 h_src;           // (q_src - 1) / 2
+  const u64* add;
+  long long aa, ab;
+  int add_even_only;
+  u64 h_src;
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
 };
 
+#define HE_MAX_BATCH 32
 enum { PRO_PLAIN = 0, PRO_CENTRED_LIFT = 1, PRO_ROUNDDIV_LIFT = 2 };
 enum { EPI_STORE = 0, EPI_ROUNDDIV = 1 };
 
@@ -78,22 +81,25 @@ hipError_t launch_tensor(int log_n, const u64* a, const u64* b, u64* out01,
 // decrypt: m[i] = c0[i] + c1[i] * s[i]   (s: [L+1][N], limb i under prime i)
 hipError_t launch_decrypt(int log_n, const u64* ct, const u64* s, u64* m,
                           int n_limbs, const PrimeDev* primes, hipStream_t st);
-// Galois automorphism in the NTT domain: out[r][n] = in[r][src_g(n)]
-hipError_t launch_automorphism(int log_n, const u64* in, u64* out, int n_rows,
-                               uint64_t g, hipStream_t st);
-// key-switch inner product: u[k][t][n] = sum_j D_{j,t}[n] * key[j][k][kt][n]
-// (keys in Montgomery form), D_{j,t} = (j == t) ? diag[t] : ext[j][t];
-// t < n_dig are data moduli (prime t), t == n_dig is the special prime.
-// gather_g != 1 reads every digit at the Galois source index (hoisting).
+// Galois automorphism in the NTT domain: item b has rows_per_item rows,
+// out[b][r][n] = in[b][r][src_{g_b}(n)]
+struct AutJob {
+  int B, rows_per_item;
+  u64 g[HE_MAX_BATCH];
+};
+hipError_t launch_automorphism(int log_n, const u64* in, u64* out, const AutJob& job, hipStream_t st);
+// key-switch inner product of B items (keys in Montgomery form):
+// u[b][k][t][n] = sum_j D_{b,j,t}[n] * key_b[j][k][kt][n],
+// D_{b,j,t} = (j == t) ? diag[b][t] : ext[b][j][t]; t < n_dig are data moduli
+// (prime t), t == n_dig is the special prime.
 struct InnerJob {
-  const u64* ext;    // [n_dig][n_dig + 1][N]
-  const u64* diag;   // [n_dig][N] (NTT domain digits of the input itself)
-  const u64* key;    // [kd][2][km][N]
-  u64* u;            // [2][n_dig + 1][N]
-  int n_dig;
-  int key_digits, key_mods;  // kd, km of the stored key
-  int special_prime;         // prime index of the special modulus
-  uint64_t gather_g;         // Galois element for hoisted digits, 1 = none
+  const u64* ext;    // [B][n_dig][n_dig + 1][N]
+  const u64* diag;   // item b at diag + b * diag_stride: [n_dig][N] NTT domain
+  long long diag_stride;
+  u64* u;            // [B][2][n_dig + 1][N]
+  int B, n_dig, special_prime;
+  const u64* key[HE_MAX_BATCH];
+  int km[HE_MAX_BATCH];  // moduli stored in each key
 };
 hipError_t launch_inner(int log_n, const InnerJob& job, const PrimeDev* primes,
                         hipStream_t st);

@@ -166,44 +166,48 @@ __global__ void k_decrypt(int n, const u64* __restrict__ ct, const u64* __restri
 }
 
 __global__ void k_automorphism(int log_n, const u64* __restrict__ in, u64* __restrict__ out, long long total,
-                               u64 g) {
+                               AutJob J) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const int n = 1 << log_n;
   const long long row = e >> log_n;
   const int i = (int)(e & (n - 1));
-  out[e] = in[row * n + gal_src(i, log_n, g)];
+  const int b = (int)(row / J.rows_per_item);
+  out[e] = in[row * n + gal_src(i, log_n, J.g[b])];
 }
 
 // key-switch inner product with lazy 128-bit accumulation (8 terms at most
 // per Montgomery reduction: 8 q^2 < q 2^64 for q < 2^60)
 __global__ void k_inner(int log_n, InnerJob J, const PrimeDev* __restrict__ primes) {
   const int n = 1 << log_n;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int nm = J.n_dig + 1;
-  if (e >= (long long)nm * n) return;
-  const int t = (int)(e >> log_n);
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)J.B * nm * n) return;
   const int i = (int)(e & (n - 1));
-  const int kt = t < J.n_dig ? t : J.key_mods - 1;
+  const long long bt = e >> log_n;
+  const int t = (int)(bt % nm), b = (int)(bt / nm);
+  const int km = J.km[b];
+  const int kt = t < J.n_dig ? t : km - 1;
   const PrimeDev P = primes[t < J.n_dig ? t : J.special_prime];
-  const int src = (J.gather_g != 1) ? gal_src(i, log_n, J.gather_g) : i;
-  const size_t kstride_k = (size_t)J.key_mods * n;        // between polys k
-  const size_t kstride_j = 2 * kstride_k;                 // between digits
-  const u64* kp = J.key + (size_t)kt * n + i;
+  const size_t ks_k = (size_t)km * n, ks_j = 2 * ks_k;
+  const u64* kp = J.key[b] + (size_t)kt * n + i;
+  const u64* diag = J.diag + b * J.diag_stride;
+  const u64* ext = J.ext + (size_t)b * J.n_dig * nm * n;
   u64 r0 = 0, r1 = 0;
   for (int j0 = 0; j0 < J.n_dig; j0 += 8) {
     U128 acc0 = {0, 0}, acc1 = {0, 0};
     const int j1 = min(J.n_dig, j0 + 8);
     for (int j = j0; j < j1; j++) {
-      const u64 d = (j == t) ? J.diag[(size_t)t * n + src] : J.ext[((size_t)j * nm + t) * n + src];
-      acc0 = add128(acc0, mul_wide(d, kp[j * kstride_j]));
-      acc1 = add128(acc1, mul_wide(d, kp[j * kstride_j + kstride_k]));
+      const u64 d = (j == t) ? diag[(size_t)t * n + i] : ext[((size_t)j * nm + t) * n + i];
+      acc0 = add128(acc0, mul_wide(d, kp[j * ks_j]));
+      acc1 = add128(acc1, mul_wide(d, kp[j * ks_j + ks_k]));
     }
     r0 = addmod(r0, mont_reduce(acc0, P), P.q);
     r1 = addmod(r1, mont_reduce(acc1, P), P.q);
   }
-  J.u[(size_t)t * n + i] = r0;
-  J.u[((size_t)nm + t) * n + i] = r1;
+  u64* u = J.u + (size_t)b * 2 * nm * n;
+  u[(size_t)t * n + i] = r0;
+  u[((size_t)nm + t) * n + i] = r1;
 }
 
 __global__ void k_keygen_combine(int n, const u64* __restrict__ a, const u64* __restrict__ ee,
@@ -378,14 +382,14 @@ hipError_t launch_decrypt(int log_n, const u64* ct, const u64* s, u64* m, int n_
   return hipGetLastError();
 }
 
-hipError_t launch_automorphism(int log_n, const u64* in, u64* out, int n_rows, uint64_t g, hipStream_t st) {
-  const long long total = (long long)n_rows << log_n;
-  hipLaunchKernelGGL(k_automorphism, grid_for(total), dim3(BLK), 0, st, log_n, in, out, total, (u64)g);
+hipError_t launch_automorphism(int log_n, const u64* in, u64* out, const AutJob& job, hipStream_t st) {
+  const long long total = ((long long)job.B * job.rows_per_item) << log_n;
+  hipLaunchKernelGGL(k_automorphism, grid_for(total), dim3(BLK), 0, st, log_n, in, out, total, job);
   return hipGetLastError();
 }
 
 hipError_t launch_inner(int log_n, const InnerJob& job, const PrimeDev* primes, hipStream_t st) {
-  const long long total = (long long)(job.n_dig + 1) << log_n;
+  const long long total = ((long long)job.B * (job.n_dig + 1)) << log_n;
   hipLaunchKernelGGL(k_inner, grid_for(total), dim3(BLK), 0, st, log_n, job, primes);
   return hipGetLastError();
 }

@@ -43,10 +43,11 @@ __device__ __forceinline__ int gidx(int gi, int c, int lo, int r) {
 
 __device__ __forceinline__ void decode_job(const NttJob& J, int w, int& a, int& b) {
   if (J.skip_diag) {
-    int nb1 = J.nb - 1;
+    const int nb1 = J.nb - 1;
     a = w / nb1;
     b = w - a * nb1;
-    b += (b >= a) ? 1 : 0;
+    const int j = J.amod > 0 ? a % J.amod : a;
+    b += (b >= j) ? 1 : 0;
   } else {
     a = w / J.nb;
     b = w - a * J.nb;
@@ -121,7 +122,7 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
     u64 sq = 0, sh = 0;
     const u64 hq_b = (PRO == PRO_ROUNDDIV_LIFT) ? J.hq[b] : 0;
     if (PRO != PRO_PLAIN) {
-      const int sp = J.src_prime >= 0 ? J.src_prime : J.src_prime_of_a[a];
+      const int sp = J.src_prime >= 0 ? J.src_prime : (J.amod > 0 ? a % J.amod : a);
       sq = primes[sp].q;
       sh = (sq - 1) >> 1;
     }
@@ -159,8 +160,7 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
     u64 inv = 0, inv_sh = 0;
     if (EPI == EPI_ROUNDDIV) {
       uu = J.u + a * J.ua + b * J.ub;
-      ad = (a == 0 ? J.add0 : J.add1);
-      if (ad) ad += b * J.ab;
+      ad = (J.add && !(J.add_even_only && (a & 1))) ? J.add + a * J.aa + b * J.ab : nullptr;
       inv = J.inv[b];
       inv_sh = J.inv_sh[b];
     }

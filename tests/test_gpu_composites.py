@@ -72,6 +72,23 @@ def test_matmul_bit_exact(deep, n_in, n_out):
     assert np.abs(dec[n_out:]).max() < 1e-6
 
 
+def test_conv_plans_in_lock_step(deep):
+    # four convolution plans applied together (batched rotations) give the
+    # oracle's per-channel ciphertexts bit for bit
+    P = deep
+    rng = np.random.default_rng(21)
+    image = rng.uniform(0, 1, (14, 14))
+    v = P.H.he_im2col(image, 4, 2)
+    _keys(P, [36 << j for j in range(4)])
+    g, o = _enc(P, v, 5, 3)
+    Ks = rng.normal(0, 0.1, (4, 16))
+    bs = rng.normal(0, 0.1, 4)
+    plans = [P.H.he_conv_plan(P.g, g, Ks[c], 36, bs[c]) for c in range(4)]
+    outs = P.H.he_plan_apply_many(P.g, plans, g)
+    for c in range(4):
+        P.ct_equal(outs[c], P.o.conv_im2col(o, Ks[c], 36, bs[c]), "channel %d" % c)
+
+
 def test_pack_and_sum_bit_exact(deep):
     P = deep
     half = P.n // 2
@@ -98,9 +115,9 @@ def cnn_fp64(d):
 def run_cnn_gpu(H, g, x, d):
     """The section 5 network through the C ABI (plans built from x)."""
     s = I.CNN_SHAPE
-    parts = []
-    for c in range(s["channels"]):
-        parts.append(H.he_enc_conv_im2col(g, x, d["conv_k"][c], s["windows"], d["conv_b"][c]))
+    plans = [H.he_conv_plan(g, x, d["conv_k"][c], s["windows"], d["conv_b"][c])
+             for c in range(s["channels"])]
+    parts = H.he_plan_apply_many(g, plans, x)
     p = H.he_pack(g, parts, s["windows"])
     s1 = H.he_square(g, p)
     h = H.he_enc_matmul(g, s1, d["w1"], d["b1"])
