@@ -153,6 +153,16 @@ def main():
     logits = H.he_decode(g, H.he_decrypt(g, y), shape["out"])
     logits_err = float(np.abs(logits - cnn_fp64(d, H.he_im2col)).max())
 
+    # host time to enqueue one step (no synchronisation inside the step)
+    H.he_sync(g)
+    enq = []
+    for _ in range(10):
+        t1 = time.perf_counter()
+        step(H, g, net, x, shape["windows"])
+        enq.append((time.perf_counter() - t1) * 1e3)
+        H.he_sync(g)
+    enqueue_ms = float(np.median(enq))
+
     log("latency distribution")
     lat = []
     for _ in range(args.latency_runs):
@@ -178,8 +188,8 @@ def main():
     stage_ms = {k: float(np.median(v_)) for k, v_ in stages.items()}
 
     log("kernel profile (HIP events on the library stream)")
-    fams = ["ntt_fwd", "ntt_inv", "modup", "moddown", "keyswitch_inner", "hoisted_inner",
-            "hoisted_moddown", "pointwise", "rescale", "sample"]
+    fams = ["ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "keyswitch_inner", "hoisted_inner",
+            "hoisted_moddown", "pointwise", "sample"]
     H.he_profile_enable(g, True)
     prof_steps = 5
     for _ in range(prof_steps):
@@ -187,17 +197,17 @@ def main():
     H.he_sync(g)
     prof = {}
     for f in fams:
-        n, ms = H.he_profile_read(g, f)
+        n, ms, units, by = H.he_profile_read(g, f)
         if n:
             prof[f] = {"launches_per_step": n / prof_steps, "ms_per_step": ms / prof_steps,
-                       "avg_launch_us": 1e3 * ms / n}
+                       "avg_launch_us": 1e3 * ms / n, "units_per_launch": units / n,
+                       "bytes_per_launch": by / n}
     H.he_profile_enable(g, False)
-
-    # roofline of the dominant kernel family (largest summed time per step)
     dom = max(prof, key=lambda k: prof[k]["ms_per_step"]) if prof else None
-    roof = None
-    if dom:
-        roof = roofline_entry(dom, prof[dom], g.n)
+    roof = roofline_entry(dom, prof[dom], g.n) if dom else None
+
+    log("kernel bench: batched NTT at N=16384")
+    kbench = kernel_bench(H, torch, I)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -229,8 +239,10 @@ def main():
         "latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "runs": int(len(lat))} if len(lat) else None),
         "stage_ms": stage_ms,
+        "host_enqueue_ms": enqueue_ms,
         "kernel_profile": prof,
         "roofline": roof,
+        "kernel_bench": kbench,
         "cpu_baseline": cpu,
         "bit_exact_repeat": bit_exact_repeat,
         "logits_max_abs_err": logits_err,
@@ -241,20 +253,91 @@ def main():
     print(json.dumps(res), flush=True)
 
 
-# Algorithmic HBM bytes per launch of each kernel family at ring degree n,
-# from the per-unit figures (one limb = 8n bytes) and the units per launch
-# recorded by the profile.  Filled in by roofline_entry.
+# Roofline of a kernel family.  NTT-type kernels (every family that runs the
+# LDS NTT) are bound by integer VALU issue: the work unit is the butterfly,
+# (N/2) log2 N per limb-NTT; the peak is the VALU issue rate (256 CUs x 4
+# SIMD16 x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s) over the
+# minimal VALU instruction count of a 64-bit Shoup butterfly on gfx950
+# (27).  The inner products are bound by HBM (their key reads).
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+BUTTERFLY_INSTR = 27
+NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "hoisted_moddown")
+
+
 def roofline_entry(fam, p, n):
-    limb = 8.0 * n
-    # per launch: a batched NTT reads and writes each limb once
-    units = p.get("limbs_per_launch")
-    if units is None:
-        return {"bound": "alu", "family": fam, "avg_launch_us": p["avg_launch_us"],
-                "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None}
-    bytes_ = 2 * limb * units
-    ach = bytes_ / (p["avg_launch_us"] * 1e-6) / 1e9
-    return {"bound": "hbm", "family": fam, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    t = p["avg_launch_us"] * 1e-6
+    hbm = p["bytes_per_launch"] / t / 1e9
+    traffic = pmc_traffic(fam)
+    if fam in NTT_FAMILIES:
+        bfly = p["units_per_launch"] * (n // 2) * (n.bit_length() - 1)
+        ach = bfly / t / 1e9
+        peak = VALU_LANE_OPS / BUTTERFLY_INSTR / 1e9
+        return {"bound": "alu", "family": fam, "achieved": ach, "peak": peak,
+                "unit": "G butterfly/s", "frac": ach / peak, "traffic": traffic,
+                "hbm_gbs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS,
+                "avg_launch_us": p["avg_launch_us"], "units_per_launch": p["units_per_launch"],
+                "algorithmic_bytes_per_launch": p["bytes_per_launch"]}
+    return {"bound": "hbm", "family": fam, "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": hbm / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_us": p["avg_launch_us"],
+            "algorithmic_bytes_per_launch": p["bytes_per_launch"]}
+
+
+def pmc_traffic(fam):
+    """HBM bytes per launch measured by rocprofv3 PMC counters (FETCH_SIZE,
+    WRITE_SIZE, calibrated by a copy kernel), valid only while the kernel
+    source is unchanged since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2104_03152_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("ntt.hip", "kernels.hip", "modarith.h", "device.h"):
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(f.read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return rec.get("families", {}).get(fam)
+
+
+def kernel_bench(H, torch, I, n_ct=256, reps=5):
+    """Batched forward + inverse NTT over 256 ciphertexts x 2 polys x 8
+    limbs at N = 16384 (4096 limb-NTTs, 512 MiB per pass)."""
+    p = I.RAW
+    g = H.he_ctx_create(p["log_n"], p["bits"], p["scale"], p["seed"], stream=None)
+    n, limbs = g.n, g.L
+    buf = torch.empty((n_ct * 2, limbs, n), dtype=torch.int64, device="cuda")
+    for i in range(limbs):
+        buf[:, i, :] = torch.randint(0, g.primes[i], (n_ct * 2, n), dtype=torch.int64, device="cuda")
+    ref = buf.clone()
+    torch.cuda.synchronize()
+    H.he_ntt_forward(g, buf.data_ptr(), n_ct * 2, limbs)
+    H.he_ntt_inverse(g, buf.data_ptr(), n_ct * 2, limbs)
+    H.he_sync(g)
+    H.he_profile_enable(g, True)
+    for _ in range(reps):
+        H.he_ntt_forward(g, buf.data_ptr(), n_ct * 2, limbs)
+        H.he_ntt_inverse(g, buf.data_ptr(), n_ct * 2, limbs)
+    H.he_sync(g)
+    out = {}
+    for fam in ("ntt_fwd", "ntt_inv"):
+        cnt, ms, units, by = H.he_profile_read(g, fam)
+        t = ms / cnt * 1e-3
+        bfly = units / cnt * (n // 2) * (n.bit_length() - 1)
+        out[fam] = {"limb_ntts_per_launch": units / cnt, "avg_launch_us": t * 1e6,
+                    "limb_ntts_per_s": units / cnt / t, "hbm_gbs": by / cnt / t / 1e9,
+                    "hbm_frac": by / cnt / t / 1e9 / HBM_PEAK_GBS,
+                    "g_butterfly_s": bfly / t / 1e9,
+                    "alu_frac": bfly / t / (VALU_LANE_OPS / BUTTERFLY_INSTR)}
+    H.he_profile_enable(g, False)
+    torch.cuda.synchronize()
+    out["roundtrip_exact"] = bool(torch.equal(buf, ref))
+    out["workload"] = "%d ciphertexts x 2 polys x %d limbs, N=%d, 50-bit primes" % (n_ct, limbs, n)
+    del buf, ref
+    g.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -231,12 +231,13 @@ void he_im2col(const double* img, uint32_t h, uint32_t w, uint32_t k,
 /* ---- kernel timing: HIP events around each launch of a named kernel
  * family while enabled (adds no work to the kernels themselves). ---- */
 he_status he_profile_enable(he_ctx* ctx, int32_t enable);
-/* launches and summed milliseconds of a kernel family since enabling
- * (synchronises).  Families: "ntt_fwd", "ntt_inv", "modup", "moddown",
- * "keyswitch_inner", "hoisted_inner", "hoisted_moddown", "pointwise",
- * "rescale", "sample". */
+/* launches, summed milliseconds, summed work units (limb-NTTs for the NTT
+ * families, items for the inner products) and summed algorithmic HBM bytes
+ * of a kernel family since enabling (synchronises).  Families: "ntt_fwd",
+ * "ntt_inv", "modup", "moddown", "rescale", "keyswitch_inner",
+ * "hoisted_inner", "hoisted_moddown", "pointwise", "sample". */
 he_status he_profile_read(he_ctx* ctx, const char* family, uint64_t* launches,
-                          double* total_ms);
+                          double* total_ms, double* units, double* bytes);
 
 #ifdef __cplusplus
 }

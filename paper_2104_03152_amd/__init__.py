@@ -86,7 +86,7 @@ _SIGS = {
     "he_key_bytes": (C.c_size_t, [_vp]),
     "he_im2col": (None, [_dp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, _dp]),
     "he_profile_enable": (C.c_int32, [_vp, C.c_int32]),
-    "he_profile_read": (C.c_int32, [_vp, C.c_char_p, _u64p, _dp]),
+    "he_profile_read": (C.c_int32, [_vp, C.c_char_p, _u64p, _dp, _dp, _dp]),
 }
 
 _lib = None
@@ -412,7 +412,8 @@ def he_profile_enable(ctx, enable=True):
 
 
 def he_profile_read(ctx, family):
-    n, ms = C.c_uint64(), C.c_double()
-    _chk(lib().he_profile_read(ctx.ptr, family.encode(), C.byref(n), C.byref(ms)),
-         "he_profile_read")
-    return n.value, ms.value
+    """(launches, total ms, work units, algorithmic HBM bytes) of a family"""
+    n, ms, units, by = C.c_uint64(), C.c_double(), C.c_double(), C.c_double()
+    _chk(lib().he_profile_read(ctx.ptr, family.encode(), C.byref(n), C.byref(ms), C.byref(units),
+                               C.byref(by)), "he_profile_read")
+    return n.value, ms.value, units.value, by.value

@@ -153,6 +153,7 @@ struct Key {
 struct ProfRec {
   std::string fam;
   hipEvent_t a, b;
+  double units, bytes;  // limb-NTTs (NTT families) and algorithmic HBM bytes
 };
 
 struct he_ctx {
@@ -178,6 +179,9 @@ struct he_ctx {
   bool prof = false;
   std::vector<ProfRec> prof_recs;
   uint64_t key_epoch = 0;  // bumped whenever a key is (re)generated
+  // divide-and-round constants for divisor prime s and target prime t:
+  // (q_s mod q_t)^-1, its Shoup companion, and (q_s - 1)/2 mod q_t
+  std::vector<u64> rd_inv, rd_inv_sh, rd_hq;
 };
 
 struct he_ct {
@@ -216,7 +220,9 @@ struct Prof {
   const char* fam;
   hipEvent_t a{}, b{};
   bool on;
-  Prof(he_ctx* c_, const char* f) : c(c_), fam(f), on(c_->prof) {
+  double units, bytes;
+  Prof(he_ctx* c_, const char* f, double units_ = 0, double bytes_ = 0)
+      : c(c_), fam(f), on(c_->prof), units(units_), bytes(bytes_) {
     if (on) {
       (void)hipEventCreate(&a);
       (void)hipEventCreate(&b);
@@ -226,7 +232,7 @@ struct Prof {
   ~Prof() {
     if (on) {
       (void)hipEventRecord(b, c->st);
-      c->prof_recs.push_back({fam, a, b});
+      c->prof_recs.push_back({fam, a, b, units, bytes});
     }
   }
 };
@@ -301,7 +307,7 @@ he_status ntt_rows(he_ctx* c, bool fwd, const u64* src, u64* dst, int n_poly, in
   J.db = c->n;
   J.src_prime = 0;
   for (int i = 0; i < n_limbs; i++) J.dst_prime[i] = (unsigned char)i;
-  Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv");
+  Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv", (double)n_poly * n_limbs, 16.0 * c->n * n_poly * n_limbs);
   hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->d_fwd, c->st)
                      : launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "ntt launch: %s", hipGetErrorString(e));
@@ -321,7 +327,7 @@ he_status ntt_rows_mods(he_ctx* c, bool fwd, const u64* src, u64* dst, int n_pol
   J.db = c->n;
   J.src_prime = 0;
   for (int i = 0; i < mods.n; i++) J.dst_prime[i] = mods.p[i];
-  Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv");
+  Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv", (double)n_poly * mods.n, 16.0 * c->n * n_poly * mods.n);
   hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->d_fwd, c->st)
                      : launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "ntt launch: %s", hipGetErrorString(e));
@@ -367,16 +373,17 @@ he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, c
   J.aa = add.aa;
   J.ab = c->n;
   J.add_even_only = add.even_only;
-  const u64 p = c->q[src_prime];
-  J.h_src = (p - 1) / 2;
+  J.h_src = (c->q[src_prime] - 1) / 2;
+  const size_t np = c->q.size();
   for (int t = 0; t < n_t; t++) {
-    const u64 qt = c->q[t];
     J.dst_prime[t] = (unsigned char)t;
-    J.hq[t] = J.h_src % qt;
-    J.inv[t] = h_inv(p % qt, qt);
-    J.inv_sh[t] = h_shoup(J.inv[t], qt);
+    J.hq[t] = c->rd_hq[src_prime * np + t];
+    J.inv[t] = c->rd_inv[src_prime * np + t];
+    J.inv_sh[t] = c->rd_inv_sh[src_prime * np + t];
   }
-  Prof pr(c, fam);
+  // per job: divisor limb, dividend limb, optional addend read; result written
+  const double jobs = (double)n_poly * n_t;
+  Prof pr(c, fam, jobs, 8.0 * c->n * jobs * (add.p ? 4.0 : 3.0));
   hipError_t e = launch_ntt_fwd(c->log_n, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV, J, c->d_primes, c->d_fwd, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "round_div launch: %s", hipGetErrorString(e));
   return HE_OK;
@@ -401,7 +408,7 @@ he_status modup(he_ctx* c, const u64* coef, int B, int Lp, u64* ext) {
   J.src_prime = -1;
   J.amod = Lp;
   for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
-  Prof pr(c, "modup");
+  Prof pr(c, "modup", (double)B * Lp * Lp, 16.0 * n * B * Lp * Lp);
   hipError_t e = launch_ntt_fwd(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, J, c->d_primes, c->d_fwd, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "modup: %s", hipGetErrorString(e));
   return HE_OK;
@@ -437,7 +444,8 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
       I.key[b] = keys[b]->d;
       I.km[b] = keys[b]->ml + 2;
     }
-    Prof pr(c, "keyswitch_inner");
+    // per item: key 2 Lp nm limbs + digits Lp nm limbs read, 2 nm written
+    Prof pr(c, "keyswitch_inner", (double)B, 8.0 * n * B * (3.0 * Lp * nm + 2.0 * nm));
     hipError_t e = launch_inner(c->log_n, I, c->d_primes, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "inner: %s", hipGetErrorString(e));
   }
@@ -450,7 +458,7 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
     J.na = 2 * B;
     J.nb = 1;
     J.dst_prime[0] = (unsigned char)c->L;
-    Prof pr(c, "ntt_inv");
+    Prof pr(c, "ntt_inv", 2.0 * B, 16.0 * n * 2 * B);
     hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "intt special: %s", hipGetErrorString(e));
   }
@@ -503,7 +511,7 @@ he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
     J.na = 2 * n_ct;
     J.nb = 1;
     J.dst_prime[0] = (unsigned char)l;
-    Prof pr(c, "ntt_inv");
+    Prof pr(c, "ntt_inv", 2.0 * n_ct, 16.0 * n * 2 * n_ct);
     hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "rescale intt: %s", hipGetErrorString(e));
   }
@@ -801,6 +809,17 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
     he_ctx_destroy(c);
     return fail(HE_EHIP, "table upload failed");
   }
+  c->rd_inv.assign((size_t)np * np, 0);
+  c->rd_inv_sh.assign((size_t)np * np, 0);
+  c->rd_hq.assign((size_t)np * np, 0);
+  for (int a = 0; a < np; a++)
+    for (int t = 0; t < np; t++) {
+      if (a == t) continue;
+      const size_t i = (size_t)a * np + t;
+      c->rd_inv[i] = h_inv(q[a] % q[t], q[t]);
+      c->rd_inv_sh[i] = h_shoup(c->rd_inv[i], q[t]);
+      c->rd_hq[i] = ((q[a] - 1) / 2) % q[t];
+    }
   encode_tables_init(c->enc, c->log_n);
   *out = c;
   return HE_OK;
@@ -1020,7 +1039,7 @@ static he_status addsub(he_ctx* c, const he_ct* a, const he_ct* b, int op, he_ct
   TRY(align2(c, a, b, &x, &y, gx, gy));
   he_ct* r = nullptr;
   TRY(new_ct(c, x->level, a->scale, &r));
-  Prof pr(c, "pointwise");
+  Prof pr(c, "pointwise", 0, 24.0 * 2 * (x->level + 1) * c->n);
   hipError_t e = launch_addsub(c->log_n, op, x->d, y->d, r->d, 2, mods_range(x->level + 1), c->d_primes, c->st);
   if (e != hipSuccess) {
     he_ct_free(r);
@@ -1424,7 +1443,8 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
       I.t_begin = 0;
       I.t_end = nm;
       I.special_prime = c->L;
-      Prof pr(c, "hoisted_inner");
+      // keys of R items + the shared digits once + R outputs
+      Prof pr(c, "hoisted_inner", (double)R, 8.0 * n * (2.0 * R * Lp * nm + Lp * nm + 2.0 * R * nm));
       hipError_t e = launch_inner_hoisted(c->log_n, I, c->d_primes, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted inner: %s", hipGetErrorString(e));
     }
@@ -1437,7 +1457,7 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
       J.na = 2 * R;
       J.nb = 1;
       J.dst_prime[0] = (unsigned char)c->L;
-      Prof pr(c, "ntt_inv");
+      Prof pr(c, "ntt_inv", 2.0 * R, 16.0 * n * 2 * R);
       hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted intt: %s", hipGetErrorString(e));
     }
@@ -1459,15 +1479,16 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
     M.nm = nm;
     M.chunk = chunk;
     M.special_prime = c->L;
-    const u64 sp = c->q[c->L];
-    M.h_src = (sp - 1) / 2;
+    M.h_src = (c->q[c->L] - 1) / 2;
+    const size_t np = c->q.size();
     for (int t = 0; t < Lp; t++) {
-      const u64 qt = c->q[t];
-      M.hq[t] = M.h_src % qt;
-      M.inv[t] = h_inv(sp % qt, qt);
-      M.inv_sh[t] = h_shoup(M.inv[t], qt);
+      M.hq[t] = c->rd_hq[c->L * np + t];
+      M.inv[t] = c->rd_inv[c->L * np + t];
+      M.inv_sh[t] = c->rd_inv_sh[c->L * np + t];
     }
-    Prof pr(c, "hoisted_moddown");
+    // per (item, poly, limb): special limb, u limb and diagonal read, and the
+    // partial sums written once per chunk
+    Prof pr(c, "hoisted_moddown", 2.0 * R * Lp, 8.0 * n * (3.0 * 2 * R * Lp + 2.0 * n_chunks * Lp));
     hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->d_fwd, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "hoisted moddown: %s", hipGetErrorString(e));
   }
@@ -1732,20 +1753,25 @@ he_status he_profile_enable(he_ctx* c, int32_t enable) {
   return HE_OK;
 }
 
-he_status he_profile_read(he_ctx* c, const char* fam, uint64_t* launches, double* total_ms) {
+he_status he_profile_read(he_ctx* c, const char* fam, uint64_t* launches, double* total_ms, double* units,
+                          double* bytes) {
   if (!c || !fam) return fail(HE_EINVAL, "NULL argument");
   HIPC(hipStreamSynchronize(c->st));
   uint64_t cnt = 0;
-  double ms = 0;
+  double ms = 0, un = 0, by = 0;
   for (auto& r : c->prof_recs) {
     if (r.fam != fam) continue;
     float t = 0;
     HIPC(hipEventElapsedTime(&t, r.a, r.b));
     ms += t;
+    un += r.units;
+    by += r.bytes;
     cnt++;
   }
   if (launches) *launches = cnt;
   if (total_ms) *total_ms = ms;
+  if (units) *units = un;
+  if (bytes) *bytes = by;
   return HE_OK;
 }
 

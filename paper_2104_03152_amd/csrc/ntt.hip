@@ -270,8 +270,9 @@ k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
 
 // Hoisted rotations: ModDown of each item (an NTT of its special-prime limb,
 // lifted) with the plaintext multiply-accumulate of the vector-matrix
-// product in the epilogue.  Workgroup (chunk, k, t) loops over its items,
-// keeping the running sums in registers.
+// product in the epilogue.  Workgroup (chunk, k, t) loops over its items;
+// the running sums live in its own slice of `partial` (each thread re-reads
+// exactly the words it wrote, so no barrier is needed for them).
 template <int LOGN>
 __global__ void __launch_bounds__(Cfg<LOGN>::T)
 k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __restrict__ tw) {
@@ -290,9 +291,7 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
   const ulonglong2* W = reinterpret_cast<const ulonglong2*>(tw) + (size_t)t * N;
   const u64 sq = primes[J.special_prime].q, sh = J.h_src;
   const u64 hq = J.hq[t], inv = J.inv[t], inv_sh = J.inv_sh[t];
-  u64 acc[16];
-#pragma unroll
-  for (int e = 0; e < 16; e++) acc[e] = 0;
+  u64* __restrict__ out = J.partial + (((size_t)chunk * 2 + k) * J.n_dig + t) * N;
   const int rb = chunk * J.chunk, re = min(J.R, rb + J.chunk);
   for (int r = rb; r < re; r++) {
     const HoistItem it = J.items[r];
@@ -308,10 +307,14 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
         x[u * (1 << R0) + c] = submod(red64(v, P), hq, q);
       }
     }
-    fwd_passes<LOGN, 0>(x, lds, W, q, tid);
-    const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
-    const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
-    const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
+    // keep the twiddle loads inside the loop (hoisting them out would hold
+    // every stage's twiddles in registers across items)
+    const ulonglong2* Wr = W;
+    asm volatile("" : "+v"(Wr));
+    fwd_passes<LOGN, 0>(x, lds, Wr, q, tid);
+    // final values through LDS so the epilogue runs in natural order:
+    // coalesced accesses and a bounded number of loads in flight
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < GF; u++) {
       const int gi = tid + C::T * u;
@@ -319,21 +322,24 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
       for (int c = 0; c < (1 << RF); c++) {
         u64 v = x[u * (1 << RF) + c];
         v = v >= q2 ? v - q2 : v;
-        v = v >= q ? v - q : v;
-        const int idx = (gi << RF) | c;
-        u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
-        if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
-        acc[u * (1 << RF) + c] = addmod(acc[u * (1 << RF) + c], mulmod(ks, dg[idx], P), q);
+        lds[pad((gi << RF) | c)] = v >= q ? v - q : v;
       }
     }
     __syncthreads();
-  }
-  u64* __restrict__ out = J.partial + (((size_t)chunk * 2 + k) * J.n_dig + t) * N;
-#pragma unroll
-  for (int u = 0; u < GF; u++) {
-    const int gi = tid + C::T * u;
-#pragma unroll
-    for (int c = 0; c < (1 << RF); c++) out[(gi << RF) | c] = acc[u * (1 << RF) + c];
+    const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
+    const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
+    const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
+    const bool first = (r == rb);
+#pragma unroll 4
+    for (int e = 0; e < 16; e++) {
+      const int idx = tid + C::T * e;
+      const u64 v = lds[pad(idx)];
+      u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+      if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
+      const u64 prod = mulmod(ks, dg[idx], P);
+      out[idx] = first ? prod : addmod(out[idx], prod, q);
+    }
+    __syncthreads();
   }
 }
 
