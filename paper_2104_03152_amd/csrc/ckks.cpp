@@ -353,6 +353,9 @@ struct Addend {
   const u64* p = nullptr;
   long long aa = 0;
   int even_only = 0;
+  const u64* gals = nullptr;   // read p at the Galois source of item a / 2
+  const u64* p2 = nullptr;     // second addend (every poly)
+  long long a2a = 0;
 };
 he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, const u64* u, long long ua,
                     u64* dst, long long da, int n_t, Addend add, const char* fam) {
@@ -373,6 +376,12 @@ he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, c
   J.aa = add.aa;
   J.ab = c->n;
   J.add_even_only = add.even_only;
+  J.add2 = add.p2;
+  J.a2a = add.a2a;
+  if (add.gals) {
+    J.add_gather = 1;
+    for (int a = 0; a < (n_poly + 1) / 2 && a < HE_MAX_BATCH; a++) J.gal[a] = add.gals[a];
+  }
   J.h_src = (c->q[src_prime] - 1) / 2;
   const size_t np = c->q.size();
   for (int t = 0; t < n_t; t++) {
@@ -416,9 +425,11 @@ he_status modup(he_ctx* c, const u64* coef, int B, int Lp, u64* ext) {
 
 // ---------------------------------------------------------------- key switching
 // Key switch of B polynomials at level l: item b's input d + b*ds (NTT domain
-// [l+1][N]) with keys[b]; out [B][2][l+1][N] = KeySwitch(d_b) + addend.
-he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const Key* const* keys, Addend add,
-                     u64* out) {
+// [l+1][N]), read at the Galois source of gals[b] when gals is given (the
+// rotated poly without materialising it), with keys[b];
+// out [B][2][l+1][N] = KeySwitch(d_b) + addends.
+he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const Key* const* keys,
+                     const u64* gals, Addend add, u64* out) {
   const int n = c->n, Lp = l + 1, nm = Lp + 1;
   if (B < 1 || B > HE_MAX_BATCH) return fail(HE_EINVAL, "key-switch batch of %d", B);
   for (int b = 0; b < B; b++)
@@ -429,7 +440,26 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
   TRY(dalloc(c, ext, (size_t)B * Lp * nm * n));
   TRY(dalloc(c, u, (size_t)B * 2 * nm * n));
   TRY(dalloc(c, ucoef, (size_t)B * 2 * n));
-  TRY(ntt_rows(c, false, d, coef.p, B, Lp, ds, (long long)Lp * n));
+  {  // coefficient form of (the rotation of) each input
+    NttJob J{};
+    J.src = d;
+    J.dst = coef.p;
+    J.na = B;
+    J.nb = Lp;
+    J.sa = ds;
+    J.sb = n;
+    J.da = (long long)Lp * n;
+    J.db = n;
+    for (int i = 0; i < Lp; i++) J.dst_prime[i] = (unsigned char)i;
+    if (gals) {
+      J.gather_src = 1;
+      J.gal_div = 1;
+      for (int b = 0; b < B; b++) J.gal[b] = gals[b];
+    }
+    Prof pr(c, "ntt_inv", (double)B * Lp, 16.0 * n * B * Lp);
+    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "intt: %s", hipGetErrorString(e));
+  }
   TRY(modup(c, coef.p, B, Lp, ext.p));
   {
     InnerJob I{};
@@ -443,6 +473,7 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
     for (int b = 0; b < B; b++) {
       I.key[b] = keys[b]->d;
       I.km[b] = keys[b]->ml + 2;
+      I.gal[b] = gals ? gals[b] : 1;
     }
     // per item: key 2 Lp nm limbs + digits Lp nm limbs read, 2 nm written
     Prof pr(c, "keyswitch_inner", (double)B, 8.0 * n * B * (3.0 * Lp * nm + 2.0 * nm));
@@ -466,34 +497,31 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
 }
 
 // Left rotations of B ciphertexts stored contiguously ([B][2][l+1][N] at in)
-// by steps[b]: tau_g on both polys, then one batched key switch of the
-// rotated poly 1 with tau_g(c0) as addend.  out: [B][2][l+1][N].
-he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps, u64* out) {
+// by steps[b]: the key switch reads tau_g(c1) by gather and adds tau_g(c0)
+// (gathered) in its last kernel; with add_in, also adds the input itself
+// (x + rot(x), the rotate-and-sum step).  out: [B][2][l+1][N].
+he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps, u64* out, bool add_in = false) {
   const int n = c->n, Lp = l + 1;
   const Key* keys[HE_MAX_BATCH];
-  AutJob A{};
-  A.B = B;
-  A.rows_per_item = 2 * Lp;
+  u64 gals[HE_MAX_BATCH];
   for (int b = 0; b < B; b++) {
     auto it = c->gal.find(steps[b]);
     if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", steps[b]);
     if (it->second.ml < l)
       return fail(HE_ENOKEY, "Galois key for step %d cut at level %d, ciphertext at %d", steps[b], it->second.ml, l);
     keys[b] = &it->second;
-    A.g[b] = galois_elt(c, steps[b]);
-  }
-  DBuf tr;
-  TRY(dalloc(c, tr, (size_t)B * 2 * Lp * n));
-  {
-    Prof pr(c, "pointwise");
-    hipError_t e = launch_automorphism(c->log_n, in, tr.p, A, c->st);
-    if (e != hipSuccess) return fail(HE_EHIP, "automorphism: %s", hipGetErrorString(e));
+    gals[b] = galois_elt(c, steps[b]);
   }
   Addend add;
-  add.p = tr.p;
+  add.p = in;
   add.aa = (long long)Lp * n;
   add.even_only = 1;
-  return key_switch(c, B, tr.p + (size_t)Lp * n, 2LL * Lp * n, l, keys, add, out);
+  add.gals = gals;
+  if (add_in) {
+    add.p2 = in;
+    add.a2a = (long long)Lp * n;
+  }
+  return key_switch(c, B, in + (size_t)Lp * n, 2LL * Lp * n, l, keys, gals, add, out);
 }
 
 // rescale of n_ct contiguous ciphertexts [n_ct][2][l+1][N] -> [n_ct][2][l][N]
@@ -1155,7 +1183,7 @@ static he_status mul_relin_raw(he_ctx* c, const he_ct* a, const he_ct* b, he_ct*
     Addend add;
     add.p = r->d;
     add.aa = (long long)Lp * n;
-    s = key_switch(c, 1, d2.p, 0, l, &kp, add, r->d);
+    s = key_switch(c, 1, d2.p, 0, l, &kp, nullptr, add, r->d);
   }
   if (s != HE_OK) {
     he_ct_free(r);
@@ -1203,17 +1231,26 @@ he_status he_rotate(he_ctx* c, const he_ct* a, int32_t step, he_ct** out) {
   return rotate_raw(c, a, step, out);
 }
 
-// x <- x + rot(x, stride 2^j), j < ceil(log2 count)
+// x <- x + rot(x, stride 2^j), j < ceil(log2 count); each step is one fused
+// rotate-and-add
 static he_status rotate_and_sum(he_ctx* c, he_ct* x, uint32_t count, uint32_t stride, he_ct** out) {
   int steps = 0;
   while ((1u << steps) < count) steps++;
   for (int j = 0; j < steps; j++) {
-    he_ct *r = nullptr, *y = nullptr;
-    he_status s = rotate_raw(c, x, (int)(stride << j), &r);
-    if (s == HE_OK) s = he_add(c, x, r, &y);
-    he_ct_free(r);
+    he_ct* y = nullptr;
+    const int st = norm_step(c, (long long)stride << j);
+    he_status s = HE_OK;
+    if (st == 0) {
+      s = he_add(c, x, x, &y);
+    } else {
+      s = new_ct(c, x->level, x->scale, &y);
+      if (s == HE_OK) s = rotate_multi(c, x->d, 1, x->level, &st, y->d, true);
+    }
     he_ct_free(x);
-    if (s != HE_OK) return s;
+    if (s != HE_OK) {
+      he_ct_free(y);
+      return s;
+    }
     x = y;
   }
   *out = x;
@@ -1359,10 +1396,8 @@ static he_status conv_apply_many(he_ctx* c, const he_plan* const* plans, int nb,
       if (e != hipSuccess) return fail(HE_EHIP, "add: %s", hipGetErrorString(e));
       continue;
     }
-    TRY(rotate_multi(c, Y.p, nb, l - 1, st.data(), R.p));
-    Prof pr(c, "pointwise");
-    hipError_t e = launch_addsub(c->log_n, 0, Y.p, R.p, Y.p, 2 * nb, mods_range(l), c->d_primes, c->st);
-    if (e != hipSuccess) return fail(HE_EHIP, "add: %s", hipGetErrorString(e));
+    TRY(rotate_multi(c, Y.p, nb, l - 1, st.data(), R.p, true));
+    std::swap(Y.p, R.p);
   }
   for (int b = 0; b < nb; b++) {
     if (!scales_match(scale, plans[b]->bias->scale)) return fail(HE_ESCALE, "bias scale");
@@ -1508,10 +1543,18 @@ static he_status matmul_apply(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out
   TRY(drop_copy(c, x, x->level, &gxr.p));
   uint32_t reps = 1;
   while ((uint64_t)p->n_in * reps * 2 <= half) {
-    he_ct *r = nullptr, *y = nullptr;
-    TRY(rotate_raw(c, gxr.p, (int)((half - p->n_in * reps) % half), &r));
-    CtGuard gr{r};
-    TRY(he_add(c, gxr.p, r, &y));
+    const int st = norm_step(c, (long long)half - (long long)p->n_in * reps);
+    he_ct* y = nullptr;
+    if (st == 0) {
+      TRY(he_add(c, gxr.p, gxr.p, &y));
+    } else {
+      TRY(new_ct(c, gxr.p->level, gxr.p->scale, &y));
+      he_status s = rotate_multi(c, gxr.p->d, 1, gxr.p->level, &st, y->d, true);
+      if (s != HE_OK) {
+        he_ct_free(y);
+        return s;
+      }
+    }
     he_ct_free(gxr.p);
     gxr.p = y;
     reps *= 2;

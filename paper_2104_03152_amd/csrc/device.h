@@ -29,8 +29,15 @@ struct NttJob {
   const u64* add;
   long long aa, ab;
   int add_even_only;
+  int add_gather;      // the addend is read at the Galois source of item a / 2
+  const u64* add2;     // second addend add2[a*a2a + b*ab] (every a), nullable
+  long long a2a;
   u64 h_src;
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
+  // inverse transforms: read the source at the Galois source index of item
+  // a / gal_div (gather_src set), i.e. transform tau_g(src) directly
+  int gather_src, gal_div;
+  u64 gal[32];
 };
 
 #define HE_MAX_BATCH 32
@@ -94,8 +101,9 @@ hipError_t launch_automorphism(int log_n, const u64* in, u64* out, const AutJob&
 // (prime t), t == n_dig is the special prime.
 struct InnerJob {
   const u64* ext;    // [B][n_dig][n_dig + 1][N]
-  const u64* diag;   // item b at diag + b * diag_stride: [n_dig][N] NTT domain
-  long long diag_stride;
+  const u64* diag;   // item b at diag + b * diag_stride: [n_dig][N] NTT domain,
+  long long diag_stride;  // read at the Galois source of gal[b] (1: none)
+  u64 gal[HE_MAX_BATCH];
   u64* u;            // [B][2][n_dig + 1][N]
   int B, n_dig, special_prime;
   const u64* key[HE_MAX_BATCH];

@@ -193,12 +193,13 @@ __global__ void k_inner(int log_n, InnerJob J, const PrimeDev* __restrict__ prim
   const u64* kp = J.key[b] + (size_t)kt * n + i;
   const u64* diag = J.diag + b * J.diag_stride;
   const u64* ext = J.ext + (size_t)b * J.n_dig * nm * n;
+  const int di = J.gal[b] != 1 ? gal_src(i, log_n, J.gal[b]) : i;
   u64 r0 = 0, r1 = 0;
   for (int j0 = 0; j0 < J.n_dig; j0 += 8) {
     U128 acc0 = {0, 0}, acc1 = {0, 0};
     const int j1 = min(J.n_dig, j0 + 8);
     for (int j = j0; j < j1; j++) {
-      const u64 d = (j == t) ? diag[(size_t)t * n + i] : ext[((size_t)j * nm + t) * n + i];
+      const u64 d = (j == t) ? diag[(size_t)t * n + di] : ext[((size_t)j * nm + t) * n + i];
       acc0 = add128(acc0, mul_wide(d, kp[j * ks_j]));
       acc1 = add128(acc1, mul_wide(d, kp[j * ks_j + ks_k]));
     }

@@ -38,14 +38,14 @@ __device__ __forceinline__ U128 mul_wide(u64 a, u64 b) {
   return r;
 }
 
+// high word of a 64x64 product as a chain of 32x32+64 multiply-adds
+// (v_mad_u64_u32): the partial carries ride in the 64-bit addend.
 __device__ __forceinline__ u64 mulhi64(u64 a, u64 b) {
-  u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
-  u64 p00 = (u64)a0 * b0;
-  u64 p01 = (u64)a0 * b1;
-  u64 p10 = (u64)a1 * b0;
-  u64 p11 = (u64)a1 * b1;
-  u64 mid = (p00 >> 32) + (u64)(u32)p01 + (u64)(u32)p10;
-  return p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+  const u64 t = (u64)a0 * b0;
+  const u64 x = (u64)a1 * b0 + (t >> 32);
+  const u64 y = (u64)a0 * b1 + (u32)x;
+  return (u64)a1 * b1 + (x >> 32) + (y >> 32);
 }
 
 __device__ __forceinline__ U128 add128(U128 a, U128 b) {

@@ -157,10 +157,14 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
     const u64 q2 = q << 1;
     const u64* __restrict__ uu = nullptr;
     const u64* __restrict__ ad = nullptr;
+    const u64* __restrict__ ad2 = nullptr;
+    u64 ag = 1;
     u64 inv = 0, inv_sh = 0;
     if (EPI == EPI_ROUNDDIV) {
       uu = J.u + a * J.ua + b * J.ub;
       ad = (J.add && !(J.add_even_only && (a & 1))) ? J.add + a * J.aa + b * J.ab : nullptr;
+      ad2 = J.add2 ? J.add2 + a * J.a2a + b * J.ab : nullptr;
+      ag = J.add_gather ? J.gal[a >> 1] : 1;
       inv = J.inv[b];
       inv_sh = J.inv_sh[b];
     }
@@ -175,7 +179,8 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
         const int idx = (gi << R) | c;
         if (EPI == EPI_ROUNDDIV) {
           v = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
-          if (ad) v = addmod(v, ad[idx], q);
+          if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
+          if (ad2) v = addmod(v, ad2[idx], q);
         }
         dst[idx] = v;
       }
@@ -231,7 +236,7 @@ __device__ __forceinline__ void inv_passes(u64 (&x)[16], u64* lds, const ulonglo
   }
 }
 
-template <int LOGN>
+template <int LOGN, bool GATHER>
 __global__ void __launch_bounds__(Cfg<LOGN>::T)
 k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __restrict__ tw) {
   using C = Cfg<LOGN>;
@@ -248,11 +253,15 @@ k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
   u64 x[16];
   {
     constexpr int R = C::bits(0), G = 16 >> R;  // bits [0, R): contiguous runs
+    const u64 g = GATHER ? J.gal[a / J.gal_div] : 1;
 #pragma unroll
     for (int u = 0; u < G; u++) {
       const int gi = tid + C::T * u;
 #pragma unroll
-      for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = src[(gi << R) | c];
+      for (int c = 0; c < (1 << R); c++) {
+        const int idx = (gi << R) | c;
+        x[u * (1 << R) + c] = src[GATHER ? gal_src(idx, LOGN, g) : idx];
+      }
     }
   }
   inv_passes<LOGN, 0>(x, lds, W, q, tid);
@@ -380,21 +389,26 @@ hipError_t fwd_launch(const NttJob& J, const PrimeDev* primes, const u64* tw, hi
   return hipGetLastError();
 }
 
-template <int LOGN>
+template <int LOGN, bool GATHER>
 hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const u64* tw, hipStream_t st) {
   using C = Cfg<LOGN>;
   const size_t shm = sizeof(u64) * C::lds_words();
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ntt_inv<LOGN>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_ntt_inv<LOGN, GATHER>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     attr = true;
   }
   const int jobs = n_jobs(J);
   if (jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ntt_inv<LOGN>), dim3(jobs), dim3(C::T), shm, st, J, primes, tw);
+  hipLaunchKernelGGL((k_ntt_inv<LOGN, GATHER>), dim3(jobs), dim3(C::T), shm, st, J, primes, tw);
   return hipGetLastError();
+}
+
+template <int LOGN>
+hipError_t inv_dispatch(const NttJob& J, const PrimeDev* primes, const u64* tw, hipStream_t st) {
+  return J.gather_src ? inv_launch<LOGN, true>(J, primes, tw, st) : inv_launch<LOGN, false>(J, primes, tw, st);
 }
 
 template <int LOGN>
@@ -425,11 +439,11 @@ hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job, const 
 hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes, const u64* inv_tw,
                           hipStream_t st) {
   switch (log_n) {
-    case 10: return inv_launch<10>(job, primes, inv_tw, st);
-    case 11: return inv_launch<11>(job, primes, inv_tw, st);
-    case 12: return inv_launch<12>(job, primes, inv_tw, st);
-    case 13: return inv_launch<13>(job, primes, inv_tw, st);
-    case 14: return inv_launch<14>(job, primes, inv_tw, st);
+    case 10: return inv_dispatch<10>(job, primes, inv_tw, st);
+    case 11: return inv_dispatch<11>(job, primes, inv_tw, st);
+    case 12: return inv_dispatch<12>(job, primes, inv_tw, st);
+    case 13: return inv_dispatch<13>(job, primes, inv_tw, st);
+    case 14: return inv_dispatch<14>(job, primes, inv_tw, st);
     default: return hipErrorInvalidValue;
   }
 }
