@@ -1342,7 +1342,9 @@ he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t
       }
     }
   }
-  p->diags = (u64*)c->pool.get(words * sizeof(u64));
+  // device buffer: [n_in][Lp][N] diagonals (NTT domain), then their Shoup
+  // companions floor(d 2^64 / q) for the fused multiply-accumulate
+  p->diags = (u64*)c->pool.get(2 * words * sizeof(u64));
   he_status s = p->diags ? HE_OK : fail(HE_EOOM, "diagonal allocation failed");
   if (s == HE_OK) {
     hipError_t e = hipMemcpyAsync(p->diags, h.data(), words * sizeof(u64), hipMemcpyHostToDevice, c->st);
@@ -1350,6 +1352,21 @@ he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t
     if (e != hipSuccess) s = fail(HE_EHIP, "diagonal upload: %s", hipGetErrorString(e));
   }
   if (s == HE_OK) s = ntt_rows(c, true, p->diags, p->diags, (int)n_in, Lp, (long long)Lp * n, (long long)Lp * n);
+  if (s == HE_OK) {
+    hipError_t e = hipMemcpyAsync(h.data(), p->diags, words * sizeof(u64), hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) s = fail(HE_EHIP, "diagonal download: %s", hipGetErrorString(e));
+  }
+  if (s == HE_OK) {
+    for (uint32_t i = 0; i < n_in; i++)
+      for (int t = 0; t < Lp; t++) {
+        u64* row = h.data() + ((size_t)i * Lp + t) * n;
+        for (int k = 0; k < n; k++) row[k] = h_shoup(row[k], c->q[t]);
+      }
+    hipError_t e = hipMemcpyAsync(p->diags + words, h.data(), words * sizeof(u64), hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) s = fail(HE_EHIP, "diagonal upload: %s", hipGetErrorString(e));
+  }
   if (s == HE_OK) {
     const double post = like->scale * c->scale / (double)c->q[like->level];
     std::vector<double> b(n_out, 0.0);
@@ -1507,6 +1524,7 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
     M.u = u.p;
     M.c0 = x->d;
     M.diags = p->diags;
+    M.diags_sh = p->diags + (size_t)p->n_in * Lp * n;
     M.items = p->items;
     M.partial = partial.p;
     M.R = R;

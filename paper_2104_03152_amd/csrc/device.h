@@ -156,7 +156,8 @@ struct HoistMac {
   const u64* ucoef;  // [R][2][N] special-prime limb of u, coefficient form
   const u64* u;      // [R][2][nm][N]
   const u64* c0;     // [n_dig][N] poly 0 of the input (NTT domain)
-  const u64* diags;  // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
+  const u64* diags;     // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
+  const u64* diags_sh;  // their Shoup companions, same layout
   const HoistItem* items;
   u64* partial;      // [n_chunks][2][n_dig][N]
   int R, n_dig, nm, chunk, special_prime;

@@ -283,7 +283,7 @@ k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
 // the running sums live in its own slice of `partial` (each thread re-reads
 // exactly the words it wrote, so no barrier is needed for them).
 template <int LOGN>
-__global__ void __launch_bounds__(Cfg<LOGN>::T)
+__global__ void __launch_bounds__(Cfg<LOGN>::T, (LOGN <= 13 ? 4 : 1))
 k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __restrict__ tw) {
   using C = Cfg<LOGN>;
   constexpr int N = C::N;
@@ -337,6 +337,7 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
     __syncthreads();
     const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
     const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
+    const u64* __restrict__ dgs = J.diags_sh + ((size_t)it.diag * J.n_dig + t) * N;
     const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
     const bool first = (r == rb);
 #pragma unroll 4
@@ -345,7 +346,7 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
       const u64 v = lds[pad(idx)];
       u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
       if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
-      const u64 prod = mulmod(ks, dg[idx], P);
+      const u64 prod = shoup(ks, dg[idx], dgs[idx], q);
       out[idx] = first ? prod : addmod(out[idx], prod, q);
     }
     __syncthreads();
