@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -169,6 +170,9 @@ struct he_ctx {
   PrimeDev* d_primes = nullptr;
   u64* d_fwd = nullptr;
   u64* d_inv = nullptr;
+  u64* d_fwd_fp = nullptr;
+  u64* d_inv_fp = nullptr;
+  NttTables tabs{};
   bool have_keys = false;
   u64* d_s = nullptr;   // [L+1][N]
   u64* d_pk = nullptr;  // [2][L][N]
@@ -308,8 +312,8 @@ he_status ntt_rows(he_ctx* c, bool fwd, const u64* src, u64* dst, int n_poly, in
   J.src_prime = 0;
   for (int i = 0; i < n_limbs; i++) J.dst_prime[i] = (unsigned char)i;
   Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv", (double)n_poly * n_limbs, 16.0 * c->n * n_poly * n_limbs);
-  hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->d_fwd, c->st)
-                     : launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+  hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->tabs, c->st)
+                     : launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "ntt launch: %s", hipGetErrorString(e));
   return HE_OK;
 }
@@ -328,8 +332,8 @@ he_status ntt_rows_mods(he_ctx* c, bool fwd, const u64* src, u64* dst, int n_pol
   J.src_prime = 0;
   for (int i = 0; i < mods.n; i++) J.dst_prime[i] = mods.p[i];
   Prof pr(c, fwd ? "ntt_fwd" : "ntt_inv", (double)n_poly * mods.n, 16.0 * c->n * n_poly * mods.n);
-  hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->d_fwd, c->st)
-                     : launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+  hipError_t e = fwd ? launch_ntt_fwd(c->log_n, PRO_PLAIN, EPI_STORE, J, c->d_primes, c->tabs, c->st)
+                     : launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "ntt launch: %s", hipGetErrorString(e));
   return HE_OK;
 }
@@ -393,7 +397,7 @@ he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, c
   // per job: divisor limb, dividend limb, optional addend read; result written
   const double jobs = (double)n_poly * n_t;
   Prof pr(c, fam, jobs, 8.0 * c->n * jobs * (add.p ? 4.0 : 3.0));
-  hipError_t e = launch_ntt_fwd(c->log_n, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV, J, c->d_primes, c->d_fwd, c->st);
+  hipError_t e = launch_ntt_fwd(c->log_n, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV, J, c->d_primes, c->tabs, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "round_div launch: %s", hipGetErrorString(e));
   return HE_OK;
 }
@@ -418,7 +422,7 @@ he_status modup(he_ctx* c, const u64* coef, int B, int Lp, u64* ext) {
   J.amod = Lp;
   for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
   Prof pr(c, "modup", (double)B * Lp * Lp, 16.0 * n * B * Lp * Lp);
-  hipError_t e = launch_ntt_fwd(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, J, c->d_primes, c->d_fwd, c->st);
+  hipError_t e = launch_ntt_fwd(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, J, c->d_primes, c->tabs, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "modup: %s", hipGetErrorString(e));
   return HE_OK;
 }
@@ -457,7 +461,7 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
       for (int b = 0; b < B; b++) J.gal[b] = gals[b];
     }
     Prof pr(c, "ntt_inv", (double)B * Lp, 16.0 * n * B * Lp);
-    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "intt: %s", hipGetErrorString(e));
   }
   TRY(modup(c, coef.p, B, Lp, ext.p));
@@ -490,7 +494,7 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
     J.nb = 1;
     J.dst_prime[0] = (unsigned char)c->L;
     Prof pr(c, "ntt_inv", 2.0 * B, 16.0 * n * 2 * B);
-    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "intt special: %s", hipGetErrorString(e));
   }
   return round_div(c, 2 * B, ucoef.p, c->L, u.p, (long long)nm * n, out, (long long)Lp * n, Lp, add, "moddown");
@@ -540,7 +544,7 @@ he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
     J.nb = 1;
     J.dst_prime[0] = (unsigned char)l;
     Prof pr(c, "ntt_inv", 2.0 * n_ct, 16.0 * n * 2 * n_ct);
-    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+    hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "rescale intt: %s", hipGetErrorString(e));
   }
   return round_div(c, 2 * n_ct, coef.p, l, in, (long long)(l + 1) * n, out, (long long)l * n, l, Addend(),
@@ -785,6 +789,7 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
   const int np = (int)q.size();
   std::vector<PrimeDev> hp(np);
   std::vector<u64> fwd((size_t)np * n * 2), inv((size_t)np * n * 2);
+  std::vector<double> fwd_fp((size_t)np * n * 2), inv_fp((size_t)np * n * 2);
   for (int i = 0; i < np; i++) {
     const u64 qi = q[i];
     PrimeDev& d = hp[i];
@@ -799,6 +804,12 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
     d.r2 = h_mulm(r64, r64, qi);
     d.ninv = h_inv((u64)n % qi, qi);
     d.ninv_sh = h_shoup(d.ninv, qi);
+    // exact FP64 butterflies need every intermediate below 2^53: q < 2^50
+    d.use_fp = qi < (1ull << 50) ? 1 : 0;
+    d.qd = (double)qi;
+    d.inv2qd = 1.0 / (2.0 * (double)qi);
+    d.ninv_d = (double)d.ninv;
+    d.ninv_qd = (double)d.ninv / (double)qi;
     // primitive 2N-th root of unity
     u64 psi = 0;
     for (u64 g = 2;; g++) {
@@ -822,21 +833,42 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
       fwd[o + 1] = h_shoup(pw[r], qi);
       inv[o] = ipw[r];
       inv[o + 1] = h_shoup(ipw[r], qi);
+      fwd_fp[o] = (double)pw[r];
+      fwd_fp[o + 1] = (double)pw[r] / (double)qi;
+      inv_fp[o] = (double)ipw[r];
+      inv_fp[o + 1] = (double)ipw[r] / (double)qi;
     }
   }
   c->d_primes = (PrimeDev*)c->pool.get(sizeof(PrimeDev) * np);
   c->d_fwd = (u64*)c->pool.get(fwd.size() * sizeof(u64));
   c->d_inv = (u64*)c->pool.get(inv.size() * sizeof(u64));
-  if (!c->d_primes || !c->d_fwd || !c->d_inv) {
+  c->d_fwd_fp = (u64*)c->pool.get(fwd_fp.size() * sizeof(double));
+  c->d_inv_fp = (u64*)c->pool.get(inv_fp.size() * sizeof(double));
+  if (!c->d_primes || !c->d_fwd || !c->d_inv || !c->d_fwd_fp || !c->d_inv_fp) {
     he_ctx_destroy(c);
     return fail(HE_EOOM, "table allocation failed");
   }
   if (hipMemcpy(c->d_primes, hp.data(), sizeof(PrimeDev) * np, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_fwd, fwd.data(), fwd.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_inv, inv.data(), inv.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c->d_inv, inv.data(), inv.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_fwd_fp, fwd_fp.data(), fwd_fp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_inv_fp, inv_fp.data(), inv_fp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     he_ctx_destroy(c);
     return fail(HE_EHIP, "table upload failed");
   }
+  // two-phase transforms for launches of up to split_jobs limbs (a few
+  // ciphertexts), scratch for exactly that many
+  int split_jobs = 256;
+  if (const char* env = getenv("HE_NTT_SPLIT_JOBS")) split_jobs = atoi(env);
+  u64* tmp = nullptr;
+  if (split_jobs > 0) {
+    tmp = (u64*)c->pool.get((size_t)split_jobs * n * sizeof(u64));
+    if (!tmp) {
+      he_ctx_destroy(c);
+      return fail(HE_EOOM, "scratch allocation failed");
+    }
+  }
+  c->tabs = NttTables{c->d_fwd, c->d_inv, c->d_fwd_fp, c->d_inv_fp, tmp, (long long)split_jobs * n, split_jobs};
   c->rd_inv.assign((size_t)np * np, 0);
   c->rd_inv_sh.assign((size_t)np * np, 0);
   c->rd_hq.assign((size_t)np * np, 0);
@@ -1510,7 +1542,7 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
       J.nb = 1;
       J.dst_prime[0] = (unsigned char)c->L;
       Prof pr(c, "ntt_inv", 2.0 * R, 16.0 * n * 2 * R);
-      hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->d_inv, c->st);
+      hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted intt: %s", hipGetErrorString(e));
     }
     // chunks of rotations so that chunks x 2 x Lp workgroups fill the chip
@@ -1542,7 +1574,7 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
     // per (item, poly, limb): special limb, u limb and diagonal read, and the
     // partial sums written once per chunk
     Prof pr(c, "hoisted_moddown", 2.0 * R * Lp, 8.0 * n * (3.0 * 2 * R * Lp + 2.0 * n_chunks * Lp));
-    hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->d_fwd, c->st);
+    hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "hoisted moddown: %s", hipGetErrorString(e));
   }
   {

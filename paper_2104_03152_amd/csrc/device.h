@@ -46,10 +46,24 @@ enum { EPI_STORE = 0, EPI_ROUNDDIV = 1 };
 
 // forward (lazy Cooley-Tukey, bit-reversed output) and inverse (Gentleman-
 // Sande, bit-reversed input, times N^-1) batched negacyclic NTT
+// Twiddle tables, N entries per prime: (w, floor(w 2^64 / q)) pairs for the
+// integer butterflies and (w, w / q) double pairs for the FP64 ones.  A
+// launch of at most split_jobs transforms runs in two phases (each limb
+// spread over several workgroups) through tmp, tmp_words words of device
+// scratch owned by the context; all launches are ordered on one stream.
+struct NttTables {
+  const u64* fwd;
+  const u64* inv;
+  const u64* fwd_fp;
+  const u64* inv_fp;
+  u64* tmp;
+  long long tmp_words;
+  int split_jobs;
+};
 hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job,
-                          const PrimeDev* primes, const u64* fwd_tw, hipStream_t st);
+                          const PrimeDev* primes, const NttTables& tabs, hipStream_t st);
 hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes,
-                          const u64* inv_tw, hipStream_t st);
+                          const NttTables& tabs, hipStream_t st);
 
 // ---- samplers (ChaCha20 streams) ----
 // signed small polynomial (ternary: kind 0, Gaussian CDT: kind 1) reduced into
@@ -165,7 +179,7 @@ struct HoistMac {
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
 };
 hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const PrimeDev* primes,
-                                      const u64* fwd_tw, hipStream_t st);
+                                      const NttTables& tabs, hipStream_t st);
 // out[k][t] = x[k][t] * diag0[t] + sum_c partial[c][k][t]
 hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const u64* x,
                              const u64* diag0, u64* out, int n_dig, const PrimeDev* primes,

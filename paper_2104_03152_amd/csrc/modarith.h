@@ -18,23 +18,24 @@ struct PrimeDev {
   u64 r2;        // 2^128 mod q (into Montgomery form)
   u64 ninv, ninv_sh;  // N^-1 mod q and its Shoup companion
   u32 k;         // bit length of q
-  u32 pad;
+  u32 use_fp;    // q < 2^50: the NTT runs in exact FP64 arithmetic
+  double qd, inv2qd;  // q and 1/(2q) as doubles
+  double ninv_d, ninv_qd;  // N^-1 mod q and N^-1 / q as doubles
 };
 
 struct U128 {
   u64 lo, hi;
 };
 
+// full 64x64 -> 128 product as a chain of 32x32+64 multiply-adds
 __device__ __forceinline__ U128 mul_wide(u64 a, u64 b) {
-  u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
-  u64 p00 = (u64)a0 * b0;
-  u64 p01 = (u64)a0 * b1;
-  u64 p10 = (u64)a1 * b0;
-  u64 p11 = (u64)a1 * b1;
-  u64 mid = (p00 >> 32) + (u64)(u32)p01 + (u64)(u32)p10;
+  const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+  const u64 t = (u64)a0 * b0;
+  const u64 x = (u64)a1 * b0 + (t >> 32);
+  const u64 y = (u64)a0 * b1 + (u32)x;
   U128 r;
-  r.lo = (mid << 32) | (u32)p00;
-  r.hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  r.lo = (y << 32) | (u32)t;
+  r.hi = (u64)a1 * b1 + (x >> 32) + (y >> 32);
   return r;
 }
 

@@ -3,13 +3,23 @@
 // One workgroup transforms one limb of N = 2^LOGN words entirely in LDS.
 // Each thread holds 16 words; the LOGN butterfly stages are split into
 // ceil(LOGN/4) register passes of radix 2^3 or 2^4, separated by LDS
-// exchanges (padded by one word every 16 to spread banks).  Butterflies are
-// Harvey's lazy ones with Shoup twiddles: forward values stay in [0, 4q),
-// inverse values in [0, 2q), one reduction at the end.
+// exchanges (padded by one word every 16 to spread banks).
 //
 // Forward: Cooley-Tukey with twiddles psi^brv(k), output in bit-reversed
 // order: slot i holds a(psi^(2 brv(i) + 1)).  Inverse: Gentleman-Sande with
 // psi^-brv(k), then N^-1.
+//
+// Two butterfly arithmetics, chosen per workgroup by the limb's prime:
+//  - integer (any prime below 2^61): Harvey's lazy butterflies with Shoup
+//    twiddles; forward values stay in [0, 4q), inverse values in [0, 2q);
+//  - FP64 (primes below 2^50): residues are integer-valued doubles.  y w mod
+//    q is the exact two-product h + l (one FMA) less qt q, qt the floor of
+//    y (w/q), which is within one of the true quotient while |y w / q| <
+//    2^52; the result lies in (-q, 2q).  Sums are folded back to [-1, 2q+1]
+//    by x - 2q floor(x / 2q).  Every intermediate is an integer below 2^53
+//    in magnitude, so the arithmetic is exact, and a butterfly is eleven
+//    full-rate FP64 operations against about twice that many 32-bit integer
+//    operations for the Shoup one.
 //
 // The prologue can lift a digit while loading (centred representative of a
 // residue mod another prime: key-switch ModUp) or form r = [x + h]_p (the
@@ -54,69 +64,248 @@ __device__ __forceinline__ void decode_job(const NttJob& J, int w, int& a, int& 
   }
 }
 
+// ---------------- butterfly arithmetics ----------------
+struct IntAr {
+  typedef u64 T;
+  typedef ulonglong2 TW;  // (w, floor(w 2^64 / q))
+  u64 q, q2;
+  __device__ explicit IntAr(const PrimeDev& P) : q(P.q), q2(P.q << 1) {}
+  // inputs in [0, 4q): X reduced to [0, 2q), outputs in [0, 4q)
+  __device__ __forceinline__ void fwd(T& X, T& Y, const TW w) const {
+    const u64 x = X >= q2 ? X - q2 : X;
+    const u64 v = shoup_lazy(Y, w.x, w.y, q);
+    X = x + v;
+    Y = x - v + q2;
+  }
+  // inputs and outputs in [0, 2q)
+  __device__ __forceinline__ void inv(T& X, T& Y, const TW w) const {
+    const u64 s = X + Y;
+    const u64 d = X - Y + q2;
+    X = s >= q2 ? s - q2 : s;
+    Y = shoup_lazy(d, w.x, w.y, q);
+  }
+  __device__ __forceinline__ T from_res(u64 v) const { return v; }
+  __device__ __forceinline__ u64 fwd_res(T v) const {
+    v = v >= q2 ? v - q2 : v;
+    return v >= q ? v - q : v;
+  }
+  __device__ __forceinline__ u64 inv_res(T v, const PrimeDev& P) const { return shoup(v, P.ninv, P.ninv_sh, q); }
+  static __device__ __forceinline__ u64 bits(T v) { return v; }
+  static __device__ __forceinline__ T unbits(u64 b) { return b; }
+};
+
+struct FpAr {
+  typedef double T;
+  typedef double2 TW;  // (w, w / q)
+  double q, q2, inv2q;
+  long long qi;
+  __device__ explicit FpAr(const PrimeDev& P) : q(P.qd), q2(2.0 * P.qd), inv2q(P.inv2qd), qi((long long)P.q) {}
+  // y w mod q in (-q, 2q) for |y w / q| < 2^52, 0 <= w < q < 2^50
+  __device__ __forceinline__ double mul(double y, double w, double wq) const {
+#pragma clang fp contract(off)
+    const double h = y * w;
+    const double l = __builtin_fma(y, w, -h);
+    const double qt = __builtin_floor(y * wq);
+    return __builtin_fma(-qt, q, h) + l;
+  }
+  // x - 2q floor(x / 2q), in [-1, 2q + 1] for |x| < 2^52
+  __device__ __forceinline__ double fold(double x) const {
+#pragma clang fp contract(off)
+    return __builtin_fma(-__builtin_floor(x * inv2q), q2, x);
+  }
+  // inputs in (-2q - 1, 4q + 1); X folded first, outputs in the same range
+  __device__ __forceinline__ void fwd(T& X, T& Y, const TW w) const {
+#pragma clang fp contract(off)
+    const double x = fold(X);
+    const double v = mul(Y, w.x, w.y);
+    X = x + v;
+    Y = x - v;
+  }
+  // inputs in (-q, 2q + 1]; outputs: X in [-1, 2q + 1], Y in (-q, 2q)
+  __device__ __forceinline__ void inv(T& X, T& Y, const TW w) const {
+#pragma clang fp contract(off)
+    const double a = X + Y, b = X - Y;
+    X = fold(a);
+    Y = mul(b, w.x, w.y);
+  }
+  __device__ __forceinline__ T from_res(u64 v) const { return (double)(long long)v; }
+  // an integer-valued double in [-q, 3q) -> [0, q)
+  __device__ __forceinline__ u64 to_res(double v) const {
+    long long t = (long long)v;
+    t += t < 0 ? qi : 0;
+    t -= t >= qi ? qi : 0;
+    t -= t >= qi ? qi : 0;
+    return (u64)t;
+  }
+  __device__ __forceinline__ u64 fwd_res(T v) const { return to_res(fold(v)); }
+  __device__ __forceinline__ u64 inv_res(T v, const PrimeDev& P) const { return to_res(mul(v, P.ninv_d, P.ninv_qd)); }
+  static __device__ __forceinline__ u64 bits(T v) { return (u64)__double_as_longlong(v); }
+  static __device__ __forceinline__ T unbits(u64 b) { return __longlong_as_double((long long)b); }
+};
+
+// ---------------- pass schedules ----------------
+// A workgroup holds a local array of 2^LOGM words, 16 per thread, and runs
+// the butterfly stages of local bits [BLO, BHI) in register passes of at
+// most 4 bits with LDS exchanges between them.  A forward pass goes from the
+// top bit down, an inverse pass from the bottom bit up.  The twiddle of the
+// stage on local bit lb at local element l is psi^brv at index
+// 2^(LOGS - 1 - lb) + ((toff + l) >> (lb + 1)), where LOGS and toff place
+// the local array in the limb (LOGS = LOGN, toff = the workgroup's first
+// element, for contiguous blocks; LOGS = LOGM, toff = 0, for columns).
+template <int LOGM, int BLO, int BHI, int LOGE = 4>
+struct Sched {
+  static constexpr int M = 1 << LOGM;
+  static constexpr int E = 1 << LOGE;  // words per thread
+  static constexpr int T = M / E;
+  static constexpr int NB = BHI - BLO;
+  static constexpr int NP = (NB + LOGE - 1) / LOGE;
+  static constexpr int bits(int p) { return NB / NP + (p < NB % NP ? 1 : 0); }
+  static constexpr int consumed(int p) {
+    int s = 0;
+    for (int i = 0; i < p; i++) s += bits(i);
+    return s;
+  }
+  static constexpr int flo(int p) { return BHI - consumed(p + 1); }  // forward pass p: bits [flo, flo + bits)
+  static constexpr int ilo(int p) { return BLO + consumed(p); }      // inverse pass p
+  static constexpr int lds_words() { return M + (M >> 4); }
+};
+
+template <class S, int LO, int R, int LO2, int R2, class Ar>
+__device__ __forceinline__ void exchange(typename Ar::T (&x)[S::E], u64* lds, int tid) {
+  constexpr int G = S::E >> R, G2 = S::E >> R2;
+#pragma unroll
+  for (int u = 0; u < G; u++)
+#pragma unroll
+    for (int c = 0; c < (1 << R); c++) lds[pad(gidx(tid + S::T * u, c, LO, R))] = Ar::bits(x[u * (1 << R) + c]);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < G2; u++)
+#pragma unroll
+    for (int c = 0; c < (1 << R2); c++)
+      x[u * (1 << R2) + c] = Ar::unbits(lds[pad(gidx(tid + S::T * u, c, LO2, R2))]);
+}
+
 // ---------------- forward passes ----------------
-template <int LOGN, int P>
-__device__ __forceinline__ void fwd_passes(u64 (&x)[16], u64* lds, const ulonglong2* __restrict__ W,
-                                           u64 q, int tid) {
-  using C = Cfg<LOGN>;
-  constexpr int R = C::bits(P);
-  constexpr int LO = LOGN - C::consumed(P + 1);
-  constexpr int G = 16 >> R;
-  const u64 q2 = q << 1;
+// Twiddles of one pass for one thread, loaded ahead of the butterflies.
+// Stage pb of a pass of R bits uses 2^(R-1-pb) twiddles per group, kept
+// at heap positions 2^(R-1-pb) - 1 + j.
+template <class S, int LOGS, int P, bool FWD, class Ar>
+struct PassTw {
+  static constexpr int R = S::bits(P);
+  static constexpr int G = S::E >> R;
+  static constexpr int PER = (1 << R) - 1;
+  static constexpr int LO = FWD ? S::flo(P) : S::ilo(P);
+  typename Ar::TW t[G * PER];
+  __device__ __forceinline__ void load(const typename Ar::TW* __restrict__ W, int tid, int toff) {
+#pragma unroll
+    for (int pb = 0; pb < R; pb++) {
+      const int lb = LO + pb;
+      const int base = (1 << (LOGS - 1 - lb)) + (toff >> (lb + 1));
+#pragma unroll
+      for (int u = 0; u < G; u++) {
+        const int gi = tid + S::T * u;
+#pragma unroll
+        for (int j = 0; j < (1 << (R - 1 - pb)); j++)
+          t[u * PER + (1 << (R - 1 - pb)) - 1 + j] = W[base + (((gi >> LO) << (R - 1 - pb)) | j)];
+      }
+    }
+  }
+};
+
+// Butterflies of pass P.  With PRE, the twiddles come from `tw` and the next
+// pass's are loaded before this pass's butterflies, so their latency
+// overlaps arithmetic and the exchange (one-wave workgroups have no other
+// waves to hide it); otherwise each stage loads its own.
+template <class S, int LOGS, int P, class Ar, bool PRE>
+__device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, const typename Ar::TW* __restrict__ W,
+                                           const Ar& ar, int tid, int toff,
+                                           const PassTw<S, LOGS, P, true, Ar>* tw = nullptr) {
+  constexpr int R = S::bits(P);
+  constexpr int LO = S::flo(P);
+  constexpr int G = S::E >> R;
+  constexpr int PER = (1 << R) - 1;
+  constexpr bool MORE = P + 1 < S::NP;
+  PassTw<S, LOGS, (MORE ? P + 1 : P), true, Ar> nxt;
+  if (PRE && MORE) nxt.load(W, tid, toff);
 #pragma unroll
   for (int r = 0; r < R; r++) {
     const int pb = R - 1 - r;
-    const int s = LOGN - 1 - (LO + pb);
+    const int lb = LO + pb;
+    const int base = (1 << (LOGS - 1 - lb)) + (toff >> (lb + 1));
 #pragma unroll
     for (int u = 0; u < G; u++) {
-      const int gi = tid + C::T * u;
+      const int gi = tid + S::T * u;
 #pragma unroll
       for (int c = 0; c < (1 << R); c++) {
         if (c & (1 << pb)) continue;
         const int i0 = u * (1 << R) + c, i1 = i0 + (1 << pb);
-        const int ti = (1 << s) + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
-        const ulonglong2 w = W[ti];
-        u64 X = x[i0];
-        X = X >= q2 ? X - q2 : X;
-        const u64 V = shoup_lazy(x[i1], w.x, w.y, q);
-        x[i0] = X + V;
-        x[i1] = X - V + q2;
+        if constexpr (PRE) {
+          ar.fwd(x[i0], x[i1], tw->t[u * PER + (1 << (R - 1 - pb)) - 1 + (c >> (pb + 1))]);
+        } else {
+          const int ti = base + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
+          ar.fwd(x[i0], x[i1], W[ti]);
+        }
       }
     }
   }
-  if constexpr (P + 1 < C::NP) {
-    constexpr int R2 = C::bits(P + 1);
-    constexpr int LO2 = LOGN - C::consumed(P + 2);
-    constexpr int G2 = 16 >> R2;
+  if constexpr (MORE) {
     if (P > 0) __syncthreads();
-#pragma unroll
-    for (int u = 0; u < G; u++)
-#pragma unroll
-      for (int c = 0; c < (1 << R); c++) lds[pad(gidx(tid + C::T * u, c, LO, R))] = x[u * (1 << R) + c];
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < G2; u++)
-#pragma unroll
-      for (int c = 0; c < (1 << R2); c++) x[u * (1 << R2) + c] = lds[pad(gidx(tid + C::T * u, c, LO2, R2))];
-    fwd_passes<LOGN, P + 1>(x, lds, W, q, tid);
+    exchange<S, LO, R, S::flo(P + 1), S::bits(P + 1), Ar>(x, lds, tid);
+    fwd_passes<S, LOGS, P + 1, Ar, PRE>(x, lds, W, ar, tid, toff, &nxt);
   }
 }
 
-template <int LOGN, int PRO, int EPI>
-__global__ void __launch_bounds__(Cfg<LOGN>::T)
-k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __restrict__ tw) {
+// ---------------- inverse passes ----------------
+template <class S, int LOGS, int P, class Ar, bool PRE>
+__device__ __forceinline__ void inv_passes(typename Ar::T (&x)[S::E], u64* lds, const typename Ar::TW* __restrict__ W,
+                                           const Ar& ar, int tid, int toff,
+                                           const PassTw<S, LOGS, P, false, Ar>* tw = nullptr) {
+  constexpr int R = S::bits(P);
+  constexpr int LO = S::ilo(P);
+  constexpr int G = S::E >> R;
+  constexpr int PER = (1 << R) - 1;
+  constexpr bool MORE = P + 1 < S::NP;
+  PassTw<S, LOGS, (MORE ? P + 1 : P), false, Ar> nxt;
+  if (PRE && MORE) nxt.load(W, tid, toff);
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    const int pb = r;
+    const int lb = LO + pb;
+    const int base = (1 << (LOGS - 1 - lb)) + (toff >> (lb + 1));
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) {
+        if (c & (1 << pb)) continue;
+        const int i0 = u * (1 << R) + c, i1 = i0 + (1 << pb);
+        if constexpr (PRE) {
+          ar.inv(x[i0], x[i1], tw->t[u * PER + (1 << (R - 1 - pb)) - 1 + (c >> (pb + 1))]);
+        } else {
+          const int ti = base + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
+          ar.inv(x[i0], x[i1], W[ti]);
+        }
+      }
+    }
+  }
+  if constexpr (MORE) {
+    if (P > 0) __syncthreads();
+    exchange<S, LO, R, S::ilo(P + 1), S::bits(P + 1), Ar>(x, lds, tid);
+    inv_passes<S, LOGS, P + 1, Ar, PRE>(x, lds, W, ar, tid, toff, &nxt);
+  }
+}
+
+// ---------------- forward kernel ----------------
+template <int LOGN, int PRO, int EPI, class Ar>
+__device__ __forceinline__ void fwd_body(const NttJob& J, const PrimeDev* __restrict__ primes,
+                                         const typename Ar::TW* __restrict__ W, const PrimeDev& P, int a, int b,
+                                         u64* lds) {
   using C = Cfg<LOGN>;
-  constexpr int N = C::N;
-  extern __shared__ u64 lds[];
+  const Ar ar(P);
   const int tid = threadIdx.x;
-  int a, b;
-  decode_job(J, blockIdx.x, a, b);
-  const int dp = J.dst_prime[b];
-  const PrimeDev P = primes[dp];
   const u64 q = P.q;
-  const ulonglong2* W = reinterpret_cast<const ulonglong2*>(tw) + (size_t)dp * N;
   const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
-  u64 x[16];
+  typename Ar::T x[16];
   {
     constexpr int R = C::bits(0), LO = LOGN - R, G = 16 >> R;
     u64 sq = 0, sh = 0;
@@ -146,15 +335,14 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
           v = v >= sq ? v - sq : v;
           v = submod(red64(v, P), hq_b, q);
         }
-        x[u * (1 << R) + c] = v;
+        x[u * (1 << R) + c] = ar.from_res(v);
       }
     }
   }
-  fwd_passes<LOGN, 0>(x, lds, W, q, tid);
+  fwd_passes<Sched<LOGN, 0, LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
   {
     constexpr int R = C::bits(C::NP - 1), G = 16 >> R;
     u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
-    const u64 q2 = q << 1;
     const u64* __restrict__ uu = nullptr;
     const u64* __restrict__ ad = nullptr;
     const u64* __restrict__ ad2 = nullptr;
@@ -173,9 +361,7 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
       const int gi = tid + C::T * u;
 #pragma unroll
       for (int c = 0; c < (1 << R); c++) {
-        u64 v = x[u * (1 << R) + c];
-        v = v >= q2 ? v - q2 : v;
-        v = v >= q ? v - q : v;
+        u64 v = ar.fwd_res(x[u * (1 << R) + c]);
         const int idx = (gi << R) | c;
         if (EPI == EPI_ROUNDDIV) {
           v = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
@@ -188,69 +374,32 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
   }
 }
 
-// ---------------- inverse passes ----------------
-template <int LOGN, int P>
-__device__ __forceinline__ void inv_passes(u64 (&x)[16], u64* lds, const ulonglong2* __restrict__ W,
-                                           u64 q, int tid) {
-  using C = Cfg<LOGN>;
-  constexpr int R = C::bits(P);
-  constexpr int LO = C::consumed(P);
-  constexpr int G = 16 >> R;
-  const u64 q2 = q << 1;
-#pragma unroll
-  for (int r = 0; r < R; r++) {
-    const int pb = r;
-    const int m_log = LOGN - 1 - (LO + pb);
-#pragma unroll
-    for (int u = 0; u < G; u++) {
-      const int gi = tid + C::T * u;
-#pragma unroll
-      for (int c = 0; c < (1 << R); c++) {
-        if (c & (1 << pb)) continue;
-        const int i0 = u * (1 << R) + c, i1 = i0 + (1 << pb);
-        const int ti = (1 << m_log) + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
-        const ulonglong2 w = W[ti];
-        const u64 X = x[i0], Y = x[i1];
-        u64 S = X + Y;
-        S = S >= q2 ? S - q2 : S;
-        x[i0] = S;
-        x[i1] = shoup_lazy(X - Y + q2, w.x, w.y, q);
-      }
-    }
-  }
-  if constexpr (P + 1 < C::NP) {
-    constexpr int R2 = C::bits(P + 1);
-    constexpr int LO2 = C::consumed(P + 1);
-    constexpr int G2 = 16 >> R2;
-    if (P > 0) __syncthreads();
-#pragma unroll
-    for (int u = 0; u < G; u++)
-#pragma unroll
-      for (int c = 0; c < (1 << R); c++) lds[pad(gidx(tid + C::T * u, c, LO, R))] = x[u * (1 << R) + c];
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < G2; u++)
-#pragma unroll
-      for (int c = 0; c < (1 << R2); c++) x[u * (1 << R2) + c] = lds[pad(gidx(tid + C::T * u, c, LO2, R2))];
-    inv_passes<LOGN, P + 1>(x, lds, W, q, tid);
-  }
-}
-
-template <int LOGN, bool GATHER>
+template <int LOGN, int PRO, int EPI>
 __global__ void __launch_bounds__(Cfg<LOGN>::T)
-k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __restrict__ tw) {
-  using C = Cfg<LOGN>;
-  constexpr int N = C::N;
+k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = Cfg<LOGN>::N;
   extern __shared__ u64 lds[];
-  const int tid = threadIdx.x;
   int a, b;
   decode_job(J, blockIdx.x, a, b);
   const int dp = J.dst_prime[b];
   const PrimeDev P = primes[dp];
-  const u64 q = P.q;
-  const ulonglong2* W = reinterpret_cast<const ulonglong2*>(tw) + (size_t)dp * N;
+  if (P.use_fp)
+    fwd_body<LOGN, PRO, EPI, FpAr>(J, primes, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)dp * N, P, a,
+                                   b, lds);
+  else
+    fwd_body<LOGN, PRO, EPI, IntAr>(J, primes, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)dp * N, P, a,
+                                    b, lds);
+}
+
+// ---------------- inverse kernel ----------------
+template <int LOGN, bool GATHER, class Ar>
+__device__ __forceinline__ void inv_body(const NttJob& J, const typename Ar::TW* __restrict__ W, const PrimeDev& P,
+                                         int a, int b, u64* lds) {
+  using C = Cfg<LOGN>;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
   const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
-  u64 x[16];
+  typename Ar::T x[16];
   {
     constexpr int R = C::bits(0), G = 16 >> R;  // bits [0, R): contiguous runs
     const u64 g = GATHER ? J.gal[a / J.gal_div] : 1;
@@ -260,11 +409,11 @@ k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
 #pragma unroll
       for (int c = 0; c < (1 << R); c++) {
         const int idx = (gi << R) | c;
-        x[u * (1 << R) + c] = src[GATHER ? gal_src(idx, LOGN, g) : idx];
+        x[u * (1 << R) + c] = ar.from_res(src[GATHER ? gal_src(idx, LOGN, g) : idx]);
       }
     }
   }
-  inv_passes<LOGN, 0>(x, lds, W, q, tid);
+  inv_passes<Sched<LOGN, 0, LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
   {
     constexpr int R = C::bits(C::NP - 1), LO = LOGN - R, G = 16 >> R;
     u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
@@ -272,32 +421,324 @@ k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const u64* __rest
     for (int u = 0; u < G; u++) {
       const int gi = tid + C::T * u;
 #pragma unroll
-      for (int c = 0; c < (1 << R); c++) dst[(c << LO) | gi] = shoup(x[u * (1 << R) + c], P.ninv, P.ninv_sh, q);
+      for (int c = 0; c < (1 << R); c++) dst[(c << LO) | gi] = ar.inv_res(x[u * (1 << R) + c], P);
     }
   }
 }
 
-// Hoisted rotations: ModDown of each item (an NTT of its special-prime limb,
-// lifted) with the plaintext multiply-accumulate of the vector-matrix
-// product in the epilogue.  Workgroup (chunk, k, t) loops over its items;
-// the running sums live in its own slice of `partial` (each thread re-reads
-// exactly the words it wrote, so no barrier is needed for them).
+template <int LOGN, bool GATHER>
+__global__ void __launch_bounds__(Cfg<LOGN>::T)
+k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = Cfg<LOGN>::N;
+  extern __shared__ u64 lds[];
+  int a, b;
+  decode_job(J, blockIdx.x, a, b);
+  const int dp = J.dst_prime[b];
+  const PrimeDev P = primes[dp];
+  if (P.use_fp)
+    inv_body<LOGN, GATHER, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)dp * N, P, a, b, lds);
+  else
+    inv_body<LOGN, GATHER, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)dp * N, P, a, b, lds);
+}
+
+// ---------------- two-phase transforms for small batches ----------------
+// The limb is viewed as 2^A rows of 2^K columns (K = ceil(LOGN / 2)): the
+// first A forward stages only mix elements of one column (stride 2^K), the
+// last K stages only elements of one contiguous block of 2^K; the inverse
+// runs the same split in the other order.  Each phase spreads a limb over
+// several workgroups of one or two waves, so that a launch of a few limbs
+// still occupies many compute units; the intermediate values (lazy, in the
+// limb's own arithmetic) pass through a scratch buffer of N words per job.
+#ifndef HE_SPLIT_LOGE
+#define HE_SPLIT_LOGE 2
+#endif
 template <int LOGN>
-__global__ void __launch_bounds__(Cfg<LOGN>::T, (LOGN <= 13 ? 4 : 1))
-k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __restrict__ tw) {
+struct Split {
+  static constexpr int K = (LOGN + 1) / 2;                     // block bits
+  static constexpr int A = LOGN - K;                           // row bits
+  static constexpr int LOGMA = (A + 4 < LOGN) ? A + 4 : LOGN;  // 16 columns per workgroup
+  static constexpr int LOGC = LOGMA - A;
+  static constexpr int LOGMB = (10 < LOGN) ? 10 : LOGN;
+  using SA = Sched<LOGMA, LOGC, LOGMA, HE_SPLIT_LOGE>;  // column phase over the row bits
+  using SB = Sched<LOGMB, 0, K, HE_SPLIT_LOGE>;          // block phase over the low bits
+  static constexpr int WA = 1 << (LOGN - LOGMA);  // workgroups per limb
+  static constexpr int WB = 1 << (LOGN - LOGMB);
+};
+
+// limb index of local element l of column workgroup sub
+template <int LOGN>
+__device__ __forceinline__ int col_g(int l, int sub) {
+  using Sp = Split<LOGN>;
+  return ((l >> Sp::LOGC) << Sp::K) | (sub << Sp::LOGC) | (l & ((1 << Sp::LOGC) - 1));
+}
+
+template <int LOGN, int PRO, class Ar>
+__device__ __forceinline__ void fwd_a_body(const NttJob& J, const PrimeDev* __restrict__ primes,
+                                           const typename Ar::TW* __restrict__ W, const PrimeDev& P, int w, int a,
+                                           int b, int sub, u64* __restrict__ tmp, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const u64 q = P.q;
+  const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
+  typename Ar::T x[S::E];
+  PassTw<S, Sp::LOGMA, 0, true, Ar> tw0;
+  tw0.load(W, tid, 0);
+  {
+    constexpr int R = S::bits(0), LO = S::flo(0), G = S::E >> R;
+    u64 sq = 0, sh = 0;
+    const u64 hq_b = (PRO == PRO_ROUNDDIV_LIFT) ? J.hq[b] : 0;
+    if (PRO != PRO_PLAIN) {
+      const int sp = J.src_prime >= 0 ? J.src_prime : (J.amod > 0 ? a % J.amod : a);
+      sq = primes[sp].q;
+      sh = (sq - 1) >> 1;
+    }
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) {
+        u64 v = src[col_g<LOGN>(gidx(gi, c, LO, R), sub)];
+        if (PRO == PRO_CENTRED_LIFT) {
+          if (v > sh) {
+            const u64 r = red64(sq - v, P);
+            v = r ? q - r : 0;
+          } else {
+            v = red64(v, P);
+          }
+        } else if (PRO == PRO_ROUNDDIV_LIFT) {
+          v += sh;
+          v = v >= sq ? v - sq : v;
+          v = submod(red64(v, P), hq_b, q);
+        }
+        x[u * (1 << R) + c] = ar.from_res(v);
+      }
+    }
+  }
+  fwd_passes<S, Sp::LOGMA, 0, Ar, true>(x, lds, W, ar, tid, 0, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::flo(S::NP - 1), G = S::E >> R;
+    u64* __restrict__ t = tmp + (size_t)w * (1 << LOGN);
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) t[col_g<LOGN>(gidx(gi, c, LO, R), sub)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
+template <int LOGN, int EPI, class Ar>
+__device__ __forceinline__ void fwd_b_body(const NttJob& J, const typename Ar::TW* __restrict__ W, const PrimeDev& P,
+                                           int w, int a, int b, int sub, const u64* __restrict__ tmp, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const u64 q = P.q;
+  const int toff = sub << Sp::LOGMB;
+  const u64* __restrict__ t = tmp + (size_t)w * (1 << LOGN) + toff;
+  typename Ar::T x[S::E];
+  PassTw<S, LOGN, 0, true, Ar> tw0;
+  tw0.load(W, tid, toff);
+  {
+    constexpr int R = S::bits(0), LO = S::flo(0), G = S::E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = Ar::unbits(t[gidx(gi, c, LO, R)]);
+    }
+  }
+  fwd_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), G = S::E >> R;
+    u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
+    const u64* __restrict__ uu = nullptr;
+    const u64* __restrict__ ad = nullptr;
+    const u64* __restrict__ ad2 = nullptr;
+    u64 ag = 1;
+    u64 inv = 0, inv_sh = 0;
+    if (EPI == EPI_ROUNDDIV) {
+      uu = J.u + a * J.ua + b * J.ub;
+      ad = (J.add && !(J.add_even_only && (a & 1))) ? J.add + a * J.aa + b * J.ab : nullptr;
+      ad2 = J.add2 ? J.add2 + a * J.a2a + b * J.ab : nullptr;
+      ag = J.add_gather ? J.gal[a >> 1] : 1;
+      inv = J.inv[b];
+      inv_sh = J.inv_sh[b];
+    }
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) {
+        u64 v = ar.fwd_res(x[u * (1 << R) + c]);
+        const int idx = toff + ((gi << R) | c);
+        if (EPI == EPI_ROUNDDIV) {
+          v = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+          if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
+          if (ad2) v = addmod(v, ad2[idx], q);
+        }
+        dst[idx] = v;
+      }
+    }
+  }
+}
+
+template <int LOGN, bool GATHER, class Ar>
+__device__ __forceinline__ void inv_1_body(const NttJob& J, const typename Ar::TW* __restrict__ W, const PrimeDev& P,
+                                           int w, int a, int b, int sub, u64* __restrict__ tmp, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const int toff = sub << Sp::LOGMB;
+  const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
+  typename Ar::T x[S::E];
+  PassTw<S, LOGN, 0, false, Ar> tw0;
+  tw0.load(W, tid, toff);
+  {
+    constexpr int R = S::bits(0), G = S::E >> R;
+    const u64 g = GATHER ? J.gal[a / J.gal_div] : 1;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) {
+        const int idx = toff + ((gi << R) | c);
+        x[u * (1 << R) + c] = ar.from_res(src[GATHER ? gal_src(idx, LOGN, g) : idx]);
+      }
+    }
+  }
+  inv_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = S::E >> R;
+    u64* __restrict__ t = tmp + (size_t)w * (1 << LOGN) + toff;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) t[gidx(gi, c, LO, R)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
+template <int LOGN, class Ar>
+__device__ __forceinline__ void inv_2_body(const NttJob& J, const typename Ar::TW* __restrict__ W, const PrimeDev& P,
+                                           int w, int a, int b, int sub, const u64* __restrict__ tmp, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const u64* __restrict__ t = tmp + (size_t)w * (1 << LOGN);
+  typename Ar::T x[S::E];
+  PassTw<S, Sp::LOGMA, 0, false, Ar> tw0;
+  tw0.load(W, tid, 0);
+  {
+    constexpr int R = S::bits(0), LO = S::ilo(0), G = S::E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = Ar::unbits(t[col_g<LOGN>(gidx(gi, c, LO, R), sub)]);
+    }
+  }
+  inv_passes<S, Sp::LOGMA, 0, Ar, true>(x, lds, W, ar, tid, 0, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = S::E >> R;
+    u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++)
+        dst[col_g<LOGN>(gidx(gi, c, LO, R), sub)] = ar.inv_res(x[u * (1 << R) + c], P);
+    }
+  }
+}
+
+#define HE_PHASE_PRELUDE(WPL)                          \
+  constexpr int N = 1 << LOGN;                         \
+  const int w = blockIdx.x / (WPL);                    \
+  const int sub = blockIdx.x - w * (WPL);              \
+  int a, b;                                            \
+  decode_job(J, w, a, b);                              \
+  const int dp = J.dst_prime[b];                       \
+  const PrimeDev P = primes[dp];                       \
+  const double2* Wf = reinterpret_cast<const double2*>(tabs_fp) + (size_t)dp * N;                 \
+  const ulonglong2* Wi = reinterpret_cast<const ulonglong2*>(tabs_int) + (size_t)dp * N;
+
+template <int LOGN, int PRO>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_ntt_fwd_a(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  __shared__ u64 lds[Split<LOGN>::SA::lds_words()];
+  const u64* tabs_fp = tabs.fwd_fp;
+  const u64* tabs_int = tabs.fwd;
+  HE_PHASE_PRELUDE(Split<LOGN>::WA)
+  if (P.use_fp)
+    fwd_a_body<LOGN, PRO, FpAr>(J, primes, Wf, P, w, a, b, sub, tabs.tmp, lds);
+  else
+    fwd_a_body<LOGN, PRO, IntAr>(J, primes, Wi, P, w, a, b, sub, tabs.tmp, lds);
+}
+
+template <int LOGN, int EPI>
+__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+k_ntt_fwd_b(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
+  const u64* tabs_fp = tabs.fwd_fp;
+  const u64* tabs_int = tabs.fwd;
+  HE_PHASE_PRELUDE(Split<LOGN>::WB)
+  if (P.use_fp)
+    fwd_b_body<LOGN, EPI, FpAr>(J, Wf, P, w, a, b, sub, tabs.tmp, lds);
+  else
+    fwd_b_body<LOGN, EPI, IntAr>(J, Wi, P, w, a, b, sub, tabs.tmp, lds);
+}
+
+template <int LOGN, bool GATHER>
+__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+k_ntt_inv_1(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
+  const u64* tabs_fp = tabs.inv_fp;
+  const u64* tabs_int = tabs.inv;
+  HE_PHASE_PRELUDE(Split<LOGN>::WB)
+  if (P.use_fp)
+    inv_1_body<LOGN, GATHER, FpAr>(J, Wf, P, w, a, b, sub, tabs.tmp, lds);
+  else
+    inv_1_body<LOGN, GATHER, IntAr>(J, Wi, P, w, a, b, sub, tabs.tmp, lds);
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_ntt_inv_2(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  __shared__ u64 lds[Split<LOGN>::SA::lds_words()];
+  const u64* tabs_fp = tabs.inv_fp;
+  const u64* tabs_int = tabs.inv;
+  HE_PHASE_PRELUDE(Split<LOGN>::WA)
+  if (P.use_fp)
+    inv_2_body<LOGN, FpAr>(J, Wf, P, w, a, b, sub, tabs.tmp, lds);
+  else
+    inv_2_body<LOGN, IntAr>(J, Wi, P, w, a, b, sub, tabs.tmp, lds);
+}
+#undef HE_PHASE_PRELUDE
+
+// ---------------- hoisted rotations: ModDown + multiply-accumulate ----------------
+// ModDown of each item (an NTT of its special-prime limb, lifted) with the
+// plaintext multiply-accumulate of the vector-matrix product in the
+// epilogue.  Workgroup (chunk, k, t) loops over its items; the running sums
+// live in its own slice of `partial` (each thread re-reads exactly the words
+// it wrote, so no barrier is needed for them).
+template <int LOGN, class Ar>
+__device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __restrict__ primes,
+                                           const typename Ar::TW* __restrict__ W, const PrimeDev& P, int chunk,
+                                           int k, int t, u64* lds) {
   using C = Cfg<LOGN>;
   constexpr int N = C::N;
   constexpr int R0 = C::bits(0), LO0 = LOGN - R0, G0 = 16 >> R0;
   constexpr int RF = C::bits(C::NP - 1), GF = 16 >> RF;
-  extern __shared__ u64 lds[];
+  const Ar ar(P);
   const int tid = threadIdx.x;
-  const int pairs = 2 * J.n_dig;
-  const int chunk = blockIdx.x / pairs;
-  const int kt = blockIdx.x - chunk * pairs;
-  const int k = kt / J.n_dig, t = kt - k * J.n_dig;
-  const PrimeDev P = primes[t];
-  const u64 q = P.q, q2 = q << 1;
-  const ulonglong2* W = reinterpret_cast<const ulonglong2*>(tw) + (size_t)t * N;
+  const u64 q = P.q;
   const u64 sq = primes[J.special_prime].q, sh = J.h_src;
   const u64 hq = J.hq[t], inv = J.inv[t], inv_sh = J.inv_sh[t];
   u64* __restrict__ out = J.partial + (((size_t)chunk * 2 + k) * J.n_dig + t) * N;
@@ -305,7 +746,7 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
   for (int r = rb; r < re; r++) {
     const HoistItem it = J.items[r];
     const u64* __restrict__ src = J.ucoef + ((size_t)r * 2 + k) * N;
-    u64 x[16];
+    typename Ar::T x[16];
 #pragma unroll
     for (int u = 0; u < G0; u++) {
       const int gi = tid + C::T * u;
@@ -313,14 +754,14 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
       for (int c = 0; c < (1 << R0); c++) {
         u64 v = src[(c << LO0) | gi] + sh;
         v = v >= sq ? v - sq : v;
-        x[u * (1 << R0) + c] = submod(red64(v, P), hq, q);
+        x[u * (1 << R0) + c] = ar.from_res(submod(red64(v, P), hq, q));
       }
     }
     // keep the twiddle loads inside the loop (hoisting them out would hold
     // every stage's twiddles in registers across items)
-    const ulonglong2* Wr = W;
+    const typename Ar::TW* Wr = W;
     asm volatile("" : "+v"(Wr));
-    fwd_passes<LOGN, 0>(x, lds, Wr, q, tid);
+    fwd_passes<Sched<LOGN, 0, LOGN>, LOGN, 0, Ar, false>(x, lds, Wr, ar, tid, 0);
     // final values through LDS so the epilogue runs in natural order:
     // coalesced accesses and a bounded number of loads in flight
     __syncthreads();
@@ -328,11 +769,7 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
     for (int u = 0; u < GF; u++) {
       const int gi = tid + C::T * u;
 #pragma unroll
-      for (int c = 0; c < (1 << RF); c++) {
-        u64 v = x[u * (1 << RF) + c];
-        v = v >= q2 ? v - q2 : v;
-        lds[pad((gi << RF) | c)] = v >= q ? v - q : v;
-      }
+      for (int c = 0; c < (1 << RF); c++) lds[pad((gi << RF) | c)] = ar.fwd_res(x[u * (1 << RF) + c]);
     }
     __syncthreads();
     const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
@@ -354,109 +791,146 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const u64* __
 }
 
 template <int LOGN>
-hipError_t hoist_launch(const HoistMac& J, const PrimeDev* primes, const u64* tw, hipStream_t st) {
-  using C = Cfg<LOGN>;
-  const size_t shm = sizeof(u64) * C::lds_words();
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_hoist_mac<LOGN>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  const int n_chunks = (J.R + J.chunk - 1) / J.chunk;
-  const int blocks = n_chunks * 2 * J.n_dig;
-  if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_hoist_mac<LOGN>), dim3(blocks), dim3(C::T), shm, st, J, primes, tw);
-  return hipGetLastError();
+__global__ void __launch_bounds__(Cfg<LOGN>::T, (LOGN <= 13 ? 4 : 1))
+k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = Cfg<LOGN>::N;
+  extern __shared__ u64 lds[];
+  const int pairs = 2 * J.n_dig;
+  const int chunk = blockIdx.x / pairs;
+  const int kt = blockIdx.x - chunk * pairs;
+  const int k = kt / J.n_dig, t = kt - k * J.n_dig;
+  const PrimeDev P = primes[t];
+  if (P.use_fp)
+    hoist_body<LOGN, FpAr>(J, primes, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P, chunk, k, t,
+                           lds);
+  else
+    hoist_body<LOGN, IntAr>(J, primes, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P, chunk, k,
+                            t, lds);
 }
 
+// ---------------- launchers ----------------
 int n_jobs(const NttJob& J) { return J.na * (J.skip_diag ? J.nb - 1 : J.nb); }
 
+template <class K>
+hipError_t set_lds(K kernel, size_t shm, bool& done) {
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  if (e == hipSuccess) done = true;
+  return e;
+}
+
+// two phases when the batch is small and the scratch buffer holds it
+bool use_split(const NttJob& J, const NttTables& tabs, int log_n) {
+  const int jobs = n_jobs(J);
+  return tabs.tmp && jobs <= tabs.split_jobs && (long long)jobs << log_n <= tabs.tmp_words;
+}
+
 template <int LOGN, int PRO, int EPI>
-hipError_t fwd_launch(const NttJob& J, const PrimeDev* primes, const u64* tw, hipStream_t st) {
+hipError_t fwd_launch(const NttJob& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
   using C = Cfg<LOGN>;
-  const size_t shm = sizeof(u64) * C::lds_words();
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ntt_fwd<LOGN, PRO, EPI>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  using Sp = Split<LOGN>;
   const int jobs = n_jobs(J);
   if (jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ntt_fwd<LOGN, PRO, EPI>), dim3(jobs), dim3(C::T), shm, st, J, primes, tw);
+  if (use_split(J, tabs, LOGN)) {
+    hipLaunchKernelGGL((k_ntt_fwd_a<LOGN, PRO>), dim3(jobs * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes, tabs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, EPI>), dim3(jobs * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
+    return hipGetLastError();
+  }
+  const size_t shm = sizeof(u64) * C::lds_words();
+  static bool attr = false;
+  hipError_t e = set_lds(k_ntt_fwd<LOGN, PRO, EPI>, shm, attr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ntt_fwd<LOGN, PRO, EPI>), dim3(jobs), dim3(C::T), shm, st, J, primes, tabs);
   return hipGetLastError();
 }
 
 template <int LOGN, bool GATHER>
-hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const u64* tw, hipStream_t st) {
+hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
   using C = Cfg<LOGN>;
-  const size_t shm = sizeof(u64) * C::lds_words();
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ntt_inv<LOGN, GATHER>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  using Sp = Split<LOGN>;
   const int jobs = n_jobs(J);
   if (jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_ntt_inv<LOGN, GATHER>), dim3(jobs), dim3(C::T), shm, st, J, primes, tw);
+  if (use_split(J, tabs, LOGN)) {
+    hipLaunchKernelGGL((k_ntt_inv_1<LOGN, GATHER>), dim3(jobs * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ntt_inv_2<LOGN>), dim3(jobs * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes, tabs);
+    return hipGetLastError();
+  }
+  const size_t shm = sizeof(u64) * C::lds_words();
+  static bool attr = false;
+  hipError_t e = set_lds(k_ntt_inv<LOGN, GATHER>, shm, attr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ntt_inv<LOGN, GATHER>), dim3(jobs), dim3(C::T), shm, st, J, primes, tabs);
   return hipGetLastError();
 }
 
 template <int LOGN>
-hipError_t inv_dispatch(const NttJob& J, const PrimeDev* primes, const u64* tw, hipStream_t st) {
-  return J.gather_src ? inv_launch<LOGN, true>(J, primes, tw, st) : inv_launch<LOGN, false>(J, primes, tw, st);
+hipError_t hoist_launch(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+  using C = Cfg<LOGN>;
+  const size_t shm = sizeof(u64) * C::lds_words();
+  static bool attr = false;
+  hipError_t e = set_lds(k_hoist_mac<LOGN>, shm, attr);
+  if (e != hipSuccess) return e;
+  const int n_chunks = (J.R + J.chunk - 1) / J.chunk;
+  const int blocks = n_chunks * 2 * J.n_dig;
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_hoist_mac<LOGN>), dim3(blocks), dim3(C::T), shm, st, J, primes, tabs);
+  return hipGetLastError();
 }
 
 template <int LOGN>
-hipError_t fwd_dispatch(int pro, int epi, const NttJob& J, const PrimeDev* primes, const u64* tw,
+hipError_t fwd_dispatch(int pro, int epi, const NttJob& J, const PrimeDev* primes, const NttTables& tabs,
                         hipStream_t st) {
-  if (pro == PRO_PLAIN && epi == EPI_STORE) return fwd_launch<LOGN, PRO_PLAIN, EPI_STORE>(J, primes, tw, st);
+  if (pro == PRO_PLAIN && epi == EPI_STORE) return fwd_launch<LOGN, PRO_PLAIN, EPI_STORE>(J, primes, tabs, st);
   if (pro == PRO_CENTRED_LIFT && epi == EPI_STORE)
-    return fwd_launch<LOGN, PRO_CENTRED_LIFT, EPI_STORE>(J, primes, tw, st);
+    return fwd_launch<LOGN, PRO_CENTRED_LIFT, EPI_STORE>(J, primes, tabs, st);
   if (pro == PRO_ROUNDDIV_LIFT && epi == EPI_ROUNDDIV)
-    return fwd_launch<LOGN, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV>(J, primes, tw, st);
+    return fwd_launch<LOGN, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV>(J, primes, tabs, st);
   return hipErrorInvalidValue;
+}
+
+template <int LOGN>
+hipError_t inv_dispatch(const NttJob& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+  return J.gather_src ? inv_launch<LOGN, true>(J, primes, tabs, st) : inv_launch<LOGN, false>(J, primes, tabs, st);
 }
 
 }  // namespace
 
 hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job, const PrimeDev* primes,
-                          const u64* fwd_tw, hipStream_t st) {
+                          const NttTables& tabs, hipStream_t st) {
   switch (log_n) {
-    case 10: return fwd_dispatch<10>(pro, epi, job, primes, fwd_tw, st);
-    case 11: return fwd_dispatch<11>(pro, epi, job, primes, fwd_tw, st);
-    case 12: return fwd_dispatch<12>(pro, epi, job, primes, fwd_tw, st);
-    case 13: return fwd_dispatch<13>(pro, epi, job, primes, fwd_tw, st);
-    case 14: return fwd_dispatch<14>(pro, epi, job, primes, fwd_tw, st);
+    case 10: return fwd_dispatch<10>(pro, epi, job, primes, tabs, st);
+    case 11: return fwd_dispatch<11>(pro, epi, job, primes, tabs, st);
+    case 12: return fwd_dispatch<12>(pro, epi, job, primes, tabs, st);
+    case 13: return fwd_dispatch<13>(pro, epi, job, primes, tabs, st);
+    case 14: return fwd_dispatch<14>(pro, epi, job, primes, tabs, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes, const u64* inv_tw,
+hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes, const NttTables& tabs,
                           hipStream_t st) {
   switch (log_n) {
-    case 10: return inv_dispatch<10>(job, primes, inv_tw, st);
-    case 11: return inv_dispatch<11>(job, primes, inv_tw, st);
-    case 12: return inv_dispatch<12>(job, primes, inv_tw, st);
-    case 13: return inv_dispatch<13>(job, primes, inv_tw, st);
-    case 14: return inv_dispatch<14>(job, primes, inv_tw, st);
+    case 10: return inv_dispatch<10>(job, primes, tabs, st);
+    case 11: return inv_dispatch<11>(job, primes, tabs, st);
+    case 12: return inv_dispatch<12>(job, primes, tabs, st);
+    case 13: return inv_dispatch<13>(job, primes, tabs, st);
+    case 14: return inv_dispatch<14>(job, primes, tabs, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const PrimeDev* primes, const u64* fwd_tw,
+hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const PrimeDev* primes, const NttTables& tabs,
                                       hipStream_t st) {
   switch (log_n) {
-    case 10: return hoist_launch<10>(job, primes, fwd_tw, st);
-    case 11: return hoist_launch<11>(job, primes, fwd_tw, st);
-    case 12: return hoist_launch<12>(job, primes, fwd_tw, st);
-    case 13: return hoist_launch<13>(job, primes, fwd_tw, st);
-    case 14: return hoist_launch<14>(job, primes, fwd_tw, st);
+    case 10: return hoist_launch<10>(job, primes, tabs, st);
+    case 11: return hoist_launch<11>(job, primes, tabs, st);
+    case 12: return hoist_launch<12>(job, primes, tabs, st);
+    case 13: return hoist_launch<13>(job, primes, tabs, st);
+    case 14: return hoist_launch<14>(job, primes, tabs, st);
     default: return hipErrorInvalidValue;
   }
 }

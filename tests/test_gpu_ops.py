@@ -241,3 +241,33 @@ def test_auto_rescale_and_deep_chain():
         ox = o.drop_to(ox, oc.level)
     out = H.he_decode(g, H.he_decrypt(g, gc), 2048)
     assert np.abs(out - x ** 8).max() < 1e-6
+
+
+def test_n16384_fifty_bit_chain_bit_exact():
+    # N=16384 with nine 50-bit primes: every limb takes the FP64 butterflies;
+    # products, rescales and rotations at the top and a lower level match the
+    # oracle bit for bit
+    p = I.RAW
+    P = Pair(p["log_n"], p["bits"], p["scale"], p["seed"], steps=[1, 7, -3])
+    H, o, g = P.H, P.o, P.g
+    rng = np.random.default_rng(16384)
+    half = P.n // 2
+    x, y = rng.uniform(-1, 1, half), rng.uniform(-1, 1, half)
+    top = o.L - 1
+    gx, ox = _enc(P, x, 0, level=top, sk=False)
+    gy, oy = _enc(P, y, 1, level=top, sk=False)
+    say("n16384 mul_relin")
+    gr, orr = H.he_mul_relin(g, gx, gy), o.mul_relin(ox, oy)
+    P.ct_equal(gr, orr, "mul_relin")
+    gs, os_ = H.he_rescale(g, gr), o.rescale(orr)
+    P.ct_equal(gs, os_, "rescale")
+    say("n16384 rotations")
+    for st in (1, 7, -3):
+        P.ct_equal(H.he_rotate(g, gs, st), o.rotate(os_, st), "rotate %d" % st)
+    g2, o2 = H.he_square(g, H.he_drop_to(g, gx, 3)), o.mul_relin(o.drop_to(ox, 3), o.drop_to(ox, 3))
+    P.ct_equal(g2, o2, "square at level 3")
+    # after the rescale the scale is 2^80 / q ~ 2^30, and the rescale and
+    # key-switch noise (a few hundred units over N = 16384 slots) sits near
+    # 2^-13 of it
+    out = H.he_decode(g, H.he_decrypt(g, H.he_rotate(g, gs, 7)), half)
+    assert np.abs(out - np.roll(x * y, -7)).max() < 1e-3
