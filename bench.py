@@ -208,6 +208,8 @@ def main():
 
     log("kernel bench: batched NTT at N=16384")
     kbench = kernel_bench(H, torch, I)
+    log("key-switch bench: batched multiply/rotate at N=16384")
+    ksbench = keyswitch_bench(H, I)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -243,6 +245,7 @@ def main():
         "kernel_profile": prof,
         "roofline": roof,
         "kernel_bench": kbench,
+        "keyswitch_bench": ksbench,
         "cpu_baseline": cpu,
         "bit_exact_repeat": bit_exact_repeat,
         "logits_max_abs_err": logits_err,
@@ -338,6 +341,68 @@ def kernel_bench(H, torch, I, n_ct=256, reps=5):
     del buf, ref
     g.close()
     return out
+
+
+def keyswitch_bench(H, I, n_ct=256, reps=3):
+    """256 ciphertexts of uniform residues at N=16384 (eight 50-bit primes
+    and a special prime): batched multiply + relinearise + rescale sharing
+    the relinearisation key; rotations R1 (each step 2^t, t = 0..10, applied
+    to all 256 ciphertexts with one key) and R2 (1024 rotations: rotation t
+    applies step t + 1 to ciphertext t mod 256, 1024 distinct keys)."""
+    p = I.RAW
+    g = H.he_ctx_create(p["log_n"], p["bits"], p["scale"], p["seed"], auto_rescale=True, stream=None)
+    n, L = g.n, g.L
+    r1 = [1 << t for t in range(11)]
+    r2 = list(range(1, 1025))
+    t0 = time.perf_counter()
+    H.he_keygen(g, [])
+    for st in sorted(set(r1 + r2)):
+        H.he_keygen_galois(g, st, -1)
+    H.he_sync(g)
+    keygen_s = time.perf_counter() - t0
+    data = I.raw_residues(g.primes, n_ct, L, n)
+    cts = [H.he_ct_import(g, data[i], L - 1, p["scale"]) for i in range(n_ct)]
+    del data
+    key_bytes = 2 * L * (L + 1) * n * 8  # one key at the top level
+    ct_bytes = 2 * L * n * 8
+
+    def timed(fn):
+        out = fn()  # warm-up (allocations, attributes)
+        H.he_sync(g)
+        del out
+        best = None
+        for _ in range(reps):
+            t = time.perf_counter()
+            out = fn()
+            H.he_sync(g)
+            dt = time.perf_counter() - t
+            del out
+            best = dt if best is None else min(best, dt)
+        return best
+
+    res = {"workload": "%d ciphertexts, N=%d, %d x 50-bit primes + special; uniform residues" % (n_ct, n, L),
+           "keygen_s": keygen_s, "galois_keys": len(set(r1 + r2))}
+    other = cts[1:] + cts[:1]
+    t = timed(lambda: H.he_mul_relin_many(g, cts, other))
+    res["mul_relin_rescale"] = {"ops": n_ct, "ms": t * 1e3, "key_switches_per_s": n_ct / t,
+                                "batch": 32, "shared_key": True}
+    per_step = {}
+    for st in r1:
+        t = timed(lambda: H.he_rotate_many(g, cts, [st] * n_ct))
+        per_step[str(st)] = t * 1e3
+    vals = list(per_step.values())
+    res["rotate_R1"] = {"ops_per_step": n_ct, "ms_per_step": per_step,
+                        "key_switches_per_s": n_ct / (min(vals) * 1e-3),
+                        "flatness_max_over_min": max(vals) / min(vals)}
+    items = [cts[t % n_ct] for t in range(len(r2))]
+    t = timed(lambda: H.he_rotate_many(g, items, r2))
+    res["rotate_R2"] = {"ops": len(r2), "ms": t * 1e3, "key_switches_per_s": len(r2) / t,
+                        "distinct_keys": len(r2),
+                        "key_gbs": len(r2) * key_bytes / t / 1e9,
+                        "key_plus_ct_hbm_frac": len(r2) * (key_bytes + 3 * ct_bytes) / t / 1e9 / HBM_PEAK_GBS}
+    del cts, other, items
+    g.close()
+    return res
 
 
 if __name__ == "__main__":

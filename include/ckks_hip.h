@@ -151,6 +151,20 @@ he_status he_drop_to(he_ctx* ctx, const he_ct* a, int32_t level, he_ct** out);
  * switch with the Galois key of that step (HE_ENOKEY if none). */
 he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out);
 
+/* ---- batches (the key switch of section 3 applied to many ciphertexts) ----
+ * n operations on operands that all sit at one level (HE_ELEVEL otherwise).
+ * Up to 32 key switches run in one set of launches, sharing the key reads;
+ * every result is bit-identical to the one-at-a-time call.  out[i] is a new
+ * ciphertext owned by the caller (he_ct_free); results of one batch share
+ * device storage that is released with the last of them.  On error every
+ * out[i] is NULL. */
+/* out[i] = he_mul_relin(a[i], b[i]) */
+he_status he_mul_relin_many(he_ctx* ctx, const he_ct* const* a, const he_ct* const* b,
+                            size_t n, he_ct** out);
+/* out[i] = he_rotate(a[i], steps[i]) */
+he_status he_rotate_many(he_ctx* ctx, const he_ct* const* a, const int32_t* steps,
+                         size_t n, he_ct** out);
+
 /* ---- composites (sections 3.1, 3.2; appendix A.3, A.4) ---- */
 
 /* x <- x + rot(x, 2^j), j < ceil(log2 n): slot 0 gets the sum of slots

@@ -65,6 +65,8 @@ _SIGS = {
     "he_rescale": (C.c_int32, [_vp, _vp, _pvp]),
     "he_drop_to": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
     "he_rotate": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
+    "he_mul_relin_many": (C.c_int32, [_vp, _pvp, _pvp, C.c_size_t, _pvp]),
+    "he_rotate_many": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
     "he_sum_slots": (C.c_int32, [_vp, _vp, C.c_uint32, _pvp]),
     "he_enc_conv_im2col": (C.c_int32, [_vp, _vp, _dp, C.c_uint32, C.c_uint32, C.c_double, _pvp]),
     "he_enc_matmul": (C.c_int32, [_vp, _vp, _dp, C.c_uint32, C.c_uint32, _dp, _pvp]),
@@ -307,6 +309,30 @@ def he_drop_to(ctx, a, level):
 
 def he_rotate(ctx, a, step):
     return _new(Ct, ctx, lib().he_rotate, "he_rotate", ctx.ptr, a.ptr, int(step))
+
+
+def he_mul_relin_many(ctx, a, b):
+    """[he_mul_relin(x, y) for x, y in zip(a, b)] as one batch."""
+    n = len(a)
+    if len(b) != n:
+        raise ValueError("operand lists differ in length")
+    pa = (C.c_void_p * n)(*[x.ptr for x in a])
+    pb = (C.c_void_p * n)(*[x.ptr for x in b])
+    outs = (C.c_void_p * n)()
+    _chk(lib().he_mul_relin_many(ctx.ptr, pa, pb, n, outs), "he_mul_relin_many")
+    return [Ct(ctx, outs[i]) for i in range(n)]
+
+
+def he_rotate_many(ctx, a, steps):
+    """[he_rotate(x, s) for x, s in zip(a, steps)] as one batch."""
+    n = len(a)
+    st = np.ascontiguousarray(steps, dtype=np.int32)
+    if st.size != n:
+        raise ValueError("one step per ciphertext")
+    pa = (C.c_void_p * n)(*[x.ptr for x in a])
+    outs = (C.c_void_p * n)()
+    _chk(lib().he_rotate_many(ctx.ptr, pa, _ptr(st, C.c_int32), n, outs), "he_rotate_many")
+    return [Ct(ctx, outs[i]) for i in range(n)]
 
 
 def he_sum_slots(ctx, a, n):

@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -193,6 +194,7 @@ struct he_ct {
   int level;
   double scale;
   u64* d;
+  std::shared_ptr<void> blk;  // set when d lies in a block shared by a batch
 };
 struct he_pt {
   he_ctx* ctx;
@@ -1263,6 +1265,161 @@ he_status he_rotate(he_ctx* c, const he_ct* a, int32_t step, he_ct** out) {
   return rotate_raw(c, a, step, out);
 }
 
+// ---------------------------------------------------------------- batches
+// B ciphertexts that share one pooled block [B][2][level+1][N]; the block
+// returns to the pool with the last of them
+static void split_block(he_ctx* c, u64* blk, int B, int level, const double* scales, he_ct** out) {
+  std::shared_ptr<void> owner(blk, [c](void* p) { c->pool.put(p); });
+  const size_t per = ct_words(c, level);
+  for (int b = 0; b < B; b++) out[b] = new he_ct{c, level, scales[b], blk + b * per, owner};
+}
+
+static he_status batch_level(const he_ct* const* a, const he_ct* const* b, size_t n, int* level) {
+  *level = -1;
+  for (size_t i = 0; i < n; i++) {
+    if (!a[i] || (b && !b[i])) return fail(HE_EINVAL, "NULL ciphertext at %zu", i);
+    const int la = a[i]->level;
+    if (*level < 0) *level = la;
+    if (la != *level || (b && b[i]->level != *level))
+      return fail(HE_ELEVEL, "batched operands must share one level (%d vs %d at %zu)", *level,
+                  b && b[i]->level != *level ? b[i]->level : la, i);
+  }
+  return HE_OK;
+}
+
+he_status he_mul_relin_many(he_ctx* c, const he_ct* const* a, const he_ct* const* b, size_t n, he_ct** out) {
+  if (!c || !out || (n && (!a || !b))) return fail(HE_EINVAL, "NULL argument");
+  for (size_t i = 0; i < n; i++) out[i] = nullptr;
+  if (n == 0) return HE_OK;
+  if (!c->have_keys) return fail(HE_ENOKEY, "no relinearisation key");
+  int l = 0;
+  TRY(batch_level(a, b, n, &l));
+  if (c->auto_rescale && l < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  const int Lp = l + 1, nn = c->n;
+  for (size_t i0 = 0; i0 < n; i0 += HE_MAX_BATCH) {
+    const int B = (int)std::min<size_t>(HE_MAX_BATCH, n - i0);
+    CtList A{}, Bl{};
+    const Key* keys[HE_MAX_BATCH];
+    for (int k = 0; k < B; k++) {
+      A.p[k] = a[i0 + k]->d;
+      Bl.p[k] = b[i0 + k]->d;
+      keys[k] = &c->relin;
+    }
+    u64* R = (u64*)c->pool.get((size_t)B * ct_words(c, l) * sizeof(u64));
+    if (!R) return fail(HE_EOOM, "batch allocation failed");
+    DBuf d2;
+    he_status s = dalloc(c, d2, (size_t)B * Lp * nn);
+    if (s == HE_OK) {
+      Prof pr(c, "pointwise");
+      hipError_t e = launch_tensor_many(c->log_n, A, Bl, B, R, d2.p, Lp, c->d_primes, c->st);
+      if (e != hipSuccess) s = fail(HE_EHIP, "tensor: %s", hipGetErrorString(e));
+    }
+    if (s == HE_OK) {
+      Addend add;
+      add.p = R;
+      add.aa = (long long)Lp * nn;
+      s = key_switch(c, B, d2.p, (long long)Lp * nn, l, keys, nullptr, add, R);
+    }
+    u64* O = R;
+    int lo = l;
+    if (s == HE_OK && c->auto_rescale) {
+      O = (u64*)c->pool.get((size_t)B * ct_words(c, l - 1) * sizeof(u64));
+      s = O ? rescale_multi(c, R, B, l, O) : fail(HE_EOOM, "batch allocation failed");
+      c->pool.put(R);
+      lo = l - 1;
+      if (s != HE_OK && O) c->pool.put(O);
+    } else if (s != HE_OK) {
+      c->pool.put(R);
+    }
+    if (s != HE_OK) {
+      for (size_t i = 0; i < i0; i++) {
+        he_ct_free(out[i]);
+        out[i] = nullptr;
+      }
+      return s;
+    }
+    double sc[HE_MAX_BATCH];
+    for (int k = 0; k < B; k++) {
+      sc[k] = a[i0 + k]->scale * b[i0 + k]->scale;
+      if (lo < l) sc[k] /= (double)c->q[l];
+    }
+    split_block(c, O, B, lo, sc, out + i0);
+  }
+  return HE_OK;
+}
+
+he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps, size_t n, he_ct** out) {
+  if (!c || !out || (n && (!a || !steps))) return fail(HE_EINVAL, "NULL argument");
+  for (size_t i = 0; i < n; i++) out[i] = nullptr;
+  if (n == 0) return HE_OK;
+  int l = 0;
+  TRY(batch_level(a, nullptr, n, &l));
+  const size_t per = ct_words(c, l);
+  for (size_t i0 = 0; i0 < n; i0 += HE_MAX_BATCH) {
+    const int B = (int)std::min<size_t>(HE_MAX_BATCH, n - i0);
+    CtList A{};
+    int st[HE_MAX_BATCH];
+    for (int k = 0; k < B; k++) {
+      A.p[k] = a[i0 + k]->d;
+      st[k] = norm_step(c, steps[i0 + k]);
+    }
+    DBuf in;
+    he_status s = dalloc(c, in, (size_t)B * per);
+    u64* O = s == HE_OK ? (u64*)c->pool.get((size_t)B * per * sizeof(u64)) : nullptr;
+    if (s == HE_OK && !O) s = fail(HE_EOOM, "batch allocation failed");
+    if (s == HE_OK) {
+      Prof pr(c, "pointwise");
+      hipError_t e = launch_gather_cts(c->log_n, A, B, l + 1, in.p, c->st);
+      if (e != hipSuccess) s = fail(HE_EHIP, "gather: %s", hipGetErrorString(e));
+    }
+    // step 0 items are copies; the rest rotate together
+    if (s == HE_OK) {
+      int idx[HE_MAX_BATCH], nr = 0;
+      for (int k = 0; k < B; k++) {
+        if (st[k] == 0) {
+          if (hipMemcpyAsync(O + k * per, in.p + k * per, per * sizeof(u64), hipMemcpyDeviceToDevice, c->st) !=
+              hipSuccess)
+            s = fail(HE_EHIP, "copy failed");
+        } else {
+          idx[nr++] = k;
+        }
+      }
+      if (s == HE_OK && nr == B) {
+        s = rotate_multi(c, in.p, B, l, st, O);
+      } else if (s == HE_OK && nr > 0) {
+        // pack the rotating items, rotate, scatter back
+        DBuf pin, pout;
+        s = dalloc(c, pin, (size_t)nr * per);
+        if (s == HE_OK) s = dalloc(c, pout, (size_t)nr * per);
+        int pst[HE_MAX_BATCH];
+        for (int r = 0; r < nr && s == HE_OK; r++) {
+          pst[r] = st[idx[r]];
+          if (hipMemcpyAsync(pin.p + r * per, in.p + idx[r] * per, per * sizeof(u64), hipMemcpyDeviceToDevice,
+                             c->st) != hipSuccess)
+            s = fail(HE_EHIP, "copy failed");
+        }
+        if (s == HE_OK) s = rotate_multi(c, pin.p, nr, l, pst, pout.p);
+        for (int r = 0; r < nr && s == HE_OK; r++)
+          if (hipMemcpyAsync(O + idx[r] * per, pout.p + r * per, per * sizeof(u64), hipMemcpyDeviceToDevice,
+                             c->st) != hipSuccess)
+            s = fail(HE_EHIP, "copy failed");
+      }
+    }
+    if (s != HE_OK) {
+      if (O) c->pool.put(O);
+      for (size_t i = 0; i < i0; i++) {
+        he_ct_free(out[i]);
+        out[i] = nullptr;
+      }
+      return s;
+    }
+    double sc[HE_MAX_BATCH];
+    for (int k = 0; k < B; k++) sc[k] = a[i0 + k]->scale;
+    split_block(c, O, B, l, sc, out + i0);
+  }
+  return HE_OK;
+}
+
 // x <- x + rot(x, stride 2^j), j < ceil(log2 count); each step is one fused
 // rotate-and-add
 static he_status rotate_and_sum(he_ctx* c, he_ct* x, uint32_t count, uint32_t stride, he_ct** out) {
@@ -1789,8 +1946,8 @@ he_status he_export_key(he_ctx* c, int32_t kind, int32_t step, uint64_t* out, si
 // ---------------------------------------------------------------- housekeeping
 void he_ct_free(he_ct* ct) {
   if (!ct) return;
-  ct->ctx->pool.put(ct->d);
-  delete ct;
+  if (!ct->blk) ct->ctx->pool.put(ct->d);
+  delete ct;  // a shared block goes back to the pool with its last view
 }
 void he_pt_free(he_pt* pt) {
   if (!pt) return;

@@ -99,6 +99,15 @@ hipError_t launch_add_plain(int log_n, const u64* a, const u64* p, u64* out,
 hipError_t launch_tensor(int log_n, const u64* a, const u64* b, u64* out01,
                          u64* out2, const ModList& mods, const PrimeDev* primes,
                          hipStream_t st);
+// B ciphertexts at one level, each at its own address ([2][n_limbs][N])
+struct CtList {
+  const u64* p[HE_MAX_BATCH];
+};
+// tensor of B pairs: out01 [B][2][n_limbs][N], out2 [B][n_limbs][N]
+hipError_t launch_tensor_many(int log_n, const CtList& a, const CtList& b, int B, u64* out01, u64* out2,
+                              int n_limbs, const PrimeDev* primes, hipStream_t st);
+// copy of B ciphertexts into one contiguous [B][2][n_limbs][N] buffer
+hipError_t launch_gather_cts(int log_n, const CtList& a, int B, int n_limbs, u64* out, hipStream_t st);
 // decrypt: m[i] = c0[i] + c1[i] * s[i]   (s: [L+1][N], limb i under prime i)
 hipError_t launch_decrypt(int log_n, const u64* ct, const u64* s, u64* m,
                           int n_limbs, const PrimeDev* primes, hipStream_t st);

@@ -155,6 +155,30 @@ __global__ void k_tensor(int n, const u64* __restrict__ a, const u64* __restrict
   out2[e] = mulmod(a1, b1, P);
 }
 
+__global__ void k_tensor_many(int log_n, CtList A, CtList Bl, u64* __restrict__ out01, u64* __restrict__ out2,
+                              int n_limbs, long long total, const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long long per = (long long)n_limbs << log_n;
+  const int item = (int)(e / per);
+  const long long r = e - item * per;
+  const PrimeDev P = primes[r >> log_n];
+  const u64* a = A.p[item];
+  const u64* b = Bl.p[item];
+  const u64 a0 = a[r], a1 = a[per + r], b0 = b[r], b1 = b[per + r];
+  u64* o = out01 + (size_t)item * 2 * per;
+  o[r] = mulmod(a0, b0, P);
+  o[per + r] = addmod(mulmod(a0, b1, P), mulmod(a1, b0, P), P.q);
+  out2[(size_t)item * per + r] = mulmod(a1, b1, P);
+}
+
+__global__ void k_gather_cts(CtList A, u64* __restrict__ out, long long per_ct, long long total) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int item = (int)(e / per_ct);
+  out[e] = A.p[item][e - item * per_ct];
+}
+
 __global__ void k_decrypt(int n, const u64* __restrict__ ct, const u64* __restrict__ s, u64* __restrict__ m,
                           int n_limbs, const PrimeDev* __restrict__ primes) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -372,6 +396,20 @@ hipError_t launch_tensor(int log_n, const u64* a, const u64* b, u64* out01, u64*
   const int n = 1 << log_n;
   hipLaunchKernelGGL(k_tensor, grid_for((long long)mods.n * n), dim3(BLK), 0, st, n, a, b, out01, out2, mods.n,
                      mods, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_tensor_many(int log_n, const CtList& a, const CtList& b, int B, u64* out01, u64* out2,
+                              int n_limbs, const PrimeDev* primes, hipStream_t st) {
+  const long long total = ((long long)B * n_limbs) << log_n;
+  hipLaunchKernelGGL(k_tensor_many, grid_for(total), dim3(BLK), 0, st, log_n, a, b, out01, out2, n_limbs, total,
+                     primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cts(int log_n, const CtList& a, int B, int n_limbs, u64* out, hipStream_t st) {
+  const long long per = (2LL * n_limbs) << log_n;
+  hipLaunchKernelGGL(k_gather_cts, grid_for(per * B), dim3(BLK), 0, st, a, out, per, per * B);
   return hipGetLastError();
 }
 
