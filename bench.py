@@ -104,6 +104,10 @@ def main():
     ap.add_argument("--latency-runs", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=8.0)
+    ap.add_argument("--no-extra-bench", action="store_true",
+                    help="skip the N=16384 NTT and key-switch benches (profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 2 GiB buffer three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,6 +120,15 @@ def main():
     from paper_2104_03152_amd import inputs as I
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.copy_calibration:
+        # a plain device-to-device copy of known size: 2 GiB read, 2 GiB written
+        src = torch.empty(1 << 28, dtype=torch.int64, device="cuda").random_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied 3 x 2 GiB")
+        return
     params = I.CNN
     shape = I.CNN_SHAPE
     d = I.cnn_inputs()
@@ -141,12 +154,15 @@ def main():
 
     log("timed %d steps" % args.steps)
     torch.cuda.synchronize()
+    window_marker(torch)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         y = step(H, g, net, x, shape["windows"])
     H.he_sync(g)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    window_marker(torch)
     ms_per_step = dt * 1e3 / args.steps
     out = H.he_ct_export(g, y)
     bit_exact_repeat = bool(np.array_equal(out, ref))
@@ -206,10 +222,12 @@ def main():
     dom = max(prof, key=lambda k: prof[k]["ms_per_step"]) if prof else None
     roof = roofline_entry(dom, prof[dom], g.n) if dom else None
 
-    log("kernel bench: batched NTT at N=16384")
-    kbench = kernel_bench(H, torch, I)
-    log("key-switch bench: batched multiply/rotate at N=16384")
-    ksbench = keyswitch_bench(H, I)
+    kbench = ksbench = None
+    if not args.no_extra_bench:
+        log("kernel bench: batched NTT at N=16384")
+        kbench = kernel_bench(H, torch, I)
+        log("key-switch bench: batched multiply/rotate at N=16384")
+        ksbench = keyswitch_bench(H, I)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -257,13 +275,14 @@ def main():
 
 
 # Roofline of a kernel family.  NTT-type kernels (every family that runs the
-# LDS NTT) are bound by integer VALU issue: the work unit is the butterfly,
-# (N/2) log2 N per limb-NTT; the peak is the VALU issue rate (256 CUs x 4
-# SIMD16 x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s) over the
-# minimal VALU instruction count of a 64-bit Shoup butterfly on gfx950
-# (27).  The inner products are bound by HBM (their key reads).
+# LDS NTT) are bound by VALU issue: the work unit is the butterfly, (N/2)
+# log2 N per limb-NTT; the peak is the VALU issue rate (256 CUs x 4 SIMD16 x
+# 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s, FP64 FMA at full rate)
+# over the VALU operation count of the cheaper of the two butterflies: the
+# exact FP64 one (11 operations; the 64-bit integer Shoup butterfly takes
+# about 27).  The inner products are bound by HBM (their key reads).
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-BUTTERFLY_INSTR = 27
+BUTTERFLY_INSTR = 11
 NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "hoisted_moddown")
 
 
@@ -303,6 +322,13 @@ def pmc_traffic(fam):
     if rec.get("source_sha256") != h.hexdigest():
         return None
     return rec.get("families", {}).get(fam)
+
+
+def window_marker(torch):
+    """A one-element fill kernel, the only torch kernel of the CNN run: the
+    profile summaries keep the dispatches between the first two."""
+    torch.full((1,), 1.0, device="cuda")
+    torch.cuda.synchronize()
 
 
 def kernel_bench(H, torch, I, n_ct=256, reps=5):

@@ -682,7 +682,8 @@ k_ntt_fwd_a(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
     fwd_a_body<LOGN, PRO, IntAr>(J, primes, Wi, P, w, a, b, sub, tabs.tmp, lds);
 }
 
-template <int LOGN, int EPI>
+// PRO names the launch family (the block phase does not use it)
+template <int LOGN, int PRO, int EPI>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ntt_fwd_b(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
@@ -835,7 +836,7 @@ hipError_t fwd_launch(const NttJob& J, const PrimeDev* primes, const NttTables& 
     hipLaunchKernelGGL((k_ntt_fwd_a<LOGN, PRO>), dim3(jobs * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes, tabs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, EPI>), dim3(jobs * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
+    hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, PRO, EPI>), dim3(jobs * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
     return hipGetLastError();
   }
   const size_t shm = sizeof(u64) * C::lds_words();

@@ -1,12 +1,21 @@
 """Summarise rocprofv3 result databases into the short text files kept under
 profiles/ (kernel-trace statistics, HBM traffic from PMC counters).
 
-    python -m paper_2104_03152_amd.rocprof_summary trace <results.db> <out.md> "<command>"
-    python -m paper_2104_03152_amd.rocprof_summary traffic <fetch.db> <write.db> \
+    python -m paper_2104_03152_amd.rocprof_summary trace <results.db> <out.md> "<command>" [bench.out]
+    python -m paper_2104_03152_amd.rocprof_summary traffic <fetch.db> <write.db> \\
         <copy_fetch.db> <copy_write.db> <out.json> <out.md> "<command>"
 
+A launch family of the library (the unit its HIP-event profile reports) is
+one kernel, or, for small batches of NTTs, a block-phase and a column-phase
+kernel issued back to back.  Per family launch: the summed duration (trace)
+or the summed HBM bytes (traffic) of its kernels, divided by the number of
+family launches (the dispatches of its first kernel).
+
+Only the dispatches between the bench's two window markers (one-element
+torch fill kernels around its timed steps) count, when the run has them.
+
 Traffic: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each kernel,
-scaled by the ratio between the known bytes of a plain 2 GiB copy kernel
+scaled by the ratio between the known bytes of a plain 2 GiB device copy
 and what the same counters read for it.
 """
 import collections
@@ -18,16 +27,19 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 2 << 30  # the calibration copy moves 2 GiB each way
+COPY_KERNEL = "copyBuffer"
+MARKER = "FillFunctor"
 
-# kernel-name fragment -> profile family (launch-site grouping of the library)
+# family -> (kernels that start a launch, kernels that complete it), as
+# name fragments of the N=8192 instantiations
 FAMILIES = [
-    ("k_ntt_inv<13>", "ntt_inv"),
-    ("k_ntt_fwd<13, 0, 0>", "ntt_fwd"),
-    ("k_ntt_fwd<13, 1, 0>", "modup"),
-    ("k_ntt_fwd<13, 2, 1>", "moddown+rescale"),
-    ("k_hoist_mac<13>", "hoisted_moddown"),
-    ("k_inner_hoisted", "hoisted_inner"),
-    ("k_inner(", "keyswitch_inner"),
+    ("ntt_inv", ["k_ntt_inv_1<13", "k_ntt_inv<13"], ["k_ntt_inv_2<13"]),
+    ("ntt_fwd", ["k_ntt_fwd_a<13, 0>", "k_ntt_fwd<13, 0, 0>"], ["k_ntt_fwd_b<13, 0, 0>"]),
+    ("modup", ["k_ntt_fwd_a<13, 1>", "k_ntt_fwd<13, 1, 0>"], ["k_ntt_fwd_b<13, 1, 0>"]),
+    ("moddown+rescale", ["k_ntt_fwd_a<13, 2>", "k_ntt_fwd<13, 2, 1>"], ["k_ntt_fwd_b<13, 2, 1>"]),
+    ("hoisted_moddown", ["k_hoist_mac<13>"], []),
+    ("hoisted_inner", ["k_inner_hoisted"], []),
+    ("keyswitch_inner", ["k_inner("], []),
 ]
 
 
@@ -43,60 +55,113 @@ def short(name):
     return name.replace("(anonymous namespace)::", "").replace("void ", "")
 
 
-def trace(db_path, out_md, command):
+def _match(name, frags):
+    return any(f in name for f in frags)
+
+
+def _families(per_kernel):
+    """per_kernel: short name -> list of values (one per dispatch).  Returns
+    family -> (launches, total value, kernel names)."""
+    out = collections.OrderedDict()
+    for fam, first, rest in FAMILIES:
+        starts = [k for k in per_kernel if _match(k, first)]
+        others = [k for k in per_kernel if _match(k, rest)]
+        launches = sum(len(per_kernel[k]) for k in starts)
+        if not launches:
+            continue
+        total = sum(sum(per_kernel[k]) for k in starts + others)
+        out[fam] = (launches, total, starts + others)
+    return out
+
+
+def _window(rows):
+    """rows: (dispatch_id, name, value).  Keeps those strictly between the
+    first two marker dispatches (all of them without markers)."""
+    marks = sorted(d for d, name, _ in rows if MARKER in name)
+    if len(marks) < 2:
+        return [(name, v) for _, name, v in rows if MARKER not in name]
+    lo, hi = marks[0], marks[1]
+    return [(name, v) for d, name, v in rows if lo < d < hi]
+
+
+def _bench_profile(path):
+    """kernel_profile of the bench JSON line printed by the traced run."""
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("{"):
+                return json.loads(line).get("kernel_profile") or {}
+    return {}
+
+
+def trace(db_path, out_md, command, bench_out=None):
+    ev = _bench_profile(bench_out)
     db = sqlite3.connect(db_path)
-    rows = db.execute("select name, duration, grid_x, workgroup_x from kernels").fetchall()
-    agg = collections.OrderedDict()
-    for name, dur, gx, wx in rows:
-        a = agg.setdefault(short(name).split("(")[0] if "<" not in name else short(name)[:60], [0, 0.0])
-        a[0] += 1
-        a[1] += dur
-    tot = sum(v[1] for v in agg.values())
+    rows = db.execute("select dispatch_id, name, duration from kernels").fetchall()
+    per = collections.defaultdict(list)
+    for name, dur in _window(rows):
+        per[short(name)].append(float(dur))
+    tot = sum(sum(v) for v in per.values())
     lines = ["# Kernel-trace statistics", "", "Command (repo root on the GPU box):", "",
              "    " + command, "",
-             "| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
-    for k, (n, d) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:20]:
-        lines.append("| `%s` | %d | %.3f | %.2f | %.1f%% |" % (k, n, d / 1e6, d / n / 1e3, 100 * d / tot))
+             "## Launch families (N = 8192)", "",
+             "Kernel time per family launch over the timed steps (sum of its kernels); beside it "
+             "the HIP-event time per launch that the bench measured without the profiler "
+             "(launch to completion on the library stream, so it also holds the gap between the "
+             "two phase kernels).", "",
+             "| family | launches | kernel us per launch | HIP-event us per launch | kernels |",
+             "|---|---|---|---|---|"]
+    for fam, (n, total, names) in _families(per).items():
+        e = ev.get(fam) or (ev.get("moddown") if fam == "moddown+rescale" else None)
+        lines.append("| %s | %d | %.2f | %s | %s |" % (
+            fam, n, total / n / 1e3, "%.2f" % e["avg_launch_us"] if e else "-",
+            ", ".join("`%s`" % k.split("(")[0] for k in names)))
+    lines += ["", "## Kernels", "", "| kernel | calls | total ms | avg us | share |", "|---|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:24]:
+        lines.append("| `%s` | %d | %.3f | %.2f | %.1f%% |" % (k.split("(")[0][:70], len(v), sum(v) / 1e6,
+                                                            sum(v) / len(v) / 1e3, 100 * sum(v) / tot))
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
 
 
 def _counter(db_path, counter):
     db = sqlite3.connect(db_path)
-    rows = db.execute("select kernel_name, value from counters_collection where counter_name=?",
+    rows = db.execute("select dispatch_id, kernel_name, value from counters_collection where counter_name=?",
                       (counter,)).fetchall()
     per = collections.defaultdict(list)
-    for name, v in rows:
+    for name, v in _window(rows):
         per[short(name)].append(float(v))
     return per
 
 
 def traffic(fetch_db, write_db, cfetch_db, cwrite_db, out_json, out_md, command):
-    cf = [v for k, vs in _counter(cfetch_db, "FETCH_SIZE").items() if "kcopy" in k for v in vs]
-    cw = [v for k, vs in _counter(cwrite_db, "WRITE_SIZE").items() if "kcopy" in k for v in vs]
-    fetch_scale = COPY_BYTES / (sum(cf) / len(cf) * 1024)
-    write_scale = COPY_BYTES / (sum(cw) / len(cw) * 1024)
+    cf = [v for k, vs in _counter(cfetch_db, "FETCH_SIZE").items() if COPY_KERNEL in k for v in vs]
+    cw = [v for k, vs in _counter(cwrite_db, "WRITE_SIZE").items() if COPY_KERNEL in k for v in vs]
+    # the largest dispatches are the 2 GiB copies
+    cf, cw = max(cf), max(cw)
+    fetch_scale = COPY_BYTES / (cf * 1024)
+    write_scale = COPY_BYTES / (cw * 1024)
     fe, wr = _counter(fetch_db, "FETCH_SIZE"), _counter(write_db, "WRITE_SIZE")
+    ffam, wfam = _families(fe), _families(wr)
     fams = {}
     lines = ["# HBM traffic from PMC counters (MNIST-shaped CNN at N = 8192)", "",
              "Commands (repo root on the GPU box):", "", "    " + command, "",
-             "Calibration: a plain 2 GiB copy kernel reads FETCH_SIZE = %.0f KiB and "
+             "Calibration: a plain 2 GiB device copy reads FETCH_SIZE = %.0f KiB and "
              "WRITE_SIZE = %.0f KiB per dispatch; scale factors %.4f (fetch) and %.4f (write)."
-             % (sum(cf) / len(cf), sum(cw) / len(cw), fetch_scale, write_scale), "",
-             "| family | kernel | dispatches | fetch KiB/launch | write KiB/launch | HBM bytes/launch |",
+             % (cf, cw, fetch_scale, write_scale), "",
+             "| family | launches | fetch KiB/launch | write KiB/launch | HBM bytes/launch | kernels |",
              "|---|---|---|---|---|---|"]
-    for frag, fam in FAMILIES:
-        fk = [k for k in fe if frag in k]
-        wk = [k for k in wr if frag in k]
-        if not fk or not wk:
+    for fam in ffam:
+        if fam not in wfam:
             continue
-        fv = [v for k in fk for v in fe[k]]
-        wv = [v for k in wk for v in wr[k]]
-        fb = sum(fv) / len(fv) * 1024 * fetch_scale
-        wb = sum(wv) / len(wv) * 1024 * write_scale
+        n, ftot, names = ffam[fam]
+        nw, wtot, _ = wfam[fam]
+        fb = ftot / n * 1024 * fetch_scale
+        wb = wtot / nw * 1024 * write_scale
         fams[fam] = fb + wb
-        lines.append("| %s | `%s` | %d | %.1f | %.1f | %.0f |" % (fam, fk[0][:40], len(fv), fb / 1024,
-                                                                   wb / 1024, fb + wb))
+        lines.append("| %s | %d | %.1f | %.1f | %.0f | %s |" % (
+            fam, n, fb / 1024, wb / 1024, fb + wb, ", ".join("`%s`" % k.split("(")[0] for k in names)))
     if "moddown+rescale" in fams:
         fams["moddown"] = fams["rescale"] = fams["moddown+rescale"]
     rec = {"source_sha256": source_sha(), "fetch_scale": fetch_scale, "write_scale": write_scale,
@@ -109,6 +174,6 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, out_json, out_md, command)
 
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
-        trace(sys.argv[2], sys.argv[3], sys.argv[4])
+        trace(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else None)
     else:
         traffic(*sys.argv[2:9])
