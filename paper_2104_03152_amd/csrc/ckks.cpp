@@ -430,6 +430,116 @@ he_status modup(he_ctx* c, const u64* coef, int B, int Lp, u64* ext) {
 }
 
 // ---------------------------------------------------------------- key switching
+// ---------------------------------------------------------------- fused key switch
+// Small batches: ModUp in three launches (inverse block phase; inverse
+// column phase + centred lift + forward column phase; forward block phase),
+// ModDown in three (inner product on p + inverse block phase; inverse
+// column phase + rounding lift + forward column phase; forward block phase
+// with the data-limb inner product, the division and the addends).
+static bool ks_fusable(const he_ctx* c, int B, int Lp) {
+  return c->tabs.split_jobs > 0 && (long long)B * Lp * Lp <= c->tabs.split_jobs;
+}
+
+struct KsBufs {
+  DBuf t1, t2, ext, t3, t4;
+};
+
+// fills K for B items at level l; allocates the intermediates
+static he_status ks_prepare(he_ctx* c, int B, const u64* d, long long ds, int l, const Key* const* keys,
+                            const u64* gals, KsJob& K, KsBufs& bufs, bool moddown) {
+  const int n = c->n, Lp = l + 1, nm = Lp + 1;
+  TRY(dalloc(c, bufs.t1, (size_t)B * Lp * n));
+  TRY(dalloc(c, bufs.t2, (size_t)B * Lp * Lp * n));
+  TRY(dalloc(c, bufs.ext, (size_t)B * Lp * nm * n));
+  if (moddown) {
+    TRY(dalloc(c, bufs.t3, (size_t)2 * B * n));
+    TRY(dalloc(c, bufs.t4, (size_t)2 * B * Lp * n));
+  }
+  K = KsJob{};
+  K.B = B;
+  K.Lp = Lp;
+  K.nm = nm;
+  K.special = c->L;
+  K.d = d;
+  K.ds = ds;
+  for (int b = 0; b < B; b++) {
+    K.gal[b] = gals ? gals[b] : 1;
+    K.key[b] = keys ? keys[b]->d : nullptr;
+    K.km[b] = keys ? keys[b]->ml + 2 : 0;
+  }
+  K.t1 = bufs.t1.p;
+  K.t2 = bufs.t2.p;
+  K.ext = bufs.ext.p;
+  K.t3 = bufs.t3.p;
+  K.t4 = bufs.t4.p;
+  const size_t np = c->q.size();
+  K.h_src = (c->q[c->L] - 1) / 2;
+  for (int t = 0; t < Lp; t++) {
+    K.hq[t] = c->rd_hq[c->L * np + t];
+    K.inv[t] = c->rd_inv[c->L * np + t];
+    K.inv_sh[t] = c->rd_inv_sh[c->L * np + t];
+  }
+  return HE_OK;
+}
+
+// ext [B][Lp][nm][N] = ModUp of the (gathered) inputs
+static he_status modup_fused(he_ctx* c, const KsJob& K, bool gather) {
+  const int n = c->n, B = K.B, Lp = K.Lp, nm = K.nm;
+  Prof pr(c, "modup", (double)B * Lp * (1 + Lp), 8.0 * n * B * Lp * (1 + Lp));
+  NttJob J{};
+  J.src = K.d;
+  J.sa = K.ds;
+  J.sb = n;
+  J.na = B;
+  J.nb = Lp;
+  for (int i = 0; i < Lp; i++) J.dst_prime[i] = (unsigned char)i;
+  if (gather) {
+    J.gather_src = 1;
+    J.gal_div = 1;
+    for (int b = 0; b < B; b++) J.gal[b] = K.gal[b];
+  }
+  J.mid = K.t1;
+  hipError_t e = launch_ntt_inv_blocks(c->log_n, J, c->d_primes, c->tabs, 1, c->st);
+  if (e == hipSuccess) e = launch_ks_modup_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e == hipSuccess) {
+    NttJob F{};
+    F.dst = K.ext;
+    F.da = (long long)nm * n;
+    F.db = n;
+    F.na = B * Lp;
+    F.nb = nm;
+    F.skip_diag = 1;
+    F.src_prime = -1;
+    F.amod = Lp;
+    for (int t = 0; t < nm; t++) F.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
+    F.mid = K.t2;
+    e = launch_ntt_fwd_blocks(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, F, c->d_primes, c->tabs, c->st);
+  }
+  if (e != hipSuccess) return fail(HE_EHIP, "fused modup: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
+// out = ModDown(inner products) + addends
+static he_status moddown_fused(he_ctx* c, KsJob& K, const Addend& add, u64* out) {
+  const int n = c->n, B = K.B, Lp = K.Lp, nm = K.nm;
+  K.out = out;
+  K.oa = (long long)Lp * n;
+  K.add = add.p;
+  K.aa = add.aa;
+  K.add_even_only = add.even_only;
+  K.add_gather = add.gals ? 1 : 0;
+  K.add2 = add.p2;
+  K.a2a = add.a2a;
+  // per item: digits Lp*nm and key 2*Lp*nm limbs read, 2*Lp written, addends read
+  const double adds = (add.p ? (add.even_only ? 1.0 : 2.0) : 0.0) + (add.p2 ? 2.0 : 0.0);
+  Prof pr(c, "moddown", 2.0 * B * (1 + Lp), 8.0 * n * B * (3.0 * Lp * nm + 2.0 * Lp + adds * Lp));
+  hipError_t e = launch_ks_special_blocks(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e == hipSuccess) e = launch_ks_moddown_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e == hipSuccess) e = launch_ks_moddown_blocks(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "fused moddown: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
 // Key switch of B polynomials at level l: item b's input d + b*ds (NTT domain
 // [l+1][N]), read at the Galois source of gals[b] when gals is given (the
 // rotated poly without materialising it), with keys[b];
@@ -441,6 +551,13 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
   for (int b = 0; b < B; b++)
     if (keys[b]->ml < l)
       return fail(HE_ENOKEY, "key valid up to level %d, ciphertext at level %d", keys[b]->ml, l);
+  if (ks_fusable(c, B, Lp)) {
+    KsJob K;
+    KsBufs bufs;
+    TRY(ks_prepare(c, B, d, ds, l, keys, gals, K, bufs, true));
+    TRY(modup_fused(c, K, gals != nullptr));
+    return moddown_fused(c, K, add, out);
+  }
   DBuf coef, ext, u, ucoef;
   TRY(dalloc(c, coef, (size_t)B * Lp * n));
   TRY(dalloc(c, ext, (size_t)B * Lp * nm * n));
@@ -534,6 +651,54 @@ he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps,
 he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
   const int n = c->n;
   if (l < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  if (c->tabs.split_jobs > 0 && 2LL * n_ct * l <= c->tabs.split_jobs) {
+    // three launches: inverse block phase of limb l; its inverse column
+    // phase, rounding lift and forward column phase for each t < l; forward
+    // block phase with the division epilogue
+    DBuf t3, t4;
+    TRY(dalloc(c, t3, (size_t)2 * n_ct * n));
+    TRY(dalloc(c, t4, (size_t)2 * n_ct * l * n));
+    const size_t np = c->q.size();
+    KsJob K{};
+    K.B = n_ct;
+    K.Lp = l;
+    K.nm = l + 1;
+    K.special = l;
+    K.t3 = t3.p;
+    K.t4 = t4.p;
+    K.h_src = (c->q[l] - 1) / 2;
+    NttJob J{};
+    J.src = in + (size_t)l * n;
+    J.sa = (long long)(l + 1) * n;
+    J.na = 2 * n_ct;
+    J.nb = 1;
+    J.dst_prime[0] = (unsigned char)l;
+    J.mid = t3.p;
+    NttJob F{};
+    F.dst = out;
+    F.da = (long long)l * n;
+    F.db = n;
+    F.na = 2 * n_ct;
+    F.nb = l;
+    F.u = in;
+    F.ua = (long long)(l + 1) * n;
+    F.ub = n;
+    F.mid = t4.p;
+    for (int t = 0; t < l; t++) {
+      K.hq[t] = c->rd_hq[l * np + t];
+      F.dst_prime[t] = (unsigned char)t;
+      F.inv[t] = c->rd_inv[l * np + t];
+      F.inv_sh[t] = c->rd_inv_sh[l * np + t];
+    }
+    // per poly: the dropped limb and the l kept limbs read, l limbs written
+    Prof pr(c, "rescale", 2.0 * n_ct * (1 + l), 8.0 * n * 2 * n_ct * (2.0 * l + 1));
+    hipError_t e = launch_ntt_inv_blocks(c->log_n, J, c->d_primes, c->tabs, 2, c->st);
+    if (e == hipSuccess) e = launch_ks_moddown_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+    if (e == hipSuccess)
+      e = launch_ntt_fwd_blocks(c->log_n, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV, F, c->d_primes, c->tabs, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "fused rescale: %s", hipGetErrorString(e));
+    return HE_OK;
+  }
   DBuf coef;
   TRY(dalloc(c, coef, 2 * (size_t)n_ct * n));
   {
@@ -1665,16 +1830,26 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
   DBuf partial;
   if (R > 0) {
     DBuf coef, ext, u, ucoef;
-    TRY(dalloc(c, coef, (size_t)Lp * n));
-    TRY(dalloc(c, ext, (size_t)Lp * nm * n));
+    KsJob K;
+    KsBufs bufs;
     TRY(dalloc(c, u, (size_t)R * 2 * nm * n));
     TRY(dalloc(c, ucoef, (size_t)R * 2 * n));
     const u64* c1 = x->d + (size_t)Lp * n;
-    TRY(ntt_rows(c, false, c1, coef.p, 1, Lp, 0, 0));
-    TRY(modup(c, coef.p, 1, Lp, ext.p));
+    const u64* extp = nullptr;
+    if (ks_fusable(c, 1, Lp)) {  // one ModUp shared by every rotation
+      TRY(ks_prepare(c, 1, c1, 0, l, nullptr, nullptr, K, bufs, false));
+      TRY(modup_fused(c, K, false));
+      extp = bufs.ext.p;
+    } else {
+      TRY(dalloc(c, coef, (size_t)Lp * n));
+      TRY(dalloc(c, ext, (size_t)Lp * nm * n));
+      TRY(ntt_rows(c, false, c1, coef.p, 1, Lp, 0, 0));
+      TRY(modup(c, coef.p, 1, Lp, ext.p));
+      extp = ext.p;
+    }
     {
       HoistInner I{};
-      I.ext = ext.p;
+      I.ext = extp;
       I.c1 = c1;
       I.items = p->items;
       I.u = u.p;

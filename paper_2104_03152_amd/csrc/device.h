@@ -38,6 +38,9 @@ struct NttJob {
   // a / gal_div (gather_src set), i.e. transform tau_g(src) directly
   int gather_src, gal_div;
   u64 gal[32];
+  // two-phase transforms: intermediate of job w at mid + w*N (NULL: the
+  // context's scratch)
+  u64* mid;
 };
 
 #define HE_MAX_BATCH 32
@@ -64,6 +67,57 @@ hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job,
                           const PrimeDev* primes, const NttTables& tabs, hipStream_t st);
 hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes,
                           const NttTables& tabs, hipStream_t st);
+
+// single phases of the two-phase transforms (intermediate at job.mid): the
+// inverse block phase (tag 1: first kernel of a key-switch ModUp, 2: of a
+// rescale, gather not allowed), and the forward block phase with its epilogue
+hipError_t launch_ntt_inv_blocks(int log_n, const NttJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                 int tag, hipStream_t st);
+hipError_t launch_ntt_fwd_blocks(int log_n, int pro, int epi, const NttJob& job, const PrimeDev* primes,
+                                 const NttTables& tabs, hipStream_t st);
+
+// Fused key switch of B items at Lp data limbs for small batches.  ModUp:
+// inverse block phase of the (gathered) input -> t1; inverse column phase,
+// centred lift to every other modulus and forward column phase -> t2;
+// forward block phase -> ext.  ModDown: inner product on the special
+// modulus and inverse block phase -> t3; inverse column phase, rounding lift
+// to each data prime and forward column phase -> t4; forward block phase
+// with the data-limb inner product, the division by p and the addends in its
+// epilogue -> out.
+struct KsJob {
+  int B, Lp, nm, special;         // items, digits (= data limbs), Lp + 1 moduli, special prime index
+  const u64* d;                   // item b's input at d + b*ds: [Lp][N], NTT domain
+  long long ds;
+  u64 gal[HE_MAX_BATCH];          // Galois element of item b (1: none)
+  const u64* key[HE_MAX_BATCH];   // item b's key [digit][2][km][N], Montgomery form
+  int km[HE_MAX_BATCH];           // moduli stored per digit in that key
+  u64* t1;                        // [B*Lp][N]
+  u64* t2;                        // [B*Lp*Lp][N]: job (b*Lp + j)*Lp + tt, target tt (< j) or tt + 1
+  u64* ext;                       // [B][Lp][nm][N]; slots [b][j][j] unused
+  u64* t3;                        // [2B][N]
+  u64* t4;                        // [2B*Lp][N]
+  u64* out;                       // poly a = 2b + k at out + a*oa: [Lp][N]
+  long long oa;
+  const u64* add;                 // addend poly a at add + a*aa (every a, or even a only)
+  long long aa;
+  int add_even_only, add_gather;  // gather: read at the Galois source of gal[b]
+  const u64* add2;                // second addend at add2 + a*a2a (nullable)
+  long long a2a;
+  u64 h_src;                      // (p - 1) / 2
+  u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];  // per data prime t: h mod q_t, p^-1 mod q_t
+};
+// ModUp columns (t1 -> t2), ModDown inner + blocks (ext -> t3), ModDown
+// columns (t3 -> t4), ModDown blocks + epilogue (t4 -> out).  The column
+// kernels also serve a rescale: `special` is then the dropped limb's prime,
+// t3 its inverse block phase, and the block phase runs as a plain NTT job.
+hipError_t launch_ks_modup_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                hipStream_t st);
+hipError_t launch_ks_special_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                    hipStream_t st);
+hipError_t launch_ks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                  hipStream_t st);
+hipError_t launch_ks_moddown_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                    hipStream_t st);
 
 // ---- samplers (ChaCha20 streams) ----
 // signed small polynomial (ternary: kind 0, Gaussian CDT: kind 1) reduced into

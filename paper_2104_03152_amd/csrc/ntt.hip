@@ -677,9 +677,9 @@ k_ntt_fwd_a(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
   const u64* tabs_int = tabs.fwd;
   HE_PHASE_PRELUDE(Split<LOGN>::WA)
   if (P.use_fp)
-    fwd_a_body<LOGN, PRO, FpAr>(J, primes, Wf, P, w, a, b, sub, tabs.tmp, lds);
+    fwd_a_body<LOGN, PRO, FpAr>(J, primes, Wf, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
   else
-    fwd_a_body<LOGN, PRO, IntAr>(J, primes, Wi, P, w, a, b, sub, tabs.tmp, lds);
+    fwd_a_body<LOGN, PRO, IntAr>(J, primes, Wi, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
 }
 
 // PRO names the launch family (the block phase does not use it)
@@ -691,12 +691,14 @@ k_ntt_fwd_b(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
   const u64* tabs_int = tabs.fwd;
   HE_PHASE_PRELUDE(Split<LOGN>::WB)
   if (P.use_fp)
-    fwd_b_body<LOGN, EPI, FpAr>(J, Wf, P, w, a, b, sub, tabs.tmp, lds);
+    fwd_b_body<LOGN, EPI, FpAr>(J, Wf, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
   else
-    fwd_b_body<LOGN, EPI, IntAr>(J, Wi, P, w, a, b, sub, tabs.tmp, lds);
+    fwd_b_body<LOGN, EPI, IntAr>(J, Wi, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
 }
 
-template <int LOGN, bool GATHER>
+// TAG names the launch family: 0 plain inverse, 1 the first kernel of a
+// fused key-switch ModUp, 2 that of a fused rescale
+template <int LOGN, bool GATHER, int TAG>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ntt_inv_1(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
@@ -704,9 +706,9 @@ k_ntt_inv_1(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
   const u64* tabs_int = tabs.inv;
   HE_PHASE_PRELUDE(Split<LOGN>::WB)
   if (P.use_fp)
-    inv_1_body<LOGN, GATHER, FpAr>(J, Wf, P, w, a, b, sub, tabs.tmp, lds);
+    inv_1_body<LOGN, GATHER, FpAr>(J, Wf, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
   else
-    inv_1_body<LOGN, GATHER, IntAr>(J, Wi, P, w, a, b, sub, tabs.tmp, lds);
+    inv_1_body<LOGN, GATHER, IntAr>(J, Wi, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
 }
 
 template <int LOGN>
@@ -717,11 +719,310 @@ k_ntt_inv_2(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
   const u64* tabs_int = tabs.inv;
   HE_PHASE_PRELUDE(Split<LOGN>::WA)
   if (P.use_fp)
-    inv_2_body<LOGN, FpAr>(J, Wf, P, w, a, b, sub, tabs.tmp, lds);
+    inv_2_body<LOGN, FpAr>(J, Wf, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
   else
-    inv_2_body<LOGN, IntAr>(J, Wi, P, w, a, b, sub, tabs.tmp, lds);
+    inv_2_body<LOGN, IntAr>(J, Wi, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
 }
 #undef HE_PHASE_PRELUDE
+
+// ---------------- fused key switch (small batches) ----------------
+// Column phases of two transforms in one workgroup: the inverse column phase
+// of a limb under prime s finishes its coefficients, which are lifted to
+// prime t (centred digit for ModUp, r - h of the divide-and-round for
+// ModDown) and run through the forward column phase under prime t.
+template <int LOGN, int PRO, class ArS, class ArT>
+__device__ __forceinline__ void cols_fused_body(const u64* __restrict__ tin, u64* __restrict__ tout,
+                                                const PrimeDev& Ps, const PrimeDev& Pt,
+                                                const typename ArS::TW* __restrict__ Wi,
+                                                const typename ArT::TW* __restrict__ Wf, u64 hs, u64 hq_t, int sub,
+                                                u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  constexpr int E = S::E;
+  const ArS ars(Ps);
+  const ArT art(Pt);
+  const int tid = threadIdx.x;
+  PassTw<S, Sp::LOGMA, 0, false, ArS> twi;
+  PassTw<S, Sp::LOGMA, 0, true, ArT> twf;
+  twi.load(Wi, tid, 0);
+  twf.load(Wf, tid, 0);
+  typename ArS::T x[E];
+  {
+    constexpr int R = S::bits(0), LO = S::ilo(0), G = E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = ArS::unbits(tin[col_g<LOGN>(gidx(gi, c, LO, R), sub)]);
+    }
+  }
+  inv_passes<S, Sp::LOGMA, 0, ArS, true>(x, lds, Wi, ars, tid, 0, &twi);
+  // coefficients mod q_s, lifted to q_t
+  const u64 qs = Ps.q, qt = Pt.q;
+  u64 v[E];
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    u64 r = ars.inv_res(x[i], Ps);
+    if (PRO == PRO_CENTRED_LIFT) {
+      if (r > hs) {
+        const u64 m = red64(qs - r, Pt);
+        r = m ? qt - m : 0;
+      } else {
+        r = red64(r, Pt);
+      }
+    } else {
+      r += hs;
+      r = r >= qs ? r - qs : r;
+      r = submod(red64(r, Pt), hq_t, qt);
+    }
+    v[i] = r;
+  }
+  constexpr int RI = S::bits(S::NP - 1), LOI = S::ilo(S::NP - 1);
+  constexpr int RF = S::bits(0), LOF = S::flo(0);
+  __syncthreads();  // the inverse passes' last reads of LDS are done
+  if constexpr (RI != RF || LOI != LOF) {
+    exchange<S, LOI, RI, LOF, RF, IntAr>(v, lds, tid);
+    __syncthreads();
+  }
+  typename ArT::T y[E];
+#pragma unroll
+  for (int i = 0; i < E; i++) y[i] = art.from_res(v[i]);
+  fwd_passes<S, Sp::LOGMA, 0, ArT, true>(y, lds, Wf, art, tid, 0, &twf);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::flo(S::NP - 1), G = E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) tout[col_g<LOGN>(gidx(gi, c, LO, R), sub)] = ArT::bits(y[u * (1 << R) + c]);
+    }
+  }
+}
+
+template <int LOGN, int PRO>
+__device__ __forceinline__ void cols_fused_dispatch(const u64* tin, u64* tout, const PrimeDev* __restrict__ primes,
+                                                    int ps, int pt, const NttTables& tabs, u64 hs, u64 hq_t,
+                                                    int sub, u64* lds) {
+  constexpr int N = 1 << LOGN;
+  const PrimeDev Ps = primes[ps], Pt = primes[pt];
+  const ulonglong2* Ii = reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)ps * N;
+  const double2* If = reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)ps * N;
+  const ulonglong2* Fi = reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)pt * N;
+  const double2* Ff = reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)pt * N;
+  if (Ps.use_fp) {
+    if (Pt.use_fp)
+      cols_fused_body<LOGN, PRO, FpAr, FpAr>(tin, tout, Ps, Pt, If, Ff, hs, hq_t, sub, lds);
+    else
+      cols_fused_body<LOGN, PRO, FpAr, IntAr>(tin, tout, Ps, Pt, If, Fi, hs, hq_t, sub, lds);
+  } else {
+    if (Pt.use_fp)
+      cols_fused_body<LOGN, PRO, IntAr, FpAr>(tin, tout, Ps, Pt, Ii, Ff, hs, hq_t, sub, lds);
+    else
+      cols_fused_body<LOGN, PRO, IntAr, IntAr>(tin, tout, Ps, Pt, Ii, Fi, hs, hq_t, sub, lds);
+  }
+}
+
+// ModUp: job w = (b*Lp + j)*Lp + tt lifts digit j of item b to modulus
+// t = tt (tt < j) or tt + 1 (t = Lp is the special prime)
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_ks_modup_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Split<LOGN>::SA::lds_words()];
+  const int w = blockIdx.x / Split<LOGN>::WA;
+  const int sub = blockIdx.x - w * Split<LOGN>::WA;
+  const int a = w / J.Lp, tt = w - a * J.Lp;
+  const int j = a % J.Lp;
+  const int t = tt < j ? tt : tt + 1;
+  const int pt = t < J.Lp ? t : J.special;
+  const u64 hs = (primes[j].q - 1) >> 1;
+  cols_fused_dispatch<LOGN, PRO_CENTRED_LIFT>(J.t1 + (size_t)a * N, J.t2 + (size_t)w * N, primes, j, pt, tabs, hs, 0,
+                                              sub, lds);
+}
+
+// ModDown columns: job w = a*Lp + t, a = 2b + k
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_ks_moddown_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Split<LOGN>::SA::lds_words()];
+  const int w = blockIdx.x / Split<LOGN>::WA;
+  const int sub = blockIdx.x - w * Split<LOGN>::WA;
+  const int a = w / J.Lp, t = w - a * J.Lp;
+  cols_fused_dispatch<LOGN, PRO_ROUNDDIV_LIFT>(J.t3 + (size_t)a * N, J.t4 + (size_t)w * N, primes, J.special, t,
+                                               tabs, J.h_src, J.hq[t], sub, lds);
+}
+
+// inner products of item b's digits with its key at modulus t for poly k, at
+// the E limb indices idx[] (Montgomery form keys: a lazy 128-bit sum of at
+// most 8 products, one reduction per group).  The E elements advance
+// together so that each digit issues 2E independent loads.
+template <int E>
+__device__ __forceinline__ void ks_inner(const KsJob& J, const PrimeDev& P, int log_n, int b, int k, int t, int kt,
+                                         const int (&idx)[E], bool diag, u64 (&r)[E]) {
+  const size_t n = (size_t)1 << log_n;
+  const int km = J.km[b];
+  const u64* __restrict__ ext = J.ext + ((size_t)b * J.Lp * J.nm + t) * n;
+  const u64* __restrict__ kp = J.key[b] + ((size_t)k * km + kt) * n;
+  const size_t ks_j = 2 * (size_t)km * n, es_j = (size_t)J.nm * n;
+  const u64 g = J.gal[b];
+  u64 dv[E];
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    dv[e] = diag ? J.d[b * J.ds + (size_t)t * n + (g != 1 ? gal_src(idx[e], log_n, g) : idx[e])] : 0;
+    r[e] = 0;
+  }
+  for (int j0 = 0; j0 < J.Lp; j0 += 8) {
+    U128 acc[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) acc[e] = U128{0, 0};
+    const int j1 = min(J.Lp, j0 + 8);
+    for (int j = j0; j < j1; j++) {
+      u64 dj[E], kj[E];
+#pragma unroll
+      for (int e = 0; e < E; e++) {
+        dj[e] = (diag && j == t) ? dv[e] : ext[j * es_j + idx[e]];
+        kj[e] = kp[j * ks_j + idx[e]];
+      }
+#pragma unroll
+      for (int e = 0; e < E; e++) acc[e] = add128(acc[e], mul_wide(dj[e], kj[e]));
+    }
+#pragma unroll
+    for (int e = 0; e < E; e++) r[e] = addmod(r[e], mont_reduce(acc[e], P), P.q);
+  }
+}
+
+// ModDown, special modulus: inner product and inverse block phase -> t3
+template <int LOGN, class Ar>
+__device__ __forceinline__ void special_blocks_body(const KsJob& J, const typename Ar::TW* __restrict__ W,
+                                                    const PrimeDev& P, int a, int sub, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  constexpr int E = S::E;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const int toff = sub << Sp::LOGMB;
+  const int b = a >> 1, k = a & 1;
+  PassTw<S, LOGN, 0, false, Ar> tw0;
+  tw0.load(W, tid, toff);
+  typename Ar::T x[E];
+  {
+    constexpr int R = S::bits(0), G = E >> R;
+    int idx[E];
+    u64 v[E];
+#pragma unroll
+    for (int u = 0; u < G; u++)
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) idx[u * (1 << R) + c] = toff + (((tid + S::T * u) << R) | c);
+    ks_inner<E>(J, P, LOGN, b, k, J.Lp, J.km[b] - 1, idx, false, v);
+#pragma unroll
+    for (int i = 0; i < E; i++) x[i] = ar.from_res(v[i]);
+  }
+  inv_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = E >> R;
+    u64* __restrict__ t = J.t3 + ((size_t)a << LOGN) + toff;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) t[gidx(gi, c, LO, R)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+k_ks_special_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
+  const int a = blockIdx.x / Split<LOGN>::WB;
+  const int sub = blockIdx.x - a * Split<LOGN>::WB;
+  const PrimeDev P = primes[J.special];
+  if (P.use_fp)
+    special_blocks_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)J.special * N, P, a,
+                                    sub, lds);
+  else
+    special_blocks_body<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)J.special * N, P,
+                                     a, sub, lds);
+}
+
+// ModDown, data limb t of poly a = 2b + k: forward block phase of the lifted
+// divisor, then (inner product - NTT(r - h)) * p^-1 + addends -> out
+template <int LOGN, class Ar>
+__device__ __forceinline__ void moddown_blocks_body(const KsJob& J, const typename Ar::TW* __restrict__ W,
+                                                    const PrimeDev& P, int w, int a, int t, int sub, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  constexpr int E = S::E;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const int toff = sub << Sp::LOGMB;
+  const int b = a >> 1, k = a & 1;
+  const u64 q = P.q;
+  PassTw<S, LOGN, 0, true, Ar> tw0;
+  tw0.load(W, tid, toff);
+  const u64* __restrict__ tin = J.t4 + ((size_t)w << LOGN) + toff;
+  typename Ar::T x[E];
+  {
+    constexpr int R = S::bits(0), LO = S::flo(0), G = E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = Ar::unbits(tin[gidx(gi, c, LO, R)]);
+    }
+  }
+  // the data-limb inner products at this thread's output indices, computed
+  // before the transform so that their loads overlap it
+  constexpr int RL = S::bits(S::NP - 1), GL = E >> RL;
+  int oidx[E];
+  u64 uu[E];
+#pragma unroll
+  for (int u = 0; u < GL; u++)
+#pragma unroll
+    for (int c = 0; c < (1 << RL); c++) oidx[u * (1 << RL) + c] = toff + (((tid + S::T * u) << RL) | c);
+  ks_inner<E>(J, P, LOGN, b, k, t, t, oidx, true, uu);
+  fwd_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), G = E >> R;
+    u64* __restrict__ dst = J.out + a * J.oa + ((size_t)t << LOGN);
+    const u64* __restrict__ ad =
+        (J.add && !(J.add_even_only && (a & 1))) ? J.add + a * J.aa + ((size_t)t << LOGN) : nullptr;
+    const u64* __restrict__ ad2 = J.add2 ? J.add2 + a * J.a2a + ((size_t)t << LOGN) : nullptr;
+    const u64 ag = J.add_gather ? J.gal[b] : 1;
+    const u64 inv = J.inv[t], inv_sh = J.inv_sh[t];
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) {
+        const int idx = toff + ((gi << R) | c);
+        u64 v = shoup(submod(uu[u * (1 << R) + c], ar.fwd_res(x[u * (1 << R) + c]), q), inv, inv_sh, q);
+        if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
+        if (ad2) v = addmod(v, ad2[idx], q);
+        dst[idx] = v;
+      }
+    }
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+k_ks_moddown_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
+  const int w = blockIdx.x / Split<LOGN>::WB;
+  const int sub = blockIdx.x - w * Split<LOGN>::WB;
+  const int a = w / J.Lp, t = w - a * J.Lp;
+  const PrimeDev P = primes[t];
+  if (P.use_fp)
+    moddown_blocks_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P, w, a, t,
+                                    sub, lds);
+  else
+    moddown_blocks_body<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P, w, a, t,
+                                     sub, lds);
+}
 
 // ---------------- hoisted rotations: ModDown + multiply-accumulate ----------------
 // ModDown of each item (an NTT of its special-prime limb, lifted) with the
@@ -854,7 +1155,7 @@ hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const NttTables& 
   const int jobs = n_jobs(J);
   if (jobs <= 0) return hipSuccess;
   if (use_split(J, tabs, LOGN)) {
-    hipLaunchKernelGGL((k_ntt_inv_1<LOGN, GATHER>), dim3(jobs * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
+    hipLaunchKernelGGL((k_ntt_inv_1<LOGN, GATHER, 0>), dim3(jobs * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ntt_inv_2<LOGN>), dim3(jobs * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes, tabs);
@@ -898,7 +1199,123 @@ hipError_t inv_dispatch(const NttJob& J, const PrimeDev* primes, const NttTables
   return J.gather_src ? inv_launch<LOGN, true>(J, primes, tabs, st) : inv_launch<LOGN, false>(J, primes, tabs, st);
 }
 
+template <int LOGN>
+hipError_t inv_blocks_launch(const NttJob& J, const PrimeDev* primes, const NttTables& tabs, int tag,
+                             hipStream_t st) {
+  using Sp = Split<LOGN>;
+  const int jobs = n_jobs(J);
+  if (jobs <= 0) return hipSuccess;
+  const dim3 grid(jobs * Sp::WB), blk(Sp::SB::T);
+  if (tag == 2)
+    hipLaunchKernelGGL((k_ntt_inv_1<LOGN, false, 2>), grid, blk, 0, st, J, primes, tabs);
+  else if (J.gather_src)
+    hipLaunchKernelGGL((k_ntt_inv_1<LOGN, true, 1>), grid, blk, 0, st, J, primes, tabs);
+  else
+    hipLaunchKernelGGL((k_ntt_inv_1<LOGN, false, 1>), grid, blk, 0, st, J, primes, tabs);
+  return hipGetLastError();
+}
+
+template <int LOGN>
+hipError_t fwd_blocks_launch(int pro, int epi, const NttJob& J, const PrimeDev* primes, const NttTables& tabs,
+                             hipStream_t st) {
+  using Sp = Split<LOGN>;
+  const int jobs = n_jobs(J);
+  if (jobs <= 0) return hipSuccess;
+  const dim3 grid(jobs * Sp::WB), blk(Sp::SB::T);
+  if (pro == PRO_PLAIN && epi == EPI_STORE)
+    hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, PRO_PLAIN, EPI_STORE>), grid, blk, 0, st, J, primes, tabs);
+  else if (pro == PRO_CENTRED_LIFT && epi == EPI_STORE)
+    hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, PRO_CENTRED_LIFT, EPI_STORE>), grid, blk, 0, st, J, primes, tabs);
+  else if (pro == PRO_ROUNDDIV_LIFT && epi == EPI_ROUNDDIV)
+    hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV>), grid, blk, 0, st, J, primes, tabs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int LOGN>
+hipError_t ks_launch(int which, const KsJob& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+  using Sp = Split<LOGN>;
+  const int B = J.B, Lp = J.Lp;
+  if (B <= 0 || Lp <= 0) return hipSuccess;
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL((k_ks_modup_cols<LOGN>), dim3(B * Lp * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
+                         tabs);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_ks_special_blocks<LOGN>), dim3(2 * B * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes,
+                         tabs);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_ks_moddown_cols<LOGN>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
+                         tabs);
+      break;
+    default:
+      hipLaunchKernelGGL((k_ks_moddown_blocks<LOGN>), dim3(2 * B * Lp * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes,
+                         tabs);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_ntt_inv_blocks(int log_n, const NttJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                 int tag, hipStream_t st) {
+  if (tag == 2 && job.gather_src) return hipErrorInvalidValue;
+#define C_(L) inv_blocks_launch<L>(job, primes, tabs, tag, st)
+  switch (log_n) {
+    case 10: return C_(10);
+    case 11: return C_(11);
+    case 12: return C_(12);
+    case 13: return C_(13);
+    case 14: return C_(14);
+    default: return hipErrorInvalidValue;
+  }
+#undef C_
+}
+
+hipError_t launch_ntt_fwd_blocks(int log_n, int pro, int epi, const NttJob& job, const PrimeDev* primes,
+                                 const NttTables& tabs, hipStream_t st) {
+#define C_(L) fwd_blocks_launch<L>(pro, epi, job, primes, tabs, st)
+  switch (log_n) {
+    case 10: return C_(10);
+    case 11: return C_(11);
+    case 12: return C_(12);
+    case 13: return C_(13);
+    case 14: return C_(14);
+    default: return hipErrorInvalidValue;
+  }
+#undef C_
+}
+
+static hipError_t ks_any(int which, int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                         hipStream_t st) {
+  switch (log_n) {
+    case 10: return ks_launch<10>(which, job, primes, tabs, st);
+    case 11: return ks_launch<11>(which, job, primes, tabs, st);
+    case 12: return ks_launch<12>(which, job, primes, tabs, st);
+    case 13: return ks_launch<13>(which, job, primes, tabs, st);
+    case 14: return ks_launch<14>(which, job, primes, tabs, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_ks_modup_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                hipStream_t st) {
+  return ks_any(0, log_n, job, primes, tabs, st);
+}
+hipError_t launch_ks_special_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                    hipStream_t st) {
+  return ks_any(1, log_n, job, primes, tabs, st);
+}
+hipError_t launch_ks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                  hipStream_t st) {
+  return ks_any(2, log_n, job, primes, tabs, st);
+}
+hipError_t launch_ks_moddown_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                    hipStream_t st) {
+  return ks_any(3, log_n, job, primes, tabs, st);
+}
 
 hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job, const PrimeDev* primes,
                           const NttTables& tabs, hipStream_t st) {
