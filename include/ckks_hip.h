@@ -137,6 +137,8 @@ he_status he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
 he_status he_negate(he_ctx* ctx, const he_ct* a, he_ct** out);
 /* plaintext at the ciphertext's scale, level >= the ciphertext's */
 he_status he_add_plain(he_ctx* ctx, const he_ct* a, const he_pt* p, he_ct** out);
+/* c0 - p (poly 0 only), the plaintext subtracted */
+he_status he_sub_plain(he_ctx* ctx, const he_ct* a, const he_pt* p, he_ct** out);
 /* ciphertext x plaintext; scale multiplies; rescales if auto_rescale */
 he_status he_mul_plain(he_ctx* ctx, const he_ct* a, const he_pt* p, he_ct** out);
 /* tensor product, relinearisation with the s^2 key; rescales if auto_rescale */
@@ -150,6 +152,24 @@ he_status he_drop_to(he_ctx* ctx, const he_ct* a, int32_t level, he_ct** out);
 /* left rotation of the slots by step: X -> X^(5^step mod 2N) and a key
  * switch with the Galois key of that step (HE_ENOKEY if none). */
 he_status he_rotate(he_ctx* ctx, const he_ct* a, int32_t step, he_ct** out);
+
+/* ---- power and polynomial evaluation (section 3: minimum-depth circuits;
+ * appendix, table of encrypted operations) ----
+ * Every product is relinearised and rescaled (whatever auto_rescale says);
+ * operands at different levels are aligned by dropping limbs (exact). */
+/* a^k, k >= 1, at multiplicative depth ceil(log2 k): the squares a^(2^i) of
+ * the set bits of k, then the two factors of least depth (ties: smaller
+ * exponent) multiplied until one is left.  HE_EINVAL for k = 0, HE_ELEVEL
+ * when the chain is too short. */
+he_status he_power(he_ctx* ctx, const he_ct* a, uint32_t k, he_ct** out);
+/* sum_i coeffs[i] a^i (n_coeffs = degree + 1).  Each a^i with i >= 1 and
+ * coeffs[i] != 0 comes from the power circuit (squares shared), is
+ * multiplied by the constant coeffs[i] encoded at scale Delta*q_l/scale(a^i)
+ * at its level l and rescaled, so every term lands at scale Delta; terms are
+ * cut to the lowest level, summed in increasing i, and coeffs[0] is added.
+ * Depth ceil(log2 d) + 1.  HE_EINVAL when no term has i >= 1. */
+he_status he_polyval(he_ctx* ctx, const he_ct* a, const double* coeffs, size_t n_coeffs,
+                     he_ct** out);
 
 /* ---- batches (the key switch of section 3 applied to many ciphertexts) ----
  * n operations on operands that all sit at one level (HE_ELEVEL otherwise).

@@ -967,6 +967,23 @@ orc_ct* orc_add_plain(const orc_ctx* c, const orc_ct* a, const orc_pt* p) {
   return r;
 }
 
+/* c0 - p: the plaintext subtracted from the first polynomial (section 3,  */
+/* element-wise operations with plain vectors)                            */
+orc_ct* orc_sub_plain(const orc_ctx* c, const orc_ct* a, const orc_pt* p) {
+  if (!scales_match(a->scale, p->scale)) FAIL(ORC_ESCALE);
+  if (p->level < a->level) FAIL(ORC_ELEVEL);
+  orc_ct* r = orc_ct_new(c, a->level, a->scale);
+  if (!r) return NULL;
+  memcpy(r->data, a->data, sizeof(u64) * 2 * (size_t)(a->level + 1) * c->n);
+  for (int i = 0; i <= a->level; i++) {
+    u64 q = c->q[i];
+    u64* z = ct_limb(c, r, 0, i);
+    const u64* y = p->data + (size_t)i * c->n;
+    for (int t = 0; t < c->n; t++) z[t] = subm(z[t], y[t], q);
+  }
+  return r;
+}
+
 orc_ct* orc_mul_plain(const orc_ctx* c, const orc_ct* a, const orc_pt* p) {
   if (p->level < a->level) FAIL(ORC_ELEVEL);
   int n = c->n;

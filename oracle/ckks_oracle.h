@@ -125,6 +125,7 @@ orc_ct* orc_add(const orc_ctx*, const orc_ct*, const orc_ct*);
 orc_ct* orc_sub(const orc_ctx*, const orc_ct*, const orc_ct*);
 orc_ct* orc_negate(const orc_ctx*, const orc_ct*);
 orc_ct* orc_add_plain(const orc_ctx*, const orc_ct*, const orc_pt*);
+orc_ct* orc_sub_plain(const orc_ctx*, const orc_ct*, const orc_pt*);
 orc_ct* orc_mul_plain(const orc_ctx*, const orc_ct*, const orc_pt*);
 /* (d0, d1, d2) tensor followed by relinearisation */
 orc_ct* orc_mul_relin(const orc_ctx*, const orc_ct*, const orc_ct*);

@@ -86,6 +86,7 @@ def lib():
         "orc_sub": (_ctp, [C.c_void_p, _ctp, _ctp]),
         "orc_negate": (_ctp, [C.c_void_p, _ctp]),
         "orc_add_plain": (_ctp, [C.c_void_p, _ctp, _ctp]),
+        "orc_sub_plain": (_ctp, [C.c_void_p, _ctp, _ctp]),
         "orc_mul_plain": (_ctp, [C.c_void_p, _ctp, _ctp]),
         "orc_mul_relin": (_ctp, [C.c_void_p, _ctp, _ctp]),
         "orc_rescale": (_ctp, [C.c_void_p, _ctp]),
@@ -274,6 +275,9 @@ class Oracle:
     def add_plain(self, a, p):
         return self._wrap(lib().orc_add_plain(self.h, a.ptr, p.ptr), 2, "add_plain")
 
+    def sub_plain(self, a, p):
+        return self._wrap(lib().orc_sub_plain(self.h, a.ptr, p.ptr), 2, "sub_plain")
+
     def mul_plain(self, a, p):
         return self._wrap(lib().orc_mul_plain(self.h, a.ptr, p.ptr), 2, "mul_plain")
 
@@ -295,6 +299,66 @@ class Oracle:
         self._chk(lib().orc_key_switch(self.h, kind, step, _ptr(d, C.c_uint64), level,
                                        _ptr(out, C.c_uint64)), "key_switch")
         return out
+
+    # -- power and polynomial evaluation (section 3: minimum-depth circuits;
+    # the circuits are the readings stated in power_plan / polyval) --
+    def _mul_rescale(self, a, b):
+        la, lb = a.level, b.level
+        if la > lb:
+            a = self.drop_to(a, lb)
+        elif lb > la:
+            b = self.drop_to(b, la)
+        return self.rescale(self.mul_relin(a, b))
+
+    def power(self, a, k, squares=None):
+        """a^k with multiplicative depth ceil(log2 k): the squares a^(2^i) of
+        the set bits of k, then the two factors of least depth (ties: the
+        smaller exponent) multiplied until one is left; every product is
+        relinearised and rescaled.  `squares` caches a^(2^i) across calls."""
+        k = int(k)
+        if k < 1:
+            raise OracleError(ORC_EINVAL, "power: exponent %d < 1" % k)
+        sq = squares if squares is not None else {}
+        sq.setdefault(0, a)
+        top = k.bit_length() - 1
+        for i in range(1, top + 1):
+            if i not in sq:
+                sq[i] = self._mul_rescale(sq[i - 1], sq[i - 1])
+        # (depth, exponent, ciphertext)
+        fac = [(i, 1 << i, sq[i]) for i in range(top + 1) if (k >> i) & 1]
+        while len(fac) > 1:
+            fac.sort(key=lambda f: (f[0], f[1]))
+            (da, ea, ca), (db, eb, cb) = fac[0], fac[1]
+            fac = fac[2:] + [(max(da, db) + 1, ea + eb, self._mul_rescale(ca, cb))]
+        return fac[0][2]
+
+    def polyval(self, a, coeffs):
+        """sum_i coeffs[i] a^i: each a^i (i >= 1, coeffs[i] != 0) from the
+        power circuit, times the constant coeffs[i] encoded at scale
+        Delta * q_l / scale(a^i) at the level l of a^i and rescaled, so that
+        every term lands at scale Delta; the terms are cut to the lowest
+        level and summed in increasing i, then coeffs[0] is added at that
+        scale.  Depth ceil(log2 d) + 1."""
+        cs = [float(x) for x in coeffs]
+        idx = [i for i in range(1, len(cs)) if cs[i] != 0.0]
+        if not idx:
+            raise OracleError(ORC_EINVAL, "polyval: no non-constant term")
+        half = self.n // 2
+        sq = {}
+        terms = []
+        for i in idx:
+            x = self.power(a, i, sq)
+            ps = self.scale * self.primes[x.level] / x.scale
+            p = self.encode(np.full(half, cs[i]), ps, x.level)
+            terms.append(self.rescale(self.mul_plain(x, p)))
+        low = min(t.level for t in terms)
+        terms = [t if t.level == low else self.drop_to(t, low) for t in terms]
+        acc = terms[0]
+        for t in terms[1:]:
+            acc = self.add(acc, t)
+        if cs[0] != 0.0:
+            acc = self.add_plain(acc, self.encode(np.full(half, cs[0]), acc.scale, acc.level))
+        return acc
 
     def sum_slots(self, a, n):
         return self._wrap(lib().orc_sum_slots(self.h, a.ptr, n), 2, "sum_slots")

@@ -60,6 +60,9 @@ _SIGS = {
     "he_negate": (C.c_int32, [_vp, _vp, _pvp]),
     "he_add_plain": (C.c_int32, [_vp, _vp, _vp, _pvp]),
     "he_mul_plain": (C.c_int32, [_vp, _vp, _vp, _pvp]),
+    "he_sub_plain": (C.c_int32, [_vp, _vp, _vp, _pvp]),
+    "he_power": (C.c_int32, [_vp, _vp, C.c_uint32, _pvp]),
+    "he_polyval": (C.c_int32, [_vp, _vp, _dp, C.c_size_t, _pvp]),
     "he_mul_relin": (C.c_int32, [_vp, _vp, _vp, _pvp]),
     "he_square": (C.c_int32, [_vp, _vp, _pvp]),
     "he_rescale": (C.c_int32, [_vp, _vp, _pvp]),
@@ -297,6 +300,7 @@ he_add = _binary("he_add")
 he_sub = _binary("he_sub")
 he_add_plain = _binary("he_add_plain")
 he_mul_plain = _binary("he_mul_plain")
+he_sub_plain = _binary("he_sub_plain")
 he_mul_relin = _binary("he_mul_relin")
 he_negate = _unary("he_negate")
 he_square = _unary("he_square")
@@ -309,6 +313,15 @@ def he_drop_to(ctx, a, level):
 
 def he_rotate(ctx, a, step):
     return _new(Ct, ctx, lib().he_rotate, "he_rotate", ctx.ptr, a.ptr, int(step))
+
+
+def he_power(ctx, a, k):
+    return _new(Ct, ctx, lib().he_power, "he_power", ctx.ptr, a.ptr, int(k))
+
+
+def he_polyval(ctx, a, coeffs):
+    cs = np.ascontiguousarray(coeffs, dtype=np.float64)
+    return _new(Ct, ctx, lib().he_polyval, "he_polyval", ctx.ptr, a.ptr, _ptr(cs, C.c_double), cs.size)
 
 
 def he_mul_relin_many(ctx, a, b):

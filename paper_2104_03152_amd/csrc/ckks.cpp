@@ -693,9 +693,8 @@ he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
     // per poly: the dropped limb and the l kept limbs read, l limbs written
     Prof pr(c, "rescale", 2.0 * n_ct * (1 + l), 8.0 * n * 2 * n_ct * (2.0 * l + 1));
     hipError_t e = launch_ntt_inv_blocks(c->log_n, J, c->d_primes, c->tabs, 2, c->st);
-    if (e == hipSuccess) e = launch_ks_moddown_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
-    if (e == hipSuccess)
-      e = launch_ntt_fwd_blocks(c->log_n, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV, F, c->d_primes, c->tabs, c->st);
+    if (e == hipSuccess) e = launch_rescale_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+    if (e == hipSuccess) e = launch_ntt_fwd_blocks(c->log_n, FAM_RESCALE, EPI_ROUNDDIV, F, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "fused rescale: %s", hipGetErrorString(e));
     return HE_OK;
   }
@@ -1293,7 +1292,7 @@ he_status he_negate(he_ctx* c, const he_ct* a, he_ct** out) {
   return HE_OK;
 }
 
-he_status he_add_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
+static he_status add_plain_impl(he_ctx* c, const he_ct* a, const he_pt* p, int neg, he_ct** out) {
   if (!c || !a || !p || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (!scales_match(a->scale, p->scale)) return fail(HE_ESCALE, "scales %g and %g differ", a->scale, p->scale);
@@ -1301,13 +1300,21 @@ he_status he_add_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
   he_ct* r = nullptr;
   TRY(new_ct(c, a->level, a->scale, &r));
   Prof pr(c, "pointwise");
-  hipError_t e = launch_add_plain(c->log_n, a->d, p->d, r->d, 2, mods_range(a->level + 1), c->d_primes, c->st);
+  hipError_t e =
+      launch_add_plain(c->log_n, a->d, p->d, r->d, 2, mods_range(a->level + 1), c->d_primes, c->st, neg);
   if (e != hipSuccess) {
     he_ct_free(r);
     return fail(HE_EHIP, "add_plain: %s", hipGetErrorString(e));
   }
   *out = r;
   return HE_OK;
+}
+
+he_status he_add_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
+  return add_plain_impl(c, a, p, 0, out);
+}
+he_status he_sub_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
+  return add_plain_impl(c, a, p, 1, out);
 }
 
 static he_status mul_plain_raw(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
@@ -1428,6 +1435,166 @@ he_status he_rotate(he_ctx* c, const he_ct* a, int32_t step, he_ct** out) {
   if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   return rotate_raw(c, a, step, out);
+}
+
+// ---------------------------------------------------------------- power, polyval
+// a*b (levels aligned by dropping), relinearised and rescaled
+static he_status mul_rescale(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
+  he_ct* r = nullptr;
+  TRY(mul_relin_raw(c, a, b, &r));
+  he_status s = rescale_raw(c, r, out);
+  he_ct_free(r);
+  return s;
+}
+
+// cache of the squares a^(2^i); entry 0 is the input (not owned)
+struct Squares {
+  std::vector<he_ct*> v;
+  ~Squares() {
+    for (size_t i = 1; i < v.size(); i++) he_ct_free(v[i]);
+  }
+};
+
+// a^k at multiplicative depth ceil(log2 k): the squares of the set bits of
+// k, then the two factors of least (depth, exponent) multiplied until one is
+// left.  *owned tells whether *out is a new ciphertext or a cached square.
+static he_status power_impl(he_ctx* c, const he_ct* a, long long k, Squares& sq, he_ct** out, bool* owned) {
+  *out = nullptr;
+  if (k < 1) return fail(HE_EINVAL, "power: exponent %lld < 1", k);
+  if (sq.v.empty()) sq.v.push_back(const_cast<he_ct*>(a));
+  int top = 0;
+  while ((k >> (top + 1)) > 0) top++;
+  while ((int)sq.v.size() <= top) {
+    he_ct* r = nullptr;
+    TRY(mul_rescale(c, sq.v.back(), sq.v.back(), &r));
+    sq.v.push_back(r);
+  }
+  struct Fac {
+    int depth;
+    long long e;
+    he_ct* ct;
+    bool own;
+  };
+  std::vector<Fac> fac;
+  for (int i = 0; i <= top; i++)
+    if ((k >> i) & 1) fac.push_back(Fac{i, 1LL << i, sq.v[i], false});
+  he_status s = HE_OK;
+  while (fac.size() > 1 && s == HE_OK) {
+    std::stable_sort(fac.begin(), fac.end(), [](const Fac& x, const Fac& y) {
+      return x.depth != y.depth ? x.depth < y.depth : x.e < y.e;
+    });
+    const Fac fa = fac[0], fb = fac[1];
+    he_ct* r = nullptr;
+    s = mul_rescale(c, fa.ct, fb.ct, &r);
+    if (fa.own) he_ct_free(fa.ct);
+    if (fb.own) he_ct_free(fb.ct);
+    fac.erase(fac.begin(), fac.begin() + 2);
+    if (s == HE_OK) fac.push_back(Fac{std::max(fa.depth, fb.depth) + 1, fa.e + fb.e, r, true});
+  }
+  if (s != HE_OK) {
+    for (auto& f : fac)
+      if (f.own) he_ct_free(f.ct);
+    return s;
+  }
+  *out = fac[0].ct;
+  *owned = fac[0].own;
+  return HE_OK;
+}
+
+he_status he_power(he_ctx* c, const he_ct* a, uint32_t k, he_ct** out) {
+  if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  Squares sq;
+  he_ct* r = nullptr;
+  bool owned = false;
+  TRY(power_impl(c, a, k, sq, &r, &owned));
+  if (owned) {
+    *out = r;
+    return HE_OK;
+  }
+  return drop_copy(c, r, r->level, out);  // k a power of two: a cached square
+}
+
+// sum_i coeffs[i] a^i: each a^i (i >= 1, coeffs[i] != 0) from the power
+// circuit times the constant coeffs[i] encoded at scale Delta * q_l /
+// scale(a^i) at a^i's level l and rescaled (every term at scale Delta), cut
+// to the lowest level and summed in increasing i; coeffs[0] added last.
+he_status he_polyval(he_ctx* c, const he_ct* a, const double* coeffs, size_t n_coeffs, he_ct** out) {
+  if (!c || !a || !out || (n_coeffs && !coeffs)) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  std::vector<size_t> idx;
+  for (size_t i = 1; i < n_coeffs; i++)
+    if (coeffs[i] != 0.0) idx.push_back(i);
+  if (idx.empty()) return fail(HE_EINVAL, "polyval: no non-constant term");
+  const size_t half = (size_t)c->n / 2;
+  Squares sq;
+  std::vector<he_ct*> terms;
+  auto free_terms = [&]() {
+    for (he_ct* t : terms) he_ct_free(t);
+    terms.clear();
+  };
+  for (size_t i : idx) {
+    he_ct* x = nullptr;
+    bool owned = false;
+    he_status s = power_impl(c, a, (long long)i, sq, &x, &owned);
+    he_pt* p = nullptr;
+    if (s == HE_OK) {
+      const double ps = c->scale * (double)c->q[x->level] / x->scale;
+      std::vector<double> v(half, coeffs[i]);
+      s = encode_impl(c, v.data(), half, ps, x->level, &p);
+    }
+    he_ct* m = nullptr;
+    if (s == HE_OK) s = mul_plain_raw(c, x, p, &m);
+    he_pt_free(p);
+    if (owned) he_ct_free(x);
+    he_ct* t = nullptr;
+    if (s == HE_OK) s = rescale_raw(c, m, &t);
+    he_ct_free(m);
+    if (s != HE_OK) {
+      free_terms();
+      return s;
+    }
+    terms.push_back(t);
+  }
+  int low = terms[0]->level;
+  for (he_ct* t : terms) low = std::min(low, t->level);
+  he_ct* acc = nullptr;
+  he_status s = HE_OK;
+  for (size_t j = 0; j < terms.size() && s == HE_OK; j++) {
+    he_ct* t = terms[j];
+    he_ct* td = nullptr;
+    if (t->level != low) {
+      s = drop_copy(c, t, low, &td);
+      if (s != HE_OK) break;
+      t = td;
+    }
+    if (!acc) {
+      s = drop_copy(c, t, low, &acc);
+    } else {
+      he_ct* r = nullptr;
+      s = he_add(c, acc, t, &r);
+      he_ct_free(acc);
+      acc = r;
+    }
+    he_ct_free(td);
+  }
+  free_terms();
+  if (s == HE_OK && coeffs[0] != 0.0) {
+    std::vector<double> v(half, coeffs[0]);
+    he_pt* p = nullptr;
+    s = encode_impl(c, v.data(), half, acc->scale, acc->level, &p);
+    he_ct* r = nullptr;
+    if (s == HE_OK) s = he_add_plain(c, acc, p, &r);
+    he_pt_free(p);
+    he_ct_free(acc);
+    acc = r;
+  }
+  if (s != HE_OK) {
+    he_ct_free(acc);
+    return s;
+  }
+  *out = acc;
+  return HE_OK;
 }
 
 // ---------------------------------------------------------------- batches

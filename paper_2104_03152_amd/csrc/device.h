@@ -45,6 +45,9 @@ struct NttJob {
 
 #define HE_MAX_BATCH 32
 enum { PRO_PLAIN = 0, PRO_CENTRED_LIFT = 1, PRO_ROUNDDIV_LIFT = 2 };
+// launch_ntt_fwd_blocks: the last kernel of a fused rescale (a divide-and-
+// round epilogue, named apart from the key-switch ModDown)
+enum { FAM_RESCALE = 3 };
 enum { EPI_STORE = 0, EPI_ROUNDDIV = 1 };
 
 // forward (lazy Cooley-Tukey, bit-reversed output) and inverse (Gentleman-
@@ -118,6 +121,9 @@ hipError_t launch_ks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* p
                                   hipStream_t st);
 hipError_t launch_ks_moddown_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                     hipStream_t st);
+// the ModDown column kernel run for a rescale
+hipError_t launch_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                               hipStream_t st);
 
 // ---- samplers (ChaCha20 streams) ----
 // signed small polynomial (ternary: kind 0, Gaussian CDT: kind 1) reduced into
@@ -145,10 +151,10 @@ hipError_t launch_addsub(int log_n, int op, const u64* a, const u64* b, u64* out
 hipError_t launch_mul_plain(int log_n, const u64* a, const u64* p, u64* out,
                             int n_poly, const ModList& mods, const PrimeDev* primes,
                             hipStream_t st);
-// add p to poly 0 only (a and out: [n_poly][n][N])
+// add p to poly 0 only, or subtract it (neg) (a and out: [n_poly][n][N])
 hipError_t launch_add_plain(int log_n, const u64* a, const u64* p, u64* out,
                             int n_poly, const ModList& mods, const PrimeDev* primes,
-                            hipStream_t st);
+                            hipStream_t st, int neg = 0);
 // tensor: (d0, d1) -> out01 [2][n][N], d2 -> out2 [n][N]
 hipError_t launch_tensor(int log_n, const u64* a, const u64* b, u64* out01,
                          u64* out2, const ModList& mods, const PrimeDev* primes,

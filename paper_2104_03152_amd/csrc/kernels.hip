@@ -132,14 +132,15 @@ __global__ void k_mul_plain(int n, const u64* __restrict__ a, const u64* __restr
 }
 
 __global__ void k_add_plain(int n, const u64* __restrict__ a, const u64* __restrict__ p, u64* __restrict__ out,
-                            long long total, int n_limbs, ModList mods, const PrimeDev* __restrict__ primes) {
+                            long long total, int n_limbs, ModList mods, const PrimeDev* __restrict__ primes,
+                            int neg) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const long long row = e / n;
   const int limb = (int)(row % n_limbs);
   const u64 q = primes[mods.p[limb]].q;
   const long long per_poly = (long long)n_limbs * n;
-  out[e] = (e < per_poly) ? addmod(a[e], p[e], q) : a[e];
+  out[e] = (e < per_poly) ? (neg ? submod(a[e], p[e], q) : addmod(a[e], p[e], q)) : a[e];
 }
 
 __global__ void k_tensor(int n, const u64* __restrict__ a, const u64* __restrict__ b, u64* __restrict__ out01,
@@ -383,11 +384,11 @@ hipError_t launch_mul_plain(int log_n, const u64* a, const u64* p, u64* out, int
 }
 
 hipError_t launch_add_plain(int log_n, const u64* a, const u64* p, u64* out, int n_poly, const ModList& mods,
-                            const PrimeDev* primes, hipStream_t st) {
+                            const PrimeDev* primes, hipStream_t st, int neg) {
   const int n = 1 << log_n;
   const long long total = (long long)n_poly * mods.n * n;
   hipLaunchKernelGGL(k_add_plain, grid_for(total), dim3(BLK), 0, st, n, a, p, out, total, mods.n, mods,
-                     primes);
+                     primes, neg);
   return hipGetLastError();
 }
 

@@ -682,8 +682,9 @@ k_ntt_fwd_a(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
     fwd_a_body<LOGN, PRO, IntAr>(J, primes, Wi, P, w, a, b, sub, J.mid ? J.mid : tabs.tmp, lds);
 }
 
-// PRO names the launch family (the block phase does not use it)
-template <int LOGN, int PRO, int EPI>
+// FAM names the launch family (the block phase has no prologue): the PRO_*
+// value of the launch, or FAM_RESCALE for the last kernel of a fused rescale
+template <int LOGN, int FAM, int EPI>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ntt_fwd_b(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
@@ -840,8 +841,9 @@ k_ks_modup_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTab
                                               sub, lds);
 }
 
-// ModDown columns: job w = a*Lp + t, a = 2b + k
-template <int LOGN>
+// ModDown columns: job w = a*Lp + t, a = 2b + k (TAG names the launch
+// family: 0 key-switch ModDown, 1 rescale)
+template <int LOGN, int TAG>
 __global__ void __launch_bounds__(Split<LOGN>::SA::T)
 k_ks_moddown_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = 1 << LOGN;
@@ -1228,6 +1230,8 @@ hipError_t fwd_blocks_launch(int pro, int epi, const NttJob& J, const PrimeDev* 
     hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, PRO_CENTRED_LIFT, EPI_STORE>), grid, blk, 0, st, J, primes, tabs);
   else if (pro == PRO_ROUNDDIV_LIFT && epi == EPI_ROUNDDIV)
     hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, PRO_ROUNDDIV_LIFT, EPI_ROUNDDIV>), grid, blk, 0, st, J, primes, tabs);
+  else if (pro == FAM_RESCALE && epi == EPI_ROUNDDIV)
+    hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, FAM_RESCALE, EPI_ROUNDDIV>), grid, blk, 0, st, J, primes, tabs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1248,7 +1252,11 @@ hipError_t ks_launch(int which, const KsJob& J, const PrimeDev* primes, const Nt
                          tabs);
       break;
     case 2:
-      hipLaunchKernelGGL((k_ks_moddown_cols<LOGN>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
+      hipLaunchKernelGGL((k_ks_moddown_cols<LOGN, 0>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
+                         tabs);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_ks_moddown_cols<LOGN, 1>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
                          tabs);
       break;
     default:
@@ -1315,6 +1323,10 @@ hipError_t launch_ks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* p
 hipError_t launch_ks_moddown_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                     hipStream_t st) {
   return ks_any(3, log_n, job, primes, tabs, st);
+}
+hipError_t launch_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                               hipStream_t st) {
+  return ks_any(4, log_n, job, primes, tabs, st);
 }
 
 hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job, const PrimeDev* primes,

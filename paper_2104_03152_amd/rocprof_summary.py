@@ -31,12 +31,18 @@ COPY_KERNEL = "copyBuffer"
 MARKER = "FillFunctor"
 
 # family -> (kernels that start a launch, kernels that complete it), as
-# name fragments of the N=8192 instantiations
+# name fragments of the N=8192 instantiations.  Small batches run the fused
+# forms (two-phase NTTs; the key switch's ModUp and ModDown in three kernels
+# each; rescale in three), large batches one workgroup per limb.
 FAMILIES = [
-    ("ntt_inv", ["k_ntt_inv_1<13", "k_ntt_inv<13"], ["k_ntt_inv_2<13"]),
+    ("ntt_inv", ["k_ntt_inv_1<13, false, 0>", "k_ntt_inv_1<13, true, 0>", "k_ntt_inv<13"], ["k_ntt_inv_2<13>"]),
     ("ntt_fwd", ["k_ntt_fwd_a<13, 0>", "k_ntt_fwd<13, 0, 0>"], ["k_ntt_fwd_b<13, 0, 0>"]),
-    ("modup", ["k_ntt_fwd_a<13, 1>", "k_ntt_fwd<13, 1, 0>"], ["k_ntt_fwd_b<13, 1, 0>"]),
-    ("moddown+rescale", ["k_ntt_fwd_a<13, 2>", "k_ntt_fwd<13, 2, 1>"], ["k_ntt_fwd_b<13, 2, 1>"]),
+    ("modup", ["k_ntt_inv_1<13, true, 1>", "k_ntt_inv_1<13, false, 1>", "k_ntt_fwd_a<13, 1>", "k_ntt_fwd<13, 1, 0>"],
+     ["k_ks_modup_cols<13>", "k_ntt_fwd_b<13, 1, 0>"]),
+    ("moddown", ["k_ks_special_blocks<13>"], ["k_ks_moddown_cols<13, 0>", "k_ks_moddown_blocks<13>"]),
+    ("rescale", ["k_ntt_inv_1<13, false, 2>"], ["k_ks_moddown_cols<13, 1>", "k_ntt_fwd_b<13, 3, 1>"]),
+    ("moddown+rescale (one workgroup per limb)", ["k_ntt_fwd_a<13, 2>", "k_ntt_fwd<13, 2, 1>"],
+     ["k_ntt_fwd_b<13, 2, 1>"]),
     ("hoisted_moddown", ["k_hoist_mac<13>"], []),
     ("hoisted_inner", ["k_inner_hoisted"], []),
     ("keyswitch_inner", ["k_inner("], []),
@@ -113,7 +119,7 @@ def trace(db_path, out_md, command, bench_out=None):
              "| family | launches | kernel us per launch | HIP-event us per launch | kernels |",
              "|---|---|---|---|---|"]
     for fam, (n, total, names) in _families(per).items():
-        e = ev.get(fam) or (ev.get("moddown") if fam == "moddown+rescale" else None)
+        e = ev.get(fam)
         lines.append("| %s | %d | %.2f | %s | %s |" % (
             fam, n, total / n / 1e3, "%.2f" % e["avg_launch_us"] if e else "-",
             ", ".join("`%s`" % k.split("(")[0] for k in names)))
@@ -162,8 +168,6 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, out_json, out_md, command)
         fams[fam] = fb + wb
         lines.append("| %s | %d | %.1f | %.1f | %.0f | %s |" % (
             fam, n, fb / 1024, wb / 1024, fb + wb, ", ".join("`%s`" % k.split("(")[0] for k in names)))
-    if "moddown+rescale" in fams:
-        fams["moddown"] = fams["rescale"] = fams["moddown+rescale"]
     rec = {"source_sha256": source_sha(), "fetch_scale": fetch_scale, "write_scale": write_scale,
            "families": fams, "command": command}
     with open(out_json, "w") as f:
