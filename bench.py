@@ -222,8 +222,10 @@ def main():
     dom = max(prof, key=lambda k: prof[k]["ms_per_step"]) if prof else None
     roof = roofline_entry(dom, prof[dom], g.n) if dom else None
 
-    kbench = ksbench = None
+    kbench = ksbench = sweep = None
     if not args.no_extra_bench:
+        log("op sweep: the appendix unary/binary operation tables at N=8192")
+        sweep = op_sweep(H, I)
         log("kernel bench: batched NTT at N=16384")
         kbench = kernel_bench(H, torch, I)
         log("key-switch bench: batched multiply/rotate at N=16384")
@@ -264,6 +266,7 @@ def main():
         "roofline": roof,
         "kernel_bench": kbench,
         "keyswitch_bench": ksbench,
+        "op_sweep": sweep,
         "cpu_baseline": cpu,
         "bit_exact_repeat": bit_exact_repeat,
         "logits_max_abs_err": logits_err,
@@ -367,6 +370,79 @@ def kernel_bench(H, torch, I, n_ct=256, reps=5):
     del buf, ref
     g.close()
     return out
+
+
+# the appendix tables of unary and binary operations (ms, 8 vCPU c4.2xlarge,
+# N = 8192, 200-bit modulus): context for op_sweep
+PAPER_OPS_MS = {
+    "negate": [0.07, 0.07, 0.07, 0.13, 0.26], "square": [4.29, 4.29, 4.29, 8.49, 17.16],
+    "polyval": [10.55, 10.46, 10.51, 21.32, 42.68], "add": [0.08, 0.08, 0.08, 0.16, 0.31],
+    "multiply": [4.45, 4.34, 4.43, 8.84, 17.75], "sub": [0.08, 0.08, 0.08, 0.15, 0.3],
+    "dot": [20.15, 23.96, 28.11, 55.94, 112.36], "add_plain": [0.8, 0.86, 1.07, 2.13, 4.19],
+    "multiply_plain": [1.75, 1.81, 2.03, 4.02, 7.97], "sub_plain": [0.8, 0.86, 1.08, 2.14, 4.21],
+    "dot_plain": [17.37, 21.36, 25.63, 51.14, 101.82]}
+
+
+def op_sweep(H, I, shapes=(256, 1024, 4096, 8192, 16384), reps=10):
+    """Each operation of the appendix tables on encrypted vectors of the
+    given lengths at N = 8192 with a 200-bit chain (60, 40, 40, 60) and
+    automatic rescaling; vectors longer than N/2 span several ciphertexts
+    (their key switches batched).  `_plain` operands are encoded inside the
+    timed call, as a plain tensor operand is; polyval evaluates 2X^2 + X; dot
+    is the product followed by a slot sum.  Milliseconds per call, wall clock
+    between synchronisations (host work included)."""
+    import numpy as np
+    g = H.he_ctx_create(13, [60, 40, 40, 60], 2.0 ** 40, 4, auto_rescale=True, stream=None)
+    H.he_keygen(g, [1 << t for t in range(12)])
+    half = g.n // 2
+    rng = np.random.default_rng(4)
+    out = {op: [] for op in PAPER_OPS_MS}
+    for shape in shapes:
+        n_ct = (shape + half - 1) // half
+        parts = [min(half, shape - i * half) for i in range(n_ct)]
+        xv = [rng.uniform(-1, 1, m) for m in parts]
+        yv = [rng.uniform(-1, 1, m) for m in parts]
+        top = g.L - 1
+        X = [H.he_encrypt(g, H.he_encode(g, v, 2.0 ** 40, top), i, False) for i, v in enumerate(xv)]
+        Y = [H.he_encrypt(g, H.he_encode(g, v, 2.0 ** 40, top), 100 + i, False) for i, v in enumerate(yv)]
+        H.he_sync(g)
+
+        def enc(vs):
+            return [H.he_encode(g, v, 2.0 ** 40, top) for v in vs]
+
+        def dot(prods):
+            acc = prods[0]
+            for p in prods[1:]:
+                acc = H.he_add(g, acc, p)
+            return H.he_sum_slots(g, acc, min(shape, half))
+
+        ops = {
+            "negate": lambda: [H.he_negate(g, a) for a in X],
+            "square": lambda: H.he_mul_relin_many(g, X, X),
+            "polyval": lambda: [H.he_polyval(g, a, [0.0, 1.0, 2.0]) for a in X],
+            "add": lambda: [H.he_add(g, a, b) for a, b in zip(X, Y)],
+            "multiply": lambda: H.he_mul_relin_many(g, X, Y),
+            "sub": lambda: [H.he_sub(g, a, b) for a, b in zip(X, Y)],
+            "dot": lambda: dot(H.he_mul_relin_many(g, X, Y)),
+            "add_plain": lambda: [H.he_add_plain(g, a, p) for a, p in zip(X, enc(yv))],
+            "multiply_plain": lambda: [H.he_mul_plain(g, a, p) for a, p in zip(X, enc(yv))],
+            "sub_plain": lambda: [H.he_sub_plain(g, a, p) for a, p in zip(X, enc(yv))],
+            "dot_plain": lambda: dot([H.he_mul_plain(g, a, p) for a, p in zip(X, enc(yv))]),
+        }
+        for name, fn in ops.items():
+            r = fn()
+            H.he_sync(g)
+            del r
+            t = time.perf_counter()
+            for _ in range(reps):
+                r = fn()
+            H.he_sync(g)
+            out[name].append((time.perf_counter() - t) * 1e3 / reps)
+            del r
+        del X, Y
+    g.close()
+    return {"shapes": list(shapes), "ms": out, "paper_ms_8vcpu": PAPER_OPS_MS,
+            "params": "N=8192, primes (60, 40, 40, 60), scale 2^40, auto rescale"}
 
 
 def keyswitch_bench(H, I, n_ct=256, reps=3):

@@ -171,6 +171,27 @@ he_status he_power(he_ctx* ctx, const he_ct* a, uint32_t k, he_ct** out);
 he_status he_polyval(he_ctx* ctx, const he_ct* a, const double* coeffs, size_t n_coeffs,
                      he_ct** out);
 
+/* ---- captured graphs (a fixed op sequence replayed with one launch) ----
+ * Everything the library enqueues on the context's stream between
+ * he_graph_begin and he_graph_end is captured (HIP stream capture, relaxed
+ * mode) into a graph; he_graph_launch replays it.  Ciphertexts created
+ * during the capture are the graph's outputs: every replay rewrites them, so
+ * free them only after he_graph_free.  Inputs are read at their addresses
+ * at replay time: feed new data with he_ct_copy into the captured inputs
+ * (same level and scale).  Intermediates freed during the capture stay
+ * reserved for the graph until he_graph_free.  Only asynchronous calls may
+ * be captured (no decrypt, decode, export, encode, key or plan creation —
+ * they synchronise, and the capture then fails at he_graph_end); a plan
+ * applied in a capture must have been applied once before.  Profiling is
+ * off inside a capture. */
+typedef struct he_graph he_graph;
+he_status he_graph_begin(he_ctx* ctx);
+he_status he_graph_end(he_ctx* ctx, he_graph** out);
+he_status he_graph_launch(he_ctx* ctx, const he_graph* g);
+void he_graph_free(he_graph* g);
+/* dst <- src (device copy; levels must match, dst takes src's scale) */
+he_status he_ct_copy(he_ctx* ctx, he_ct* dst, const he_ct* src);
+
 /* ---- batches (the key switch of section 3 applied to many ciphertexts) ----
  * n operations on operands that all sit at one level (HE_ELEVEL otherwise).
  * Up to 32 key switches run in one set of launches, sharing the key reads;

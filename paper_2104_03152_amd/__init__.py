@@ -69,6 +69,11 @@ _SIGS = {
     "he_drop_to": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
     "he_rotate": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
     "he_mul_relin_many": (C.c_int32, [_vp, _pvp, _pvp, C.c_size_t, _pvp]),
+    "he_graph_begin": (C.c_int32, [_vp]),
+    "he_graph_end": (C.c_int32, [_vp, _pvp]),
+    "he_graph_launch": (C.c_int32, [_vp, _vp]),
+    "he_graph_free": (None, [_vp]),
+    "he_ct_copy": (C.c_int32, [_vp, _vp, _vp]),
     "he_rotate_many": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
     "he_sum_slots": (C.c_int32, [_vp, _vp, C.c_uint32, _pvp]),
     "he_enc_conv_im2col": (C.c_int32, [_vp, _vp, _dp, C.c_uint32, C.c_uint32, C.c_double, _pvp]),
@@ -322,6 +327,26 @@ def he_power(ctx, a, k):
 def he_polyval(ctx, a, coeffs):
     cs = np.ascontiguousarray(coeffs, dtype=np.float64)
     return _new(Ct, ctx, lib().he_polyval, "he_polyval", ctx.ptr, a.ptr, _ptr(cs, C.c_double), cs.size)
+
+
+class Graph(_Handle):
+    _free = "he_graph_free"
+
+
+def he_graph_begin(ctx):
+    _chk(lib().he_graph_begin(ctx.ptr), "he_graph_begin")
+
+
+def he_graph_end(ctx):
+    return _new(Graph, ctx, lib().he_graph_end, "he_graph_end", ctx.ptr)
+
+
+def he_graph_launch(ctx, g):
+    _chk(lib().he_graph_launch(ctx.ptr, g.ptr), "he_graph_launch")
+
+
+def he_ct_copy(ctx, dst, src):
+    _chk(lib().he_ct_copy(ctx.ptr, dst.ptr, src.ptr), "he_ct_copy")
 
 
 def he_mul_relin_many(ctx, a, b):

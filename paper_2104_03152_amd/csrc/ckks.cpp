@@ -130,10 +130,18 @@ struct Pool {
     bytes_live += bytes;
     return p;
   }
+  // while a graph is captured, freed buffers stay with the graph (its
+  // replays write them) instead of going back to the cache
+  bool retain = false;
+  std::vector<void*> retained;
   void put(void* p) {
     if (!p) return;
     auto it = live.find(p);
     if (it == live.end()) return;
+    if (retain) {
+      retained.push_back(p);
+      return;
+    }
     cache[it->second].push_back(p);
     bytes_live -= it->second;
     live.erase(it);
@@ -174,6 +182,7 @@ struct he_ctx {
   u64* d_fwd_fp = nullptr;
   u64* d_inv_fp = nullptr;
   NttTables tabs{};
+  bool capturing = false;  // a graph capture of st is open
   bool have_keys = false;
   u64* d_s = nullptr;   // [L+1][N]
   u64* d_pk = nullptr;  // [2][L][N]
@@ -228,7 +237,7 @@ struct Prof {
   bool on;
   double units, bytes;
   Prof(he_ctx* c_, const char* f, double units_ = 0, double bytes_ = 0)
-      : c(c_), fam(f), on(c_->prof), units(units_), bytes(bytes_) {
+      : c(c_), fam(f), on(c_->prof && !c_->capturing), units(units_), bytes(bytes_) {
     if (on) {
       (void)hipEventCreate(&a);
       (void)hipEventCreate(&b);
@@ -430,6 +439,14 @@ he_status modup(he_ctx* c, const u64* coef, int B, int Lp, u64* ext) {
 }
 
 // ---------------------------------------------------------------- key switching
+// calls that synchronise or copy from host memory are refused while a graph
+// capture is open (a captured host copy would replay from freed memory)
+#define NO_CAPTURE(c)                                                                  \
+  do {                                                                                 \
+    if ((c) && (c)->capturing)                                                         \
+      return fail(HE_EINVAL, "%s: not allowed during a graph capture", __func__);       \
+  } while (0)
+
 // ---------------------------------------------------------------- fused key switch
 // Small batches: ModUp in three launches (inverse block phase; inverse
 // column phase + centred lift + forward column phase; forward block phase),
@@ -722,8 +739,8 @@ he_status drop_copy(he_ctx* c, const he_ct* a, int level, he_ct** out) {
   TRY(new_ct(c, level, a->scale, out));
   const size_t row = (size_t)(level + 1) * c->n * sizeof(u64);
   for (int k = 0; k < 2; k++)
-    HIPC(hipMemcpyAsync((*out)->d + (size_t)k * (level + 1) * c->n, a->d + (size_t)k * (a->level + 1) * c->n,
-                        row, hipMemcpyDeviceToDevice, c->st));
+    HIPC(launch_copy(a->d + (size_t)k * (a->level + 1) * c->n, (*out)->d + (size_t)k * (level + 1) * c->n,
+                     (long long)(row / sizeof(u64)), c->st));
   return HE_OK;
 }
 
@@ -1075,6 +1092,7 @@ he_status he_ctx_info(const he_ctx* c, int32_t* log_n, int32_t* n_data, uint64_t
 }
 
 he_status he_keygen(he_ctx* c, const int32_t* steps, size_t n_steps) {
+  NO_CAPTURE(c);
   if (!c) return fail(HE_EINVAL, "NULL context");
   const int n = c->n, L = c->L;
   if (!c->have_keys) {
@@ -1118,17 +1136,20 @@ he_status he_keygen(he_ctx* c, const int32_t* steps, size_t n_steps) {
 }
 
 he_status he_keygen_galois(he_ctx* c, int32_t step, int32_t max_level) {
+  NO_CAPTURE(c);
   if (!c) return fail(HE_EINVAL, "NULL context");
   return galois_key(c, step, max_level);
 }
 
 he_status he_encode(he_ctx* c, const double* v, size_t n, double scale, int32_t level, he_pt** out) {
+  NO_CAPTURE(c);
   if (!c || !out || (!v && n)) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   return encode_impl(c, v, n, scale, level, out);
 }
 
 he_status he_pt_import(he_ctx* c, const int64_t* coeffs, double scale, int32_t level, he_pt** out) {
+  NO_CAPTURE(c);
   if (!c || !coeffs || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (level < 0 || level >= c->L) return fail(HE_ELEVEL, "level %d outside 0..%d", level, c->L - 1);
@@ -1136,6 +1157,7 @@ he_status he_pt_import(he_ctx* c, const int64_t* coeffs, double scale, int32_t l
 }
 
 he_status he_pt_export(he_ctx* c, const he_pt* pt, uint64_t* h, size_t cap, int32_t* level, double* scale) {
+  NO_CAPTURE(c);
   if (!c || !pt || !h) return fail(HE_EINVAL, "NULL argument");
   const size_t words = pt_words(c, pt->level);
   if (cap < words) return fail(HE_EINVAL, "capacity %zu < %zu words", cap, words);
@@ -1148,6 +1170,7 @@ he_status he_pt_export(he_ctx* c, const he_pt* pt, uint64_t* h, size_t cap, int3
 }
 
 he_status he_decode(he_ctx* c, const he_pt* pt, double* out, size_t nv) {
+  NO_CAPTURE(c);
   if (!c || !pt || (!out && nv)) return fail(HE_EINVAL, "NULL argument");
   if (nv > (size_t)c->n / 2) return fail(HE_ERANGE, "%zu values exceed N/2", nv);
   std::vector<u64> v;
@@ -1212,6 +1235,7 @@ he_status he_decrypt(he_ctx* c, const he_ct* ct, he_pt** out) {
 }
 
 he_status he_ct_export(he_ctx* c, const he_ct* ct, uint64_t* h, size_t cap, int32_t* level, double* scale) {
+  NO_CAPTURE(c);
   if (!c || !ct || !h) return fail(HE_EINVAL, "NULL argument");
   const size_t words = ct_words(c, ct->level);
   if (cap < words) return fail(HE_EINVAL, "capacity %zu < %zu words", cap, words);
@@ -1224,6 +1248,7 @@ he_status he_ct_export(he_ctx* c, const he_ct* ct, uint64_t* h, size_t cap, int3
 }
 
 he_status he_ct_import(he_ctx* c, const uint64_t* h, int32_t level, double scale, he_ct** out) {
+  NO_CAPTURE(c);
   if (!c || !h || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (level < 0 || level >= c->L) return fail(HE_ELEVEL, "level %d outside 0..%d", level, c->L - 1);
@@ -1709,8 +1734,7 @@ he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps,
       int idx[HE_MAX_BATCH], nr = 0;
       for (int k = 0; k < B; k++) {
         if (st[k] == 0) {
-          if (hipMemcpyAsync(O + k * per, in.p + k * per, per * sizeof(u64), hipMemcpyDeviceToDevice, c->st) !=
-              hipSuccess)
+          if (launch_copy(in.p + k * per, O + k * per, (long long)per, c->st) != hipSuccess)
             s = fail(HE_EHIP, "copy failed");
         } else {
           idx[nr++] = k;
@@ -1726,14 +1750,12 @@ he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps,
         int pst[HE_MAX_BATCH];
         for (int r = 0; r < nr && s == HE_OK; r++) {
           pst[r] = st[idx[r]];
-          if (hipMemcpyAsync(pin.p + r * per, in.p + idx[r] * per, per * sizeof(u64), hipMemcpyDeviceToDevice,
-                             c->st) != hipSuccess)
+          if (launch_copy(in.p + idx[r] * per, pin.p + r * per, (long long)per, c->st) != hipSuccess)
             s = fail(HE_EHIP, "copy failed");
         }
         if (s == HE_OK) s = rotate_multi(c, pin.p, nr, l, pst, pout.p);
         for (int r = 0; r < nr && s == HE_OK; r++)
-          if (hipMemcpyAsync(O + idx[r] * per, pout.p + r * per, per * sizeof(u64), hipMemcpyDeviceToDevice,
-                             c->st) != hipSuccess)
+          if (launch_copy(pout.p + r * per, O + idx[r] * per, (long long)per, c->st) != hipSuccess)
             s = fail(HE_EHIP, "copy failed");
       }
     }
@@ -1794,6 +1816,7 @@ static he_status encode_slots(he_ctx* c, const std::vector<double>& v, double sc
 
 he_status he_conv_plan(he_ctx* c, const he_ct* like, const double* kernel, uint32_t kk, uint32_t windows,
                        double bias, he_plan** out) {
+  NO_CAPTURE(c);
   if (!c || !like || !kernel || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   const uint32_t half = (uint32_t)c->n / 2;
@@ -1825,6 +1848,7 @@ he_status he_conv_plan(he_ctx* c, const he_ct* like, const double* kernel, uint3
 
 he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t n_in, uint32_t n_out,
                          const double* bias, he_plan** out) {
+  NO_CAPTURE(c);
   if (!c || !like || !W || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   const uint32_t half = (uint32_t)c->n / 2;
@@ -1962,6 +1986,7 @@ static he_status hoist_items(he_ctx* c, he_plan* p, int level) {
   const int R = (int)p->n_in - 1;
   if (R <= 0) return HE_OK;
   if (p->items && p->items_epoch == c->key_epoch) return HE_OK;
+  if (c->capturing) return fail(HE_EINVAL, "apply the plan once before capturing it");
   std::vector<HoistItem> h(R);
   for (int r = 0; r < R; r++) {
     const int step = norm_step(c, r + 1);
@@ -2154,6 +2179,7 @@ he_status he_plan_apply_many(he_ctx* c, const he_plan* const* plans, uint32_t nb
 
 he_status he_enc_conv_im2col(he_ctx* c, const he_ct* x, const double* kernel, uint32_t kk, uint32_t windows,
                              double bias, he_ct** out) {
+  NO_CAPTURE(c);
   he_plan* p = nullptr;
   TRY(he_conv_plan(c, x, kernel, kk, windows, bias, &p));
   he_status s = he_plan_apply(c, p, x, out);
@@ -2163,6 +2189,7 @@ he_status he_enc_conv_im2col(he_ctx* c, const he_ct* x, const double* kernel, ui
 
 he_status he_enc_matmul(he_ctx* c, const he_ct* x, const double* W, uint32_t n_in, uint32_t n_out,
                         const double* bias, he_ct** out) {
+  NO_CAPTURE(c);
   he_plan* p = nullptr;
   TRY(he_matmul_plan(c, x, W, n_in, n_out, bias, &p));
   he_status s = he_plan_apply(c, p, x, out);
@@ -2223,7 +2250,7 @@ he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t wid
   he_ct* r = nullptr;
   TRY(new_ct(c, l - 1, scale0, &r));
   CtGuard gr{r};
-  HIPC(hipMemcpyAsync(r->d, Y.p, ct_w1 * sizeof(u64), hipMemcpyDeviceToDevice, c->st));
+  HIPC(launch_copy(Y.p, r->d, (long long)ct_w1, c->st));
   for (int k = 1; k < np; k++) {
     Prof pr(c, "pointwise");
     hipError_t e = launch_addsub(c->log_n, 0, r->d, R.p + (k - 1) * ct_w1, r->d, 2, mods_range(l), c->d_primes, c->st);
@@ -2248,6 +2275,7 @@ he_status he_ntt_inverse(he_ctx* c, uint64_t* data, size_t n_polys, int32_t n_li
 
 // ---------------------------------------------------------------- key export
 he_status he_export_secret(he_ctx* c, int64_t* s) {
+  NO_CAPTURE(c);
   if (!c || !s) return fail(HE_EINVAL, "NULL argument");
   if (!c->have_keys) return fail(HE_ENOKEY, "no secret key");
   std::vector<u64> v;
@@ -2258,6 +2286,7 @@ he_status he_export_secret(he_ctx* c, int64_t* s) {
 }
 
 he_status he_export_key(he_ctx* c, int32_t kind, int32_t step, uint64_t* out, size_t cap, int32_t* max_level) {
+  NO_CAPTURE(c);
   if (!c || !out) return fail(HE_EINVAL, "NULL argument");
   const Key* k = nullptr;
   if (kind == 0) {
@@ -2286,6 +2315,70 @@ he_status he_export_key(he_ctx* c, int32_t kind, int32_t step, uint64_t* out, si
 }
 
 // ---------------------------------------------------------------- housekeeping
+// ---------------------------------------------------------------- graphs
+struct he_graph {
+  he_ctx* ctx;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  std::vector<void*> retained;  // intermediates the replays write
+};
+
+he_status he_graph_begin(he_ctx* c) {
+  if (!c) return fail(HE_EINVAL, "NULL context");
+  if (c->capturing) return fail(HE_EINVAL, "a capture is already open");
+  hipError_t e = hipStreamBeginCapture(c->st, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return fail(HE_EHIP, "capture begin: %s", hipGetErrorString(e));
+  c->capturing = true;
+  c->pool.retain = true;
+  return HE_OK;
+}
+
+he_status he_graph_end(he_ctx* c, he_graph** out) {
+  if (!c || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (!c->capturing) return fail(HE_EINVAL, "no capture open");
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->st, &g);
+  c->capturing = false;
+  c->pool.retain = false;
+  std::vector<void*> kept;
+  kept.swap(c->pool.retained);
+  hipGraphExec_t x = nullptr;
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess || !g || !x) {
+    if (g) (void)hipGraphDestroy(g);
+    for (void* p : kept) c->pool.put(p);
+    return fail(HE_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+  }
+  *out = new he_graph{c, g, x, std::move(kept)};
+  return HE_OK;
+}
+
+he_status he_graph_launch(he_ctx* c, const he_graph* g) {
+  if (!c || !g) return fail(HE_EINVAL, "NULL argument");
+  if (g->ctx != c) return fail(HE_EINVAL, "graph of another context");
+  if (c->capturing) return fail(HE_EINVAL, "capture open on this context");
+  HIPC(hipGraphLaunch(g->exec, c->st));
+  return HE_OK;
+}
+
+void he_graph_free(he_graph* g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->ctx->st);
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  for (void* p : g->retained) g->ctx->pool.put(p);
+  delete g;
+}
+
+he_status he_ct_copy(he_ctx* c, he_ct* dst, const he_ct* src) {
+  if (!c || !dst || !src) return fail(HE_EINVAL, "NULL argument");
+  if (dst->level != src->level) return fail(HE_ELEVEL, "levels %d and %d differ", dst->level, src->level);
+  HIPC(launch_copy(src->d, dst->d, (long long)ct_words(c, src->level), c->st));
+  dst->scale = src->scale;
+  return HE_OK;
+}
+
 void he_ct_free(he_ct* ct) {
   if (!ct) return;
   if (!ct->blk) ct->ctx->pool.put(ct->d);
@@ -2307,6 +2400,7 @@ void he_plan_free(he_plan* p) {
 
 he_status he_sync(he_ctx* c) {
   if (!c) return fail(HE_EINVAL, "NULL context");
+  NO_CAPTURE(c);
   HIPC(hipStreamSynchronize(c->st));
   return HE_OK;
 }

@@ -166,6 +166,9 @@ struct CtList {
 // tensor of B pairs: out01 [B][2][n_limbs][N], out2 [B][n_limbs][N]
 hipError_t launch_tensor_many(int log_n, const CtList& a, const CtList& b, int B, u64* out01, u64* out2,
                               int n_limbs, const PrimeDev* primes, hipStream_t st);
+// device copy of `words` words (a kernel, so that graph capture records a
+// kernel node)
+hipError_t launch_copy(const u64* src, u64* dst, long long words, hipStream_t st);
 // copy of B ciphertexts into one contiguous [B][2][n_limbs][N] buffer
 hipError_t launch_gather_cts(int log_n, const CtList& a, int B, int n_limbs, u64* out, hipStream_t st);
 // decrypt: m[i] = c0[i] + c1[i] * s[i]   (s: [L+1][N], limb i under prime i)

@@ -15,6 +15,8 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
+#include <thread>
 #include <vector>
 
 #include "encode.h"
@@ -213,6 +215,7 @@ int encode_coeffs(const EncodeTables& T, const double* z, size_t nz, double scal
   const double eps = std::ldexp(1.0, -53);
   const double fft_bound = 2.0 * fac * (2.0 * sumabs) * (8.0 * (T.log_n + 2)) * eps;
   const double twice = 2.0 * scale / (double)n;
+  std::vector<int> amb;  // coefficients the bound cannot round
   for (int k = 0; k < n; k++) {
     std::complex<double> zk = std::conj(T.zeta[k]);
     double v = (G[k] * zk).real() * fac;
@@ -226,23 +229,49 @@ int encode_coeffs(const EncodeTables& T, const double* z, size_t nz, double scal
       out[k] = v < 0 ? -mag : mag;
       continue;
     }
-    // double-double recomputation of this coefficient
-    dd acc = {0.0, 0.0};
-    for (size_t j = 0; j < nz; j++) {
-      if (z[j] == 0.0) continue;
-      const size_t t = (size_t)(((uint64_t)T.rot5[j] * (uint64_t)k) % two_n);
-      dd p = two_prod(z[j], T.chi[t]);
-      p.lo += z[j] * T.clo[t];
-      acc = dd_add(acc, quick_two_sum(p.hi, p.lo));
-    }
-    acc = dd_mul_d(acc, twice);
-    bool neg = acc.hi < 0 || (acc.hi == 0 && acc.lo < 0);
-    dd a = neg ? dd{-acc.hi, -acc.lo} : acc;
-    if (a.hi >= 4611686018427387904.0) return -2;
-    int64_t mag = round_dd_nonneg(a);
-    out[k] = neg ? -mag : mag;
+    amb.push_back(k);
   }
-  return 0;
+  // double-double recomputation of the ambiguous coefficients, split over
+  // host threads when there are many (a full vector at scale 2^40 leaves a
+  // few percent of them, each an O(n) sum)
+  std::atomic<int> bad{0};
+  auto exact = [&](size_t i0, size_t i1) {
+    for (size_t i = i0; i < i1; i++) {
+      const int k = amb[i];
+      dd acc = {0.0, 0.0};
+      for (size_t j = 0; j < nz; j++) {
+        if (z[j] == 0.0) continue;
+        const size_t t = (size_t)(((uint64_t)T.rot5[j] * (uint64_t)k) % two_n);
+        dd p = two_prod(z[j], T.chi[t]);
+        p.lo += z[j] * T.clo[t];
+        acc = dd_add(acc, quick_two_sum(p.hi, p.lo));
+      }
+      acc = dd_mul_d(acc, twice);
+      bool neg = acc.hi < 0 || (acc.hi == 0 && acc.lo < 0);
+      dd a = neg ? dd{-acc.hi, -acc.lo} : acc;
+      if (a.hi >= 4611686018427387904.0) {
+        bad = 1;
+        return;
+      }
+      int64_t mag = round_dd_nonneg(a);
+      out[k] = neg ? -mag : mag;
+    }
+  };
+  const size_t work = amb.size() * nz;
+  unsigned nth = std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  if (work < (1u << 18) || nth < 2) {
+    exact(0, amb.size());
+  } else {
+    nth = (unsigned)std::min<size_t>(nth, amb.size());
+    std::vector<std::thread> th;
+    const size_t per = (amb.size() + nth - 1) / nth;
+    for (unsigned t = 0; t < nth; t++) {
+      const size_t i0 = t * per, i1 = std::min(amb.size(), i0 + per);
+      if (i0 < i1) th.emplace_back(exact, i0, i1);
+    }
+    for (auto& x : th) x.join();
+  }
+  return bad ? -2 : 0;
 }
 
 void decode_values(const EncodeTables& T, const double* m, double scale, double* out, size_t nz) {

@@ -180,6 +180,11 @@ __global__ void k_gather_cts(CtList A, u64* __restrict__ out, long long per_ct, 
   out[e] = A.p[item][e - item * per_ct];
 }
 
+__global__ void k_copy(const u64* __restrict__ src, u64* __restrict__ dst, long long words) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < words) dst[e] = src[e];
+}
+
 __global__ void k_decrypt(int n, const u64* __restrict__ ct, const u64* __restrict__ s, u64* __restrict__ m,
                           int n_limbs, const PrimeDev* __restrict__ primes) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -411,6 +416,12 @@ hipError_t launch_tensor_many(int log_n, const CtList& a, const CtList& b, int B
 hipError_t launch_gather_cts(int log_n, const CtList& a, int B, int n_limbs, u64* out, hipStream_t st) {
   const long long per = (2LL * n_limbs) << log_n;
   hipLaunchKernelGGL(k_gather_cts, grid_for(per * B), dim3(BLK), 0, st, a, out, per, per * B);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const u64* src, u64* dst, long long words, hipStream_t st) {
+  if (words <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, grid_for(words), dim3(BLK), 0, st, src, dst, words);
   return hipGetLastError();
 }
 
