@@ -134,8 +134,9 @@ def main():
     d = I.cnn_inputs()
     log("context + keys")
     t0 = time.perf_counter()
+    # the library's own stream (capturable into a graph)
     g = H.he_ctx_create(params["log_n"], params["bits"], params["scale"], params["seed"],
-                        auto_rescale=True)
+                        auto_rescale=True, stream=None)
     H.he_keygen(g, [])
     for st, lv in sorted(I.cnn_rotation_steps().items()):
         H.he_keygen_galois(g, st, lv)
@@ -222,6 +223,9 @@ def main():
     dom = max(prof, key=lambda k: prof[k]["ms_per_step"]) if prof else None
     roof = roofline_entry(dom, prof[dom], g.n) if dom else None
 
+    log("graph: one captured step, replayed")
+    graph_res = graph_replay(H, g, net, x, shape["windows"], ref, args.steps)
+
     kbench = ksbench = sweep = None
     if not args.no_extra_bench:
         log("op sweep: the appendix unary/binary operation tables at N=8192")
@@ -264,6 +268,7 @@ def main():
         "host_enqueue_ms": enqueue_ms,
         "kernel_profile": prof,
         "roofline": roof,
+        "graph_replay": graph_res,
         "kernel_bench": kbench,
         "keyswitch_bench": ksbench,
         "op_sweep": sweep,
@@ -325,6 +330,32 @@ def pmc_traffic(fam):
     if rec.get("source_sha256") != h.hexdigest():
         return None
     return rec.get("families", {}).get(fam)
+
+
+def graph_replay(H, g, net, x, width, ref, steps):
+    """The same step captured once into a HIP graph (input: a copy of x) and
+    replayed `steps` times; checked bit for bit against the eager output."""
+    import numpy as np
+    xin = H.he_drop_to(g, x, x.info()[0])
+    H.he_sync(g)
+    H.he_graph_begin(g)
+    y = step(H, g, net, xin, width)
+    graph = H.he_graph_end(g)
+    H.he_graph_launch(g, graph)
+    H.he_sync(g)
+    exact = bool(np.array_equal(H.he_ct_export(g, y), ref))
+    t0 = time.perf_counter()
+    enq = 0.0
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        H.he_graph_launch(g, graph)
+        enq += time.perf_counter() - t1
+    H.he_sync(g)
+    dt = time.perf_counter() - t0
+    exact = exact and bool(np.array_equal(H.he_ct_export(g, y), ref))
+    graph.free()
+    return {"ms_per_step": dt * 1e3 / steps, "inferences_per_s": steps / dt,
+            "host_launch_ms": enq * 1e3 / steps, "bit_exact_vs_eager": exact}
 
 
 def window_marker(torch):
