@@ -171,6 +171,19 @@ he_status he_power(he_ctx* ctx, const he_ct* a, uint32_t k, he_ct** out);
 he_status he_polyval(he_ctx* ctx, const he_ct* a, const double* coeffs, size_t n_coeffs,
                      he_ct** out);
 
+/* ---- NTT autotuner ----
+ * Times batched forward + inverse NTTs of J limb-transforms (J = 16, 32, ...
+ * up to max_jobs) with one workgroup per limb and with the two-phase
+ * kernels (a limb spread over several workgroups), and from then on runs
+ * each launch in the form that won for its size (rounded up to the next J;
+ * larger launches follow the largest J).  *split_jobs: the largest J won by
+ * the two-phase form (0: none).  The choice changes timing only, never
+ * results.
+ * table (nullable) receives rows (J, us one-workgroup, us two-phase), at
+ * most table_cap doubles.  Synchronises; not allowed during a capture. */
+he_status he_tune_ntt(he_ctx* ctx, int32_t max_jobs, int32_t* split_jobs, double* table,
+                      size_t table_cap);
+
 /* ---- captured graphs (a fixed op sequence replayed with one launch) ----
  * Everything the library enqueues on the context's stream between
  * he_graph_begin and he_graph_end is captured (HIP stream capture, relaxed

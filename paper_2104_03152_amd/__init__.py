@@ -69,6 +69,7 @@ _SIGS = {
     "he_drop_to": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
     "he_rotate": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
     "he_mul_relin_many": (C.c_int32, [_vp, _pvp, _pvp, C.c_size_t, _pvp]),
+    "he_tune_ntt": (C.c_int32, [_vp, C.c_int32, _i32p, _dp, C.c_size_t]),
     "he_graph_begin": (C.c_int32, [_vp]),
     "he_graph_end": (C.c_int32, [_vp, _pvp]),
     "he_graph_launch": (C.c_int32, [_vp, _vp]),
@@ -327,6 +328,17 @@ def he_power(ctx, a, k):
 def he_polyval(ctx, a, coeffs):
     cs = np.ascontiguousarray(coeffs, dtype=np.float64)
     return _new(Ct, ctx, lib().he_polyval, "he_polyval", ctx.ptr, a.ptr, _ptr(cs, C.c_double), cs.size)
+
+
+def he_tune_ntt(ctx, max_jobs=1024):
+    """Returns (split_jobs chosen, rows of (J, us one-workgroup, us two-phase))."""
+    chosen = C.c_int32()
+    cap = 3 * 16
+    table = np.zeros(cap, dtype=np.float64)
+    _chk(lib().he_tune_ntt(ctx.ptr, int(max_jobs), C.byref(chosen), _ptr(table, C.c_double), cap),
+         "he_tune_ntt")
+    rows = [tuple(table[i:i + 3]) for i in range(0, cap, 3) if table[i] > 0]
+    return chosen.value, rows
 
 
 class Graph(_Handle):

@@ -183,6 +183,7 @@ struct he_ctx {
   u64* d_inv_fp = nullptr;
   NttTables tabs{};
   bool capturing = false;  // a graph capture of st is open
+  int fuse_max = 256;      // fused key switch when B*Lp^2 <= this, fused rescale when 2*n_ct*l <= this
   bool have_keys = false;
   u64* d_s = nullptr;   // [L+1][N]
   u64* d_pk = nullptr;  // [2][L][N]
@@ -454,7 +455,7 @@ he_status modup(he_ctx* c, const u64* coef, int B, int Lp, u64* ext) {
 // column phase + rounding lift + forward column phase; forward block phase
 // with the data-limb inner product, the division and the addends).
 static bool ks_fusable(const he_ctx* c, int B, int Lp) {
-  return c->tabs.split_jobs > 0 && (long long)B * Lp * Lp <= c->tabs.split_jobs;
+  return (long long)B * Lp * Lp <= c->fuse_max;
 }
 
 struct KsBufs {
@@ -668,7 +669,7 @@ he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps,
 he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
   const int n = c->n;
   if (l < 1) return fail(HE_ELEVEL, "no level left to rescale");
-  if (c->tabs.split_jobs > 0 && 2LL * n_ct * l <= c->tabs.split_jobs) {
+  if (2LL * n_ct * l <= c->fuse_max) {
     // three launches: inverse block phase of limb l; its inverse column
     // phase, rounding lift and forward column phase for each t < l; forward
     // block phase with the division epilogue
@@ -1043,6 +1044,7 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
   // ciphertexts), scratch for exactly that many
   int split_jobs = 256;
   if (const char* env = getenv("HE_NTT_SPLIT_JOBS")) split_jobs = atoi(env);
+  if (const char* env = getenv("HE_FUSE_MAX")) c->fuse_max = atoi(env);
   u64* tmp = nullptr;
   if (split_jobs > 0) {
     tmp = (u64*)c->pool.get((size_t)split_jobs * n * sizeof(u64));
@@ -1051,7 +1053,8 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
       return fail(HE_EOOM, "scratch allocation failed");
     }
   }
-  c->tabs = NttTables{c->d_fwd, c->d_inv, c->d_fwd_fp, c->d_inv_fp, tmp, (long long)split_jobs * n, split_jobs};
+  c->tabs = NttTables{c->d_fwd, c->d_inv, c->d_fwd_fp, c->d_inv_fp, tmp, (long long)split_jobs * n, split_jobs,
+                      0, 0u, 0};
   c->rd_inv.assign((size_t)np * np, 0);
   c->rd_inv_sh.assign((size_t)np * np, 0);
   c->rd_hq.assign((size_t)np * np, 0);
@@ -2315,6 +2318,92 @@ he_status he_export_key(he_ctx* c, int32_t kind, int32_t step, uint64_t* out, si
 }
 
 // ---------------------------------------------------------------- housekeeping
+// ---------------------------------------------------------------- NTT autotuner
+// Times batched forward + inverse transforms of J limbs (the context's data
+// primes in turn) with one workgroup per limb and with the two-phase
+// kernels, for J = 16, 32, ... up to max_jobs, and keeps the faster form for
+// each size (launches are bucketed by the next candidate J).
+he_status he_tune_ntt(he_ctx* c, int32_t max_jobs, int32_t* split_jobs, double* table, size_t table_cap) {
+  if (!c) return fail(HE_EINVAL, "NULL context");
+  NO_CAPTURE(c);
+  if (max_jobs < 16) return fail(HE_EINVAL, "max_jobs %d < 16", max_jobs);
+  const int n = c->n, L = c->L;
+  std::vector<int> cand;
+  for (int j = 16; j <= max_jobs && cand.size() < 16; j *= 2) cand.push_back(j);
+  const int jmax = cand.back();
+  DBuf buf;
+  TRY(dalloc(c, buf, (size_t)jmax * n));
+  HIPC(hipMemsetAsync(buf.p, 0, (size_t)jmax * n * sizeof(u64), c->st));
+  u64* tmp = (u64*)c->pool.get((size_t)jmax * n * sizeof(u64));
+  if (!tmp) return fail(HE_EOOM, "tuning scratch");
+  const NttTables saved = c->tabs;
+  hipEvent_t ea, eb;
+  HIPC(hipEventCreate(&ea));
+  HIPC(hipEventCreate(&eb));
+  he_status s = HE_OK;
+  unsigned mask = 0;
+  int largest = 0;  // largest J that chose the two-phase form
+  size_t row = 0;
+  for (size_t ci = 0; ci < cand.size() && s == HE_OK; ci++) {
+    const int J = cand[ci];
+    const int nb = std::min(L, J), na = J / nb;
+    float ms[2] = {0, 0};
+    for (int mode = 0; mode < 2 && s == HE_OK; mode++) {
+      c->tabs = saved;
+      c->tabs.tmp = tmp;
+      c->tabs.tmp_words = (long long)jmax * n;
+      c->tabs.tuned = 0;
+      c->tabs.split_jobs = mode ? jmax : 0;
+      for (int rep = 0; rep < 6 && s == HE_OK; rep++) {  // the first repetition warms up
+        if (rep == 1) (void)hipEventRecord(ea, c->st);
+        s = ntt_rows(c, true, buf.p, buf.p, na, nb, (long long)nb * n, (long long)nb * n);
+        if (s == HE_OK) s = ntt_rows(c, false, buf.p, buf.p, na, nb, (long long)nb * n, (long long)nb * n);
+      }
+      (void)hipEventRecord(eb, c->st);
+      (void)hipEventSynchronize(eb);
+      (void)hipEventElapsedTime(&ms[mode], ea, eb);
+    }
+    if (s != HE_OK) break;
+    if (table && row + 3 <= table_cap) {
+      table[row++] = J;
+      table[row++] = ms[0] / 5 * 1e3;  // us per forward + inverse pair
+      table[row++] = ms[1] / 5 * 1e3;
+    }
+    if (ms[1] < ms[0]) {
+      mask |= 1u << ci;
+      largest = J;
+    }
+  }
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  c->tabs = saved;
+  if (s != HE_OK) {
+    c->pool.put(tmp);
+    return s;
+  }
+  // scratch for the largest two-phase batch (launches beyond it run one
+  // workgroup per limb)
+  if (c->tabs.tmp) c->pool.put(c->tabs.tmp);
+  c->pool.put(tmp);
+  c->tabs.tmp = nullptr;
+  c->tabs.tmp_words = 0;
+  c->tabs.split_jobs = largest;
+  c->tabs.tuned = 1;
+  c->tabs.split_mask = mask;
+  c->tabs.n_buckets = (int)cand.size();
+  if (largest > 0) {
+    c->tabs.tmp = (u64*)c->pool.get((size_t)largest * n * sizeof(u64));
+    if (!c->tabs.tmp) {
+      c->tabs.tuned = 0;
+      c->tabs.split_jobs = 0;
+      return fail(HE_EOOM, "scratch allocation failed");
+    }
+    c->tabs.tmp_words = (long long)largest * n;
+  }
+  if (split_jobs) *split_jobs = largest;
+  return HE_OK;
+}
+
 // ---------------------------------------------------------------- graphs
 struct he_graph {
   he_ctx* ctx;

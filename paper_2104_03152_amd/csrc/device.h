@@ -57,6 +57,9 @@ enum { EPI_STORE = 0, EPI_ROUNDDIV = 1 };
 // launch of at most split_jobs transforms runs in two phases (each limb
 // spread over several workgroups) through tmp, tmp_words words of device
 // scratch owned by the context; all launches are ordered on one stream.
+// After tuning, split_mask bit i chooses the two-phase form for launches of
+// up to 16 * 2^i jobs (the last bit for anything larger); split_jobs then
+// only caps the scratch.
 struct NttTables {
   const u64* fwd;
   const u64* inv;
@@ -65,6 +68,9 @@ struct NttTables {
   u64* tmp;
   long long tmp_words;
   int split_jobs;
+  int tuned;
+  unsigned split_mask;
+  int n_buckets;
 };
 hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job,
                           const PrimeDev* primes, const NttTables& tabs, hipStream_t st);

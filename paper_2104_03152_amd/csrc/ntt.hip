@@ -1123,10 +1123,15 @@ hipError_t set_lds(K kernel, size_t shm, bool& done) {
   return e;
 }
 
-// two phases when the batch is small and the scratch buffer holds it
+// two phases when the batch is small (or the tuned table says so for its
+// size) and the scratch buffer holds it
 bool use_split(const NttJob& J, const NttTables& tabs, int log_n) {
   const int jobs = n_jobs(J);
-  return tabs.tmp && jobs <= tabs.split_jobs && (long long)jobs << log_n <= tabs.tmp_words;
+  if (!tabs.tmp || (long long)jobs << log_n > tabs.tmp_words) return false;
+  if (!tabs.tuned) return jobs <= tabs.split_jobs;
+  int b = 0;
+  while (b + 1 < tabs.n_buckets && jobs > (16 << b)) b++;
+  return (tabs.split_mask >> b) & 1;
 }
 
 template <int LOGN, int PRO, int EPI>
