@@ -185,6 +185,18 @@ __device__ __forceinline__ void exchange(typename Ar::T (&x)[S::E], u64* lds, in
       x[u * (1 << R2) + c] = Ar::unbits(lds[pad(gidx(tid + S::T * u, c, LO2, R2))]);
 }
 
+// Twiddle index of a pass whose group bits start at LO: for LO >= 6 the
+// index (gi >> LO) is the same for the 64 lanes of a wave (gi = tid + T*u
+// with T a multiple of 64), so it is made wave-uniform and the twiddle comes
+// through the scalar cache instead of 64 vector lanes.
+template <class S, int LO>
+__device__ __forceinline__ int tw_index(int ti) {
+  if constexpr (LO >= 6 && S::T % 64 == 0)
+    return __builtin_amdgcn_readfirstlane(ti);
+  else
+    return ti;
+}
+
 // ---------------- forward passes ----------------
 // Twiddles of one pass for one thread, loaded ahead of the butterflies.
 // Stage pb of a pass of R bits uses 2^(R-1-pb) twiddles per group, kept
@@ -206,7 +218,7 @@ struct PassTw {
         const int gi = tid + S::T * u;
 #pragma unroll
         for (int j = 0; j < (1 << (R - 1 - pb)); j++)
-          t[u * PER + (1 << (R - 1 - pb)) - 1 + j] = W[base + (((gi >> LO) << (R - 1 - pb)) | j)];
+          t[u * PER + (1 << (R - 1 - pb)) - 1 + j] = W[tw_index<S, LO>(base + (((gi >> LO) << (R - 1 - pb)) | j))];
       }
     }
   }
@@ -243,7 +255,7 @@ __device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, 
           ar.fwd(x[i0], x[i1], tw->t[u * PER + (1 << (R - 1 - pb)) - 1 + (c >> (pb + 1))]);
         } else {
           const int ti = base + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
-          ar.fwd(x[i0], x[i1], W[ti]);
+          ar.fwd(x[i0], x[i1], W[tw_index<S, LO>(ti)]);
         }
       }
     }
@@ -283,7 +295,7 @@ __device__ __forceinline__ void inv_passes(typename Ar::T (&x)[S::E], u64* lds, 
           ar.inv(x[i0], x[i1], tw->t[u * PER + (1 << (R - 1 - pb)) - 1 + (c >> (pb + 1))]);
         } else {
           const int ti = base + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
-          ar.inv(x[i0], x[i1], W[ti]);
+          ar.inv(x[i0], x[i1], W[tw_index<S, LO>(ti)]);
         }
       }
     }

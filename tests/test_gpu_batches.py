@@ -4,6 +4,7 @@ across more than one batch of 32 key switches."""
 import numpy as np
 import pytest
 
+from paper_2104_03152_amd import inputs as I
 from tests.gpu_common import Pair, say
 
 pytestmark = pytest.mark.gpu
@@ -74,3 +75,21 @@ def test_batches_reject_mixed_levels(deep):
         P.H.he_rotate_many(P.g, [g3[0], g2[0]], [1, 1])
     with pytest.raises(P.H.HeError):
         P.H.he_rotate_many(P.g, [g3[0]], [3])  # no key for step 3
+
+
+def test_n16384_batched_keyswitch_sampled():
+    # the launch configuration of the N=16384 key-switch bench: 34 products
+    # of uniform-residue ciphertexts at the top level in batches of 32
+    # (one workgroup per limb, the unfused key switch), auto-rescaled;
+    # sampled items against the oracle bit for bit
+    p = I.RAW
+    P = Pair(p["log_n"], p["bits"], p["scale"], p["seed"], auto_rescale=True)
+    L = P.o.L
+    data = I.raw_residues(P.g.primes, 34, L, P.n, seed=31)
+    g = [P.H.he_ct_import(P.g, data[i], L - 1, p["scale"]) for i in range(34)]
+    say("n16384 mul_relin_many")
+    outs = P.H.he_mul_relin_many(P.g, g, g[1:] + g[:1])
+    for i in (0, 31, 33):
+        a = P.o.ct_from_data(data[i], L - 1, p["scale"])
+        b = P.o.ct_from_data(data[(i + 1) % 34], L - 1, p["scale"])
+        P.ct_equal(outs[i], P.o.rescale(P.o.mul_relin(a, b)), "item %d" % i)
