@@ -29,21 +29,6 @@
 
 namespace {
 
-template <int LOGN>
-struct Cfg {
-  static constexpr int N = 1 << LOGN;
-  static constexpr int E = 16;  // words per thread
-  static constexpr int T = N / E;
-  static constexpr int NP = (LOGN + 3) / 4;
-  static constexpr int bits(int p) { return LOGN / NP + (p < LOGN % NP ? 1 : 0); }
-  static constexpr int consumed(int p) {
-    int s = 0;
-    for (int i = 0; i < p; i++) s += bits(i);
-    return s;
-  }
-  static constexpr int lds_words() { return N + (N >> 4); }
-};
-
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
 // element index of word c of group gi in a pass over bits [lo, lo + r)
@@ -168,6 +153,22 @@ struct Sched {
   static constexpr int flo(int p) { return BHI - consumed(p + 1); }  // forward pass p: bits [flo, flo + bits)
   static constexpr int ilo(int p) { return BLO + consumed(p); }      // inverse pass p
   static constexpr int lds_words() { return M + (M >> 4); }
+};
+
+// One workgroup per limb: the whole limb in LDS, E = 2^HE_SINGLE_LOGE words
+// per thread, passes over all LOGN bits.
+#ifndef HE_SINGLE_LOGE
+#define HE_SINGLE_LOGE 3
+#endif
+// words per thread of the one-workgroup-per-limb kernels: at most 1024
+// threads per workgroup
+constexpr int single_loge(int logn) { return logn - 10 > HE_SINGLE_LOGE ? logn - 10 : HE_SINGLE_LOGE; }
+template <int LOGN>
+struct Cfg : Sched<LOGN, 0, LOGN, single_loge(LOGN)> {
+  static constexpr int N = 1 << LOGN;
+  // waves per SIMD for two workgroups per compute unit (LDS allows two up
+  // to N = 8192)
+  static constexpr int WAVES2 = (LOGN <= 13 ? 2 : 1) * (Sched<LOGN, 0, LOGN, single_loge(LOGN)>::T / 256);
 };
 
 template <class S, int LO, int R, int LO2, int R2, class Ar>
@@ -317,9 +318,9 @@ __device__ __forceinline__ void fwd_body(const NttJob& J, const PrimeDev* __rest
   const int tid = threadIdx.x;
   const u64 q = P.q;
   const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
-  typename Ar::T x[16];
+  typename Ar::T x[C::E];
   {
-    constexpr int R = C::bits(0), LO = LOGN - R, G = 16 >> R;
+    constexpr int R = C::bits(0), LO = LOGN - R, G = C::E >> R;
     u64 sq = 0, sh = 0;
     const u64 hq_b = (PRO == PRO_ROUNDDIV_LIFT) ? J.hq[b] : 0;
     if (PRO != PRO_PLAIN) {
@@ -351,9 +352,9 @@ __device__ __forceinline__ void fwd_body(const NttJob& J, const PrimeDev* __rest
       }
     }
   }
-  fwd_passes<Sched<LOGN, 0, LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
+  fwd_passes<Cfg<LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
   {
-    constexpr int R = C::bits(C::NP - 1), G = 16 >> R;
+    constexpr int R = C::bits(C::NP - 1), G = C::E >> R;
     u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
     const u64* __restrict__ uu = nullptr;
     const u64* __restrict__ ad = nullptr;
@@ -387,7 +388,7 @@ __device__ __forceinline__ void fwd_body(const NttJob& J, const PrimeDev* __rest
 }
 
 template <int LOGN, int PRO, int EPI>
-__global__ void __launch_bounds__(Cfg<LOGN>::T)
+__global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::WAVES2)
 k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = Cfg<LOGN>::N;
   extern __shared__ u64 lds[];
@@ -411,9 +412,9 @@ __device__ __forceinline__ void inv_body(const NttJob& J, const typename Ar::TW*
   const Ar ar(P);
   const int tid = threadIdx.x;
   const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
-  typename Ar::T x[16];
+  typename Ar::T x[C::E];
   {
-    constexpr int R = C::bits(0), G = 16 >> R;  // bits [0, R): contiguous runs
+    constexpr int R = C::bits(0), G = C::E >> R;  // bits [0, R): contiguous runs
     const u64 g = GATHER ? J.gal[a / J.gal_div] : 1;
 #pragma unroll
     for (int u = 0; u < G; u++) {
@@ -425,9 +426,9 @@ __device__ __forceinline__ void inv_body(const NttJob& J, const typename Ar::TW*
       }
     }
   }
-  inv_passes<Sched<LOGN, 0, LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
+  inv_passes<Cfg<LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
   {
-    constexpr int R = C::bits(C::NP - 1), LO = LOGN - R, G = 16 >> R;
+    constexpr int R = C::bits(C::NP - 1), LO = LOGN - R, G = C::E >> R;
     u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
 #pragma unroll
     for (int u = 0; u < G; u++) {
@@ -439,7 +440,7 @@ __device__ __forceinline__ void inv_body(const NttJob& J, const typename Ar::TW*
 }
 
 template <int LOGN, bool GATHER>
-__global__ void __launch_bounds__(Cfg<LOGN>::T)
+__global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::WAVES2)
 k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = Cfg<LOGN>::N;
   extern __shared__ u64 lds[];
@@ -1050,8 +1051,8 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
                                            int k, int t, u64* lds) {
   using C = Cfg<LOGN>;
   constexpr int N = C::N;
-  constexpr int R0 = C::bits(0), LO0 = LOGN - R0, G0 = 16 >> R0;
-  constexpr int RF = C::bits(C::NP - 1), GF = 16 >> RF;
+  constexpr int R0 = C::bits(0), LO0 = LOGN - R0, G0 = C::E >> R0;
+  constexpr int RF = C::bits(C::NP - 1), GF = C::E >> RF;
   const Ar ar(P);
   const int tid = threadIdx.x;
   const u64 q = P.q;
@@ -1062,7 +1063,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
   for (int r = rb; r < re; r++) {
     const HoistItem it = J.items[r];
     const u64* __restrict__ src = J.ucoef + ((size_t)r * 2 + k) * N;
-    typename Ar::T x[16];
+    typename Ar::T x[C::E];
 #pragma unroll
     for (int u = 0; u < G0; u++) {
       const int gi = tid + C::T * u;
@@ -1077,7 +1078,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     // every stage's twiddles in registers across items)
     const typename Ar::TW* Wr = W;
     asm volatile("" : "+v"(Wr));
-    fwd_passes<Sched<LOGN, 0, LOGN>, LOGN, 0, Ar, false>(x, lds, Wr, ar, tid, 0);
+    fwd_passes<Cfg<LOGN>, LOGN, 0, Ar, false>(x, lds, Wr, ar, tid, 0);
     // final values through LDS so the epilogue runs in natural order:
     // coalesced accesses and a bounded number of loads in flight
     __syncthreads();
@@ -1094,7 +1095,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
     const bool first = (r == rb);
 #pragma unroll 4
-    for (int e = 0; e < 16; e++) {
+    for (int e = 0; e < C::E; e++) {
       const int idx = tid + C::T * e;
       const u64 v = lds[pad(idx)];
       u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
@@ -1107,7 +1108,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
 }
 
 template <int LOGN>
-__global__ void __launch_bounds__(Cfg<LOGN>::T, (LOGN <= 13 ? 4 : 1))
+__global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::WAVES2)
 k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = Cfg<LOGN>::N;
   extern __shared__ u64 lds[];
