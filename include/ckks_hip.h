@@ -82,6 +82,9 @@ typedef struct {
 he_status he_ctx_create(const he_params* params, he_alloc_fn alloc,
                         he_free_fn free_fn, void* alloc_user, void* hip_stream,
                         he_ctx** out);
+/* Waits for the context's stream and releases all its device memory.  Free
+ * every ciphertext, plaintext, plan and graph of the context before: their
+ * handles are invalid afterwards (freeing one then is undefined). */
 void he_ctx_destroy(he_ctx* ctx);
 /* primes: n_data_primes + 1 entries (special prime last). */
 he_status he_ctx_info(const he_ctx* ctx, int32_t* log_n, int32_t* n_data_primes,

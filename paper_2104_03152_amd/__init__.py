@@ -136,7 +136,10 @@ class _Handle:
 
     def free(self):
         if self.ptr:
-            getattr(lib(), self._free)(self.ptr)
+            # a handle that outlives its context is only dropped: the
+            # context's destruction released its device memory
+            if self.ctx is None or getattr(self.ctx, "ptr", None):
+                getattr(lib(), self._free)(self.ptr)
             self.ptr = None
 
     def __del__(self):

@@ -1042,9 +1042,9 @@ k_ks_moddown_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Nt
 // ---------------- hoisted rotations: ModDown + multiply-accumulate ----------------
 // ModDown of each item (an NTT of its special-prime limb, lifted) with the
 // plaintext multiply-accumulate of the vector-matrix product in the
-// epilogue.  Workgroup (chunk, k, t) loops over its items; the running sums
-// live in its own slice of `partial` (each thread re-reads exactly the words
-// it wrote, so no barrier is needed for them).
+// epilogue.  Workgroup (chunk, k, t) loops over its items; each thread
+// keeps the running sums of its E output words in registers and writes
+// them to its workgroup's slice of `partial` once at the end.
 template <int LOGN, class Ar>
 __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __restrict__ primes,
                                            const typename Ar::TW* __restrict__ W, const PrimeDev& P, int chunk,
@@ -1060,6 +1060,9 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
   const u64 hq = J.hq[t], inv = J.inv[t], inv_sh = J.inv_sh[t];
   u64* __restrict__ out = J.partial + (((size_t)chunk * 2 + k) * J.n_dig + t) * N;
   const int rb = chunk * J.chunk, re = min(J.R, rb + J.chunk);
+  u64 acc[C::E];
+#pragma unroll
+  for (int e = 0; e < C::E; e++) acc[e] = 0;
   for (int r = rb; r < re; r++) {
     const HoistItem it = J.items[r];
     const u64* __restrict__ src = J.ucoef + ((size_t)r * 2 + k) * N;
@@ -1093,22 +1096,24 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
     const u64* __restrict__ dgs = J.diags_sh + ((size_t)it.diag * J.n_dig + t) * N;
     const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
-    const bool first = (r == rb);
-#pragma unroll 4
+#pragma unroll
     for (int e = 0; e < C::E; e++) {
       const int idx = tid + C::T * e;
       const u64 v = lds[pad(idx)];
       u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
       if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
-      const u64 prod = shoup(ks, dg[idx], dgs[idx], q);
-      out[idx] = first ? prod : addmod(out[idx], prod, q);
+      acc[e] = addmod(acc[e], shoup(ks, dg[idx], dgs[idx], q), q);
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int e = 0; e < C::E; e++) out[tid + C::T * e] = acc[e];
 }
 
+// one workgroup per compute unit: the registers hold the running sums
+// (two workgroups would spill them)
 template <int LOGN>
-__global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::WAVES2)
+__global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::T / 256)
 k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = Cfg<LOGN>::N;
   extern __shared__ u64 lds[];

@@ -50,5 +50,6 @@ def test_alone_equals_mix():
     S.serve(H, reqs, 4 << 30, batched=False)
     for r in reqs:
         assert np.array_equal(H.he_ct_export(r.client.g, r.out), mix[r.rid]), "request %d" % r.rid
+    del reqs, lat  # every handle before its context
     for c in clients:
         c.close()
