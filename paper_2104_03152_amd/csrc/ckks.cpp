@@ -666,9 +666,11 @@ he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps,
 }
 
 // rescale of n_ct contiguous ciphertexts [n_ct][2][l+1][N] -> [n_ct][2][l][N]
-he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
+// add0 (nullable, n_ct = 1): a plaintext added to poly 0 of the result
+he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out, const u64* add0 = nullptr) {
   const int n = c->n;
   if (l < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  if (add0 && n_ct != 1) return fail(HE_EINVAL, "rescale addend for one ciphertext only");
   if (2LL * n_ct * l <= c->fuse_max) {
     // three launches: inverse block phase of limb l; its inverse column
     // phase, rounding lift and forward column phase for each t < l; forward
@@ -702,6 +704,12 @@ he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
     F.ua = (long long)(l + 1) * n;
     F.ub = n;
     F.mid = t4.p;
+    if (add0) {
+      F.add = add0;
+      F.aa = 0;
+      F.ab = n;
+      F.add_even_only = 1;
+    }
     for (int t = 0; t < l; t++) {
       K.hq[t] = c->rd_hq[l * np + t];
       F.dst_prime[t] = (unsigned char)t;
@@ -731,7 +739,13 @@ he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
     hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "rescale intt: %s", hipGetErrorString(e));
   }
-  return round_div(c, 2 * n_ct, coef.p, l, in, (long long)(l + 1) * n, out, (long long)l * n, l, Addend(),
+  Addend add;
+  if (add0) {
+    add.p = add0;
+    add.aa = 0;
+    add.even_only = 1;
+  }
+  return round_div(c, 2 * n_ct, coef.p, l, in, (long long)(l + 1) * n, out, (long long)l * n, l, add,
                    "rescale");
 }
 
@@ -1941,12 +1955,14 @@ static he_status conv_apply_many(he_ctx* c, const he_plan* const* plans, int nb,
   TRY(dalloc(c, Y, nb * ct_w1));
   TRY(dalloc(c, R, nb * ct_w1));
   {
-    Prof pr(c, "pointwise");
+    CtList in{}, kp{};
     for (int b = 0; b < nb; b++) {
-      hipError_t e = launch_mul_plain(c->log_n, x->d, plans[b]->kernel->d, M.p + b * ct_w, 2, mods_range(Lp),
-                                      c->d_primes, c->st);
-      if (e != hipSuccess) return fail(HE_EHIP, "mul_plain: %s", hipGetErrorString(e));
+      in.p[b] = x->d;
+      kp.p[b] = plans[b]->kernel->d;
     }
+    Prof pr(c, "pointwise");
+    hipError_t e = launch_mul_plain_many(c->log_n, in, kp, nb, Lp, M.p, c->d_primes, c->st);
+    if (e != hipSuccess) return fail(HE_EHIP, "mul_plain: %s", hipGetErrorString(e));
   }
   TRY(rescale_multi(c, M.p, nb, l, Y.p));
   const double scale = x->scale * plans[0]->kernel->scale / (double)c->q[l];
@@ -1964,18 +1980,36 @@ static he_status conv_apply_many(he_ctx* c, const he_plan* const* plans, int nb,
     TRY(rotate_multi(c, Y.p, nb, l - 1, st.data(), R.p, true));
     std::swap(Y.p, R.p);
   }
+  CtList in{}, bp{};
+  OutList ol{};
   for (int b = 0; b < nb; b++) {
-    if (!scales_match(scale, plans[b]->bias->scale)) return fail(HE_ESCALE, "bias scale");
-    he_ct* r = nullptr;
-    TRY(new_ct(c, l - 1, scale, &r));
-    Prof pr(c, "pointwise");
-    hipError_t e = launch_add_plain(c->log_n, Y.p + b * ct_w1, plans[b]->bias->d, r->d, 2, mods_range(l),
-                                    c->d_primes, c->st);
-    if (e != hipSuccess) {
-      he_ct_free(r);
-      return fail(HE_EHIP, "add_plain: %s", hipGetErrorString(e));
+    if (!scales_match(scale, plans[b]->bias->scale)) {
+      for (int k = 0; k < b; k++) {
+        he_ct_free(outs[k]);
+        outs[k] = nullptr;
+      }
+      return fail(HE_ESCALE, "bias scale");
     }
-    outs[b] = r;
+    he_status s = new_ct(c, l - 1, scale, &outs[b]);
+    if (s != HE_OK) {
+      for (int k = 0; k < b; k++) {
+        he_ct_free(outs[k]);
+        outs[k] = nullptr;
+      }
+      return s;
+    }
+    in.p[b] = Y.p + b * ct_w1;
+    bp.p[b] = plans[b]->bias->d;
+    ol.p[b] = outs[b]->d;
+  }
+  Prof pr(c, "pointwise");
+  hipError_t e = launch_add_plain_many(c->log_n, in, bp, ol, nb, l, c->d_primes, c->st);
+  if (e != hipSuccess) {
+    for (int b = 0; b < nb; b++) {
+      he_ct_free(outs[b]);
+      outs[b] = nullptr;
+    }
+    return fail(HE_EHIP, "add_plain: %s", hipGetErrorString(e));
   }
   return HE_OK;
 }
@@ -2138,10 +2172,21 @@ static he_status matmul_apply(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out
   }
   CtGuard acc;
   TRY(hoisted_mac(c, p, gxr.p, &acc.p));
+  // rescale with the bias added to poly 0 in the same kernel
+  const int la = acc.p->level;
+  if (la < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  const double sc = acc.p->scale / (double)c->q[la];
+  if (!scales_match(sc, p->bias->scale)) return fail(HE_ESCALE, "scales %g and %g differ", sc, p->bias->scale);
+  if (p->bias->level < la - 1) return fail(HE_ELEVEL, "bias level %d below %d", p->bias->level, la - 1);
   he_ct* y = nullptr;
-  TRY(rescale_raw(c, acc.p, &y));
-  CtGuard gy{y};
-  return he_add_plain(c, y, p->bias, out);
+  TRY(new_ct(c, la - 1, sc, &y));
+  he_status s = rescale_multi(c, acc.p->d, 1, la, y->d, p->bias->d);
+  if (s != HE_OK) {
+    he_ct_free(y);
+    return s;
+  }
+  *out = y;
+  return HE_OK;
 }
 
 he_status he_plan_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out) {
@@ -2227,15 +2272,20 @@ he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t wid
   DBuf M, Y;
   TRY(dalloc(c, M, np * ct_w));
   TRY(dalloc(c, Y, np * ct_w1));
-  for (int k = 0; k < np; k++) {
-    CtGuard a;
-    const he_ct* src = parts[k];
-    if (src->level != l) {
-      TRY(drop_copy(c, src, l, &a.p));
-      src = a.p;
+  {
+    std::vector<CtGuard> dropped(np);
+    CtList in{}, mp{};
+    for (int k = 0; k < np; k++) {
+      const he_ct* src = parts[k];
+      if (src->level != l) {
+        TRY(drop_copy(c, src, l, &dropped[k].p));
+        src = dropped[k].p;
+      }
+      in.p[k] = src->d;
+      mp.p[k] = mask->d;
     }
     Prof pr(c, "pointwise");
-    hipError_t e = launch_mul_plain(c->log_n, src->d, mask->d, M.p + k * ct_w, 2, mods_range(Lp), c->d_primes, c->st);
+    hipError_t e = launch_mul_plain_many(c->log_n, in, mp, np, Lp, M.p, c->d_primes, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "mul_plain: %s", hipGetErrorString(e));
   }
   TRY(rescale_multi(c, M.p, np, l, Y.p));
@@ -2253,11 +2303,12 @@ he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t wid
   he_ct* r = nullptr;
   TRY(new_ct(c, l - 1, scale0, &r));
   CtGuard gr{r};
-  HIPC(launch_copy(Y.p, r->d, (long long)ct_w1, c->st));
-  for (int k = 1; k < np; k++) {
+  {
+    CtList in{};
+    in.p[0] = Y.p;
+    for (int k = 1; k < np; k++) in.p[k] = R.p + (k - 1) * ct_w1;
     Prof pr(c, "pointwise");
-    hipError_t e = launch_addsub(c->log_n, 0, r->d, R.p + (k - 1) * ct_w1, r->d, 2, mods_range(l), c->d_primes, c->st);
-    if (e != hipSuccess) return fail(HE_EHIP, "add: %s", hipGetErrorString(e));
+    HIPC(launch_sum_cts(c->log_n, in, np, l, r->d, c->d_primes, c->st));
   }
   *out = r;
   gr.p = nullptr;

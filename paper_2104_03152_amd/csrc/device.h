@@ -169,6 +169,20 @@ hipError_t launch_tensor(int log_n, const u64* a, const u64* b, u64* out01,
 struct CtList {
   const u64* p[HE_MAX_BATCH];
 };
+// B ciphertexts or plaintexts written at their own addresses
+struct OutList {
+  u64* p[HE_MAX_BATCH];
+};
+// out[b] = in[b] (x) p[b] for B ciphertexts [2][n_limbs][N] (plaintexts
+// [>= n_limbs][N]); out contiguous [B][2][n_limbs][N]
+hipError_t launch_mul_plain_many(int log_n, const CtList& in, const CtList& p, int B, int n_limbs, u64* out,
+                                 const PrimeDev* primes, hipStream_t st);
+// out[b] = in[b] + p[b] on poly 0 (poly 1 copied)
+hipError_t launch_add_plain_many(int log_n, const CtList& in, const CtList& p, const OutList& out, int B,
+                                 int n_limbs, const PrimeDev* primes, hipStream_t st);
+// out = sum of B ciphertexts [2][n_limbs][N]
+hipError_t launch_sum_cts(int log_n, const CtList& in, int B, int n_limbs, u64* out, const PrimeDev* primes,
+                          hipStream_t st);
 // tensor of B pairs: out01 [B][2][n_limbs][N], out2 [B][n_limbs][N]
 hipError_t launch_tensor_many(int log_n, const CtList& a, const CtList& b, int B, u64* out01, u64* out2,
                               int n_limbs, const PrimeDev* primes, hipStream_t st);

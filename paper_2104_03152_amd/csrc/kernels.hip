@@ -180,6 +180,40 @@ __global__ void k_gather_cts(CtList A, u64* __restrict__ out, long long per_ct, 
   out[e] = A.p[item][e - item * per_ct];
 }
 
+__global__ void k_mul_plain_many(int log_n, CtList in, CtList pl, int n_limbs, u64* __restrict__ out,
+                                 long long total, const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long long per_poly = (long long)n_limbs << log_n, per = 2 * per_poly;
+  const int b = (int)(e / per);
+  const long long r = e - b * per;
+  const long long rl = r >= per_poly ? r - per_poly : r;  // index within the poly
+  const PrimeDev P = primes[rl >> log_n];
+  out[e] = mulmod(in.p[b][r], pl.p[b][rl], P);
+}
+
+__global__ void k_add_plain_many(int log_n, CtList in, CtList pl, OutList outl, int n_limbs, long long total,
+                                 const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long long per_poly = (long long)n_limbs << log_n, per = 2 * per_poly;
+  const int b = (int)(e / per);
+  const long long r = e - b * per;
+  const u64 v = in.p[b][r];
+  outl.p[b][r] = r < per_poly ? addmod(v, pl.p[b][r], primes[r >> log_n].q) : v;
+}
+
+__global__ void k_sum_cts(int log_n, CtList in, int B, int n_limbs, u64* __restrict__ out, long long total,
+                          const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const long long per_poly = (long long)n_limbs << log_n;
+  const u64 q = primes[(e >= per_poly ? e - per_poly : e) >> log_n].q;
+  u64 v = in.p[0][e];
+  for (int b = 1; b < B; b++) v = addmod(v, in.p[b][e], q);
+  out[e] = v;
+}
+
 __global__ void k_copy(const u64* __restrict__ src, u64* __restrict__ dst, long long words) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < words) dst[e] = src[e];
@@ -416,6 +450,30 @@ hipError_t launch_tensor_many(int log_n, const CtList& a, const CtList& b, int B
 hipError_t launch_gather_cts(int log_n, const CtList& a, int B, int n_limbs, u64* out, hipStream_t st) {
   const long long per = (2LL * n_limbs) << log_n;
   hipLaunchKernelGGL(k_gather_cts, grid_for(per * B), dim3(BLK), 0, st, a, out, per, per * B);
+  return hipGetLastError();
+}
+
+hipError_t launch_mul_plain_many(int log_n, const CtList& in, const CtList& p, int B, int n_limbs, u64* out,
+                                 const PrimeDev* primes, hipStream_t st) {
+  const long long total = ((2LL * n_limbs) << log_n) * B;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mul_plain_many, grid_for(total), dim3(BLK), 0, st, log_n, in, p, n_limbs, out, total, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_plain_many(int log_n, const CtList& in, const CtList& p, const OutList& out, int B,
+                                 int n_limbs, const PrimeDev* primes, hipStream_t st) {
+  const long long total = ((2LL * n_limbs) << log_n) * B;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_plain_many, grid_for(total), dim3(BLK), 0, st, log_n, in, p, out, n_limbs, total, primes);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_cts(int log_n, const CtList& in, int B, int n_limbs, u64* out, const PrimeDev* primes,
+                          hipStream_t st) {
+  const long long total = (2LL * n_limbs) << log_n;
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_cts, grid_for(total), dim3(BLK), 0, st, log_n, in, B, n_limbs, out, total, primes);
   return hipGetLastError();
 }
 
