@@ -235,11 +235,13 @@ he_status he_enc_conv_im2col(he_ctx* ctx, const he_ct* x, const double* kernel,
                              uint32_t kk, uint32_t windows, double bias,
                              he_ct** out);
 /* vector-matrix product y = x W + bias, W row-major n_in x n_out: replicate
- * x (zero beyond n_in) by right rotations n_in*2^j while the copies fit in
- * N/2 slots, then y = sum_i rot_left(x_rep, i) * diag_i with
+ * x (zero beyond n_in) R times, R the largest power of two with
+ * n_in * R <= N/2, as x plus its right rotations by n_in * m (m = 1..R-1),
+ * then y = sum_i rot_left(x_rep, i) * diag_i with
  * diag_i[j] = W[(i+j) mod n_in][j] (j < n_out), one rescale, bias added.
- * The n_in - 1 rotations of x_rep share one digit decomposition (hoisted);
- * results are identical to rotating one by one. */
+ * Both sets of rotations (R - 1 of x, n_in - 1 of x_rep) share one digit
+ * decomposition each (hoisted); results are identical to rotating one by
+ * one.  Needs Galois keys for the steps N/2 - n_in*m and 1..n_in-1. */
 he_status he_enc_matmul(he_ctx* ctx, const he_ct* x, const double* W,
                         uint32_t n_in, uint32_t n_out, const double* bias,
                         he_ct** out);

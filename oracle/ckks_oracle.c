@@ -1276,20 +1276,25 @@ orc_ct* orc_conv_im2col(const orc_ctx* c, const orc_ct* x, const double* kernel,
   return y;
 }
 
-/* Vector-matrix product (section 3.1): replicate x (zero beyond n_in) by   */
-/* doubling with right rotations by n_in * 2^j while the copies fit in N/2  */
-/* slots; then y = sum_i rot_left(x_rep, i) * diag_i with                   */
+/* Vector-matrix product (section 3.1): replicate x (zero beyond n_in) R    */
+/* times, R the largest power of two with n_in * R <= N/2, as x plus its    */
+/* right rotations by n_in * m, m = 1..R-1; then                            */
+/* y = sum_i rot_left(x_rep, i) * diag_i with                               */
 /* diag_i[j] = W[(i + j) mod n_in][j] for j < n_out (0 elsewhere); one      */
 /* rescale after the sum; bias added to slots 0..n_out-1.                   */
 orc_ct* orc_matmul(const orc_ctx* c, const orc_ct* x, const double* w,
                    uint32_t n_in, uint32_t n_out, const double* bias) {
   uint32_t half = (uint32_t)c->n / 2;
   if (n_in == 0 || n_out == 0 || n_in > half || n_out > half) FAIL(ORC_ERANGE);
+  /* replication: R copies (the largest power of two that fits), the input  */
+  /* plus its right rotations by n_in * m, m = 1..R-1, each rotation of the  */
+  /* input itself                                                            */
   uint32_t reps = 1;
+  while ((uint64_t)n_in * reps * 2 <= half) reps *= 2;
   orc_ct* xr = orc_drop_to(c, x, x->level);
   if (!xr) return NULL;
-  while ((uint64_t)n_in * reps * 2 <= half) {
-    orc_ct* r = orc_rotate(c, xr, (int)((half - n_in * reps) % half));
+  for (uint32_t m = 1; m < reps; m++) {
+    orc_ct* r = orc_rotate(c, x, (int)((half - n_in * m) % half));
     if (!r) {
       orc_ct_free(xr);
       return NULL;
@@ -1299,7 +1304,6 @@ orc_ct* orc_matmul(const orc_ctx* c, const orc_ct* x, const double* w,
     orc_ct_free(xr);
     if (!y) return NULL;
     xr = y;
-    reps *= 2;
   }
   if ((uint64_t)n_in + n_out - 1 > (uint64_t)n_in * reps) {
     orc_ct_free(xr);

@@ -226,6 +226,8 @@ struct he_plan {
   u64* diags = nullptr;          // matmul diagonals [n_in][level+1][N], NTT domain
   HoistItem* items = nullptr;    // device table of the hoisted rotations
   uint64_t items_epoch = ~0ull;
+  HoistItem* rep_items = nullptr;  // device table of the replication rotations
+  uint64_t rep_epoch = ~0ull;
 };
 
 namespace {
@@ -2018,42 +2020,74 @@ static he_status conv_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct**
   return conv_apply_many(c, &p, 1, x, out);
 }
 
-// device table of the hoisted rotations 1..n_in-1 (rebuilt when keys change)
-static he_status hoist_items(he_ctx* c, he_plan* p, int level) {
-  const int R = (int)p->n_in - 1;
+// device table of hoisted rotations by steps[r] (diagonal index diags[r],
+// -1 for none), keys checked at `level`; rebuilt when keys change
+static he_status build_items(he_ctx* c, const std::vector<int>& steps, const std::vector<int>& diags, int level,
+                             HoistItem** dev, uint64_t* epoch) {
+  const int R = (int)steps.size();
   if (R <= 0) return HE_OK;
-  if (p->items && p->items_epoch == c->key_epoch) return HE_OK;
+  if (*dev && *epoch == c->key_epoch) return HE_OK;
   if (c->capturing) return fail(HE_EINVAL, "apply the plan once before capturing it");
   std::vector<HoistItem> h(R);
   for (int r = 0; r < R; r++) {
-    const int step = norm_step(c, r + 1);
+    const int step = norm_step(c, steps[r]);
     auto it = c->gal.find(step);
     if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", step);
     if (it->second.ml < level) return fail(HE_ENOKEY, "Galois key for step %d cut below level %d", step, level);
     h[r].key = it->second.d;
     h[r].g = galois_elt(c, step);
     h[r].km = it->second.ml + 2;
-    h[r].diag = r + 1;
+    h[r].diag = diags[r];
   }
-  if (!p->items) {
-    p->items = (HoistItem*)c->pool.get(sizeof(HoistItem) * R);
-    if (!p->items) return fail(HE_EOOM, "item table allocation failed");
+  if (!*dev) {
+    *dev = (HoistItem*)c->pool.get(sizeof(HoistItem) * R);
+    if (!*dev) return fail(HE_EOOM, "item table allocation failed");
   }
-  HIPC(hipMemcpyAsync(p->items, h.data(), sizeof(HoistItem) * R, hipMemcpyHostToDevice, c->st));
+  HIPC(hipMemcpyAsync(*dev, h.data(), sizeof(HoistItem) * R, hipMemcpyHostToDevice, c->st));
   HIPC(hipStreamSynchronize(c->st));
-  p->items_epoch = c->key_epoch;
+  *epoch = c->key_epoch;
   return HE_OK;
+}
+
+// the rotations 1..n_in-1 of the vector-matrix product, item r multiplied
+// by diagonal r
+static he_status hoist_items(he_ctx* c, he_plan* p, int level) {
+  const int R = (int)p->n_in - 1;
+  std::vector<int> steps(std::max(R, 0)), diags(std::max(R, 0));
+  for (int r = 0; r < R; r++) {
+    steps[r] = r + 1;
+    diags[r] = r + 1;
+  }
+  return build_items(c, steps, diags, level, &p->items, &p->items_epoch);
+}
+
+// replication copies: R the largest power of two with n_in * R <= N/2, the
+// right rotations by n_in * m, m = 1..R-1 (no diagonal)
+static int replication_count(const he_ctx* c, uint32_t n_in) {
+  const uint32_t half = (uint32_t)c->n / 2;
+  int reps = 1;
+  while ((uint64_t)n_in * reps * 2 <= half) reps *= 2;
+  return reps;
+}
+static he_status rep_items(he_ctx* c, he_plan* p, int level) {
+  const int R = replication_count(c, p->n_in) - 1;
+  std::vector<int> steps(std::max(R, 0)), diags(std::max(R, 0), -1);
+  for (int m = 1; m <= R; m++) steps[m - 1] = (int)((long long)c->n / 2 - (long long)p->n_in * m);
+  return build_items(c, steps, diags, level, &p->rep_items, &p->rep_epoch);
 }
 
 // acc = sum_i rot_left(x, i) * diag_i, the n_in - 1 rotations hoisted: one
 // ModUp of x's poly 1, one batched inner product, one batched ModDown NTT
 // fused with the multiply-accumulate (partial sums per chunk of rotations)
-static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
+// R hoisted rotations of x by the items' steps; with diagonals (rows of
+// diags, Shoup companions at diags_sh) each rotation is multiplied by its
+// diagonal and the i = 0 term is x * diags[0]; without, the rotations and x
+// are summed.  out_scale: the result's scale.
+static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u64* diags, const u64* diags_sh,
+                              const he_ct* x, double out_scale, he_ct** out) {
   const int l = x->level, Lp = l + 1, nm = Lp + 1, n = c->n;
-  const int R = (int)p->n_in - 1;
-  TRY(hoist_items(c, p, l));
   he_ct* acc = nullptr;
-  TRY(new_ct(c, l, x->scale * c->scale, &acc));
+  TRY(new_ct(c, l, out_scale, &acc));
   CtGuard gacc{acc};
   int n_chunks = 0;
   DBuf partial;
@@ -2080,7 +2114,7 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
       HoistInner I{};
       I.ext = extp;
       I.c1 = c1;
-      I.items = p->items;
+      I.items = items;
       I.u = u.p;
       I.R = R;
       I.n_dig = Lp;
@@ -2116,9 +2150,9 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
     M.ucoef = ucoef.p;
     M.u = u.p;
     M.c0 = x->d;
-    M.diags = p->diags;
-    M.diags_sh = p->diags + (size_t)p->n_in * Lp * n;
-    M.items = p->items;
+    M.diags = diags;
+    M.diags_sh = diags_sh;
+    M.items = items;
     M.partial = partial.p;
     M.R = R;
     M.n_dig = Lp;
@@ -2134,13 +2168,14 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
     }
     // per (item, poly, limb): special limb, u limb and diagonal read, and the
     // partial sums written once per chunk
-    Prof pr(c, "hoisted_moddown", 2.0 * R * Lp, 8.0 * n * (3.0 * 2 * R * Lp + 2.0 * n_chunks * Lp));
+    Prof pr(c, diags ? "hoisted_moddown" : "hoisted_replication", 2.0 * R * Lp,
+            8.0 * n * ((diags ? 3.0 : 2.0) * 2 * R * Lp + 2.0 * n_chunks * Lp));
     hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "hoisted moddown: %s", hipGetErrorString(e));
   }
   {
     Prof pr(c, "pointwise");
-    hipError_t e = launch_mac_finish(c->log_n, partial.p, n_chunks, x->d, p->diags, acc->d, Lp, c->d_primes, c->st);
+    hipError_t e = launch_mac_finish(c->log_n, partial.p, n_chunks, x->d, diags, acc->d, Lp, c->d_primes, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "mac finish: %s", hipGetErrorString(e));
   }
   *out = acc;
@@ -2148,28 +2183,24 @@ static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out)
   return HE_OK;
 }
 
+static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
+  TRY(hoist_items(c, p, x->level));
+  const size_t rows = (size_t)p->n_in * (x->level + 1) * c->n;
+  return hoisted_core(c, p->items, (int)p->n_in - 1, p->diags, p->diags + rows, x, x->scale * c->scale, out);
+}
+
+// x replicated: x plus its hoisted right rotations by n_in * m
+static he_status hoisted_rep(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
+  TRY(rep_items(c, p, x->level));
+  return hoisted_core(c, p->rep_items, replication_count(c, p->n_in) - 1, nullptr, nullptr, x, x->scale, out);
+}
+
 static he_status matmul_apply(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
-  const uint32_t half = (uint32_t)c->n / 2;
   CtGuard gxr;
-  TRY(drop_copy(c, x, x->level, &gxr.p));
-  uint32_t reps = 1;
-  while ((uint64_t)p->n_in * reps * 2 <= half) {
-    const int st = norm_step(c, (long long)half - (long long)p->n_in * reps);
-    he_ct* y = nullptr;
-    if (st == 0) {
-      TRY(he_add(c, gxr.p, gxr.p, &y));
-    } else {
-      TRY(new_ct(c, gxr.p->level, gxr.p->scale, &y));
-      he_status s = rotate_multi(c, gxr.p->d, 1, gxr.p->level, &st, y->d, true);
-      if (s != HE_OK) {
-        he_ct_free(y);
-        return s;
-      }
-    }
-    he_ct_free(gxr.p);
-    gxr.p = y;
-    reps *= 2;
-  }
+  if (replication_count(c, p->n_in) > 1)
+    TRY(hoisted_rep(c, p, x, &gxr.p));
+  else
+    TRY(drop_copy(c, x, x->level, &gxr.p));
   CtGuard acc;
   TRY(hoisted_mac(c, p, gxr.p, &acc.p));
   // rescale with the bias added to poly 0 in the same kernel
@@ -2535,6 +2566,7 @@ void he_plan_free(he_plan* p) {
   he_pt_free(p->bias);
   if (p->diags) p->ctx->pool.put(p->diags);
   if (p->items) p->ctx->pool.put(p->items);
+  if (p->rep_items) p->ctx->pool.put(p->rep_items);
   delete p;
 }
 

@@ -257,7 +257,7 @@ hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev
 // ModDown of every item fused with the diagonal multiply-accumulate: WG
 // (chunk c, poly k, modulus t) sums over its items r:
 //   ((u[r][k][t] - NTT(r_r - h)) p^-1 + [k == 0] c0[t][src_r]) * diag[r][t]
-// into partial[c][k][t].
+// into partial[c][k][t] (without the diagonal factor when diags is NULL).
 struct HoistMac {
   const u64* ucoef;  // [R][2][N] special-prime limb of u, coefficient form
   const u64* u;      // [R][2][nm][N]
@@ -272,7 +272,8 @@ struct HoistMac {
 };
 hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const PrimeDev* primes,
                                       const NttTables& tabs, hipStream_t st);
-// out[k][t] = x[k][t] * diag0[t] + sum_c partial[c][k][t]
+// out[k][t] = x[k][t] * diag0[t] + sum_c partial[c][k][t] (x[k][t] itself
+// when diag0 is NULL)
 hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const u64* x,
                              const u64* diag0, u64* out, int n_dig, const PrimeDev* primes,
                              hipStream_t st);

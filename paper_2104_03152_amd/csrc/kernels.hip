@@ -382,6 +382,20 @@ __global__ void k_mac_finish(int log_n, const u64* __restrict__ partial, int n_c
   out[e] = s;
 }
 
+// out[k][t] = x[k][t] + sum_c partial[c][k][t] (the replication: no diagonal)
+__global__ void k_rep_finish(int log_n, const u64* __restrict__ partial, int n_chunks, const u64* __restrict__ x,
+                             u64* __restrict__ out, int n_dig, const PrimeDev* __restrict__ primes) {
+  const int n = 1 << log_n;
+  const long long per = 2LL * n_dig * n;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= per) return;
+  const int t = (int)((e >> log_n) % n_dig);
+  const u64 q = primes[t].q;
+  u64 s = x[e];
+  for (int c = 0; c < n_chunks; c++) s = addmod(s, partial[(size_t)c * per + e], q);
+  out[e] = s;
+}
+
 inline dim3 grid_for(long long total) { return dim3((unsigned)((total + BLK - 1) / BLK)); }
 
 }  // namespace
@@ -553,7 +567,11 @@ hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev
 hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const u64* x, const u64* diag0, u64* out,
                              int n_dig, const PrimeDev* primes, hipStream_t st) {
   const long long total = (2LL * n_dig) << log_n;
-  hipLaunchKernelGGL(k_mac_finish, grid_for(total), dim3(BLK), 0, st, log_n, partial, n_chunks, x, diag0, out,
-                     n_dig, primes);
+  if (diag0)
+    hipLaunchKernelGGL(k_mac_finish, grid_for(total), dim3(BLK), 0, st, log_n, partial, n_chunks, x, diag0, out,
+                       n_dig, primes);
+  else
+    hipLaunchKernelGGL(k_rep_finish, grid_for(total), dim3(BLK), 0, st, log_n, partial, n_chunks, x, out, n_dig,
+                       primes);
   return hipGetLastError();
 }

@@ -1045,7 +1045,7 @@ k_ks_moddown_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Nt
 // epilogue.  Workgroup (chunk, k, t) loops over its items; each thread
 // keeps the running sums of its E output words in registers and writes
 // them to its workgroup's slice of `partial` once at the end.
-template <int LOGN, class Ar>
+template <int LOGN, bool DIAG, class Ar>
 __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __restrict__ primes,
                                            const typename Ar::TW* __restrict__ W, const PrimeDev& P, int chunk,
                                            int k, int t, u64* lds) {
@@ -1093,16 +1093,28 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     }
     __syncthreads();
     const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
-    const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
-    const u64* __restrict__ dgs = J.diags_sh + ((size_t)it.diag * J.n_dig + t) * N;
     const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
+    if constexpr (DIAG) {
+      const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
+      const u64* __restrict__ dgs = J.diags_sh + ((size_t)it.diag * J.n_dig + t) * N;
 #pragma unroll
-    for (int e = 0; e < C::E; e++) {
-      const int idx = tid + C::T * e;
-      const u64 v = lds[pad(idx)];
-      u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
-      if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
-      acc[e] = addmod(acc[e], shoup(ks, dg[idx], dgs[idx], q), q);
+      for (int e = 0; e < C::E; e++) {
+        const int idx = tid + C::T * e;
+        const u64 v = lds[pad(idx)];
+        u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+        if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
+        acc[e] = addmod(acc[e], shoup(ks, dg[idx], dgs[idx], q), q);
+      }
+    } else {
+      // a replication: the rotations are only summed
+#pragma unroll
+      for (int e = 0; e < C::E; e++) {
+        const int idx = tid + C::T * e;
+        const u64 v = lds[pad(idx)];
+        u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+        if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
+        acc[e] = addmod(acc[e], ks, q);
+      }
     }
     __syncthreads();
   }
@@ -1112,7 +1124,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
 
 // one workgroup per compute unit: the registers hold the running sums
 // (two workgroups would spill them)
-template <int LOGN>
+template <int LOGN, bool DIAG>
 __global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::T / 256)
 k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = Cfg<LOGN>::N;
@@ -1123,11 +1135,11 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTabl
   const int k = kt / J.n_dig, t = kt - k * J.n_dig;
   const PrimeDev P = primes[t];
   if (P.use_fp)
-    hoist_body<LOGN, FpAr>(J, primes, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P, chunk, k, t,
-                           lds);
+    hoist_body<LOGN, DIAG, FpAr>(J, primes, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P,
+                                 chunk, k, t, lds);
   else
-    hoist_body<LOGN, IntAr>(J, primes, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P, chunk, k,
-                            t, lds);
+    hoist_body<LOGN, DIAG, IntAr>(J, primes, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P,
+                                  chunk, k, t, lds);
 }
 
 // ---------------- launchers ----------------
@@ -1194,18 +1206,26 @@ hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const NttTables& 
   return hipGetLastError();
 }
 
-template <int LOGN>
-hipError_t hoist_launch(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+template <int LOGN, bool DIAG>
+hipError_t hoist_launch_as(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
   using C = Cfg<LOGN>;
   const size_t shm = sizeof(u64) * C::lds_words();
   static bool attr = false;
-  hipError_t e = set_lds(k_hoist_mac<LOGN>, shm, attr);
+  hipError_t e = set_lds(k_hoist_mac<LOGN, DIAG>, shm, attr);
   if (e != hipSuccess) return e;
   const int n_chunks = (J.R + J.chunk - 1) / J.chunk;
   const int blocks = n_chunks * 2 * J.n_dig;
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_hoist_mac<LOGN>), dim3(blocks), dim3(C::T), shm, st, J, primes, tabs);
+  hipLaunchKernelGGL((k_hoist_mac<LOGN, DIAG>), dim3(blocks), dim3(C::T), shm, st, J, primes, tabs);
   return hipGetLastError();
+}
+
+// the diagonal product and the plain sum (a replication) are separate
+// instantiations: no branch on the diagonal pointer inside the kernel
+template <int LOGN>
+hipError_t hoist_launch(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+  return J.diags ? hoist_launch_as<LOGN, true>(J, primes, tabs, st)
+                 : hoist_launch_as<LOGN, false>(J, primes, tabs, st);
 }
 
 template <int LOGN>

@@ -44,6 +44,16 @@ def cnn_inputs(seed=2):
     return dict(img=img, conv_k=conv_k, conv_b=conv_b, w1=w1, b1=b1, w2=w2, b2=b2)
 
 
+def replication_steps(n_in, n_slots):
+    """Left-rotation steps that replicate an n_in-vector R times (R the
+    largest power of two with n_in * R <= n_slots): right rotations by
+    n_in * m, m = 1..R-1."""
+    reps = 1
+    while n_in * reps * 2 <= n_slots:
+        reps *= 2
+    return [n_slots - n_in * m for m in range(1, reps)]
+
+
 def cnn_rotation_steps(n_slots=4096):
     """Left-rotation steps the MNIST-shaped network uses, each with the
     highest level it is used at (levels counted as in a 7-data-prime chain:
@@ -63,17 +73,13 @@ def cnn_rotation_steps(n_slots=4096):
     for c in range(1, s["channels"]):       # channel packing: right by 64c
         use(n_slots - win * c, 4)
     n_in = s["channels"] * win
-    reps = 1
-    while n_in * reps * 2 <= n_slots:       # FC1 replication
-        use(n_slots - n_in * reps, 3)
-        reps *= 2
+    for st in replication_steps(n_in, n_slots):   # FC1 replication
+        use(st, 3)
     for i in range(1, n_in):                # FC1 diagonals
         use(i, 3)
     n_in = s["hidden"]
-    reps = 1
-    while n_in * reps * 2 <= n_slots:       # FC2 replication
-        use(n_slots - n_in * reps, 1)
-        reps *= 2
+    for st in replication_steps(n_in, n_slots):   # FC2 replication
+        use(st, 1)
     for i in range(1, n_in):                # FC2 diagonals
         use(i, 1)
     return levels

@@ -57,12 +57,7 @@ def test_matmul_bit_exact(deep, n_in, n_out):
     W = rng.normal(0, 0.1, (n_in, n_out))
     b = rng.normal(0, 0.1, n_out)
     x = rng.uniform(-1, 1, n_in)
-    reps = 1
-    steps = []
-    while n_in * reps * 2 <= half:
-        steps.append(half - n_in * reps)
-        reps *= 2
-    _keys(P, steps + list(range(1, n_in)))
+    _keys(P, I.replication_steps(n_in, half) + list(range(1, n_in)))
     g, o = _enc(P, x, 2, 3)
     say("matmul", n_in, n_out)
     gy, oy = P.H.he_enc_matmul(P.g, g, W, b), P.o.matmul(o, W, b)

@@ -6,6 +6,7 @@ new input data is copied into the captured input."""
 import numpy as np
 import pytest
 
+from paper_2104_03152_amd import inputs as I
 from tests.gpu_common import Pair, say
 
 pytestmark = pytest.mark.gpu
@@ -24,8 +25,8 @@ def test_graph_replays_match_eager():
     H, g = P.H, P.g
     rng = np.random.default_rng(12)
     # rotations: 1, 2, 4 (sum of 8 slots), 1..15 (the hoisted product of a
-    # 16-input matrix) and 2048 - 16 * 2^j (its replication by doubling)
-    steps = sorted(set([1, 2, 4] + list(range(1, 16)) + [2048 - 16 * (1 << j) for j in range(7)]))
+    # 16-input matrix) and its replication steps
+    steps = sorted(set([1, 2, 4] + list(range(1, 16)) + I.replication_steps(16, 2048)))
     for st in steps:
         H.he_keygen_galois(g, st, -1)
     W = rng.normal(0, 0.1, (16, 6))

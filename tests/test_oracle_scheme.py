@@ -317,10 +317,8 @@ def test_composites_vs_fp64(deep):
     W = rng.normal(0, 0.1, (n_in, n_out))
     b = rng.normal(0, 0.1, n_out)
     xv = rng.uniform(-1, 1, n_in)
-    reps = 1
-    while n_in * reps * 2 <= half:
-        o.galois_keygen(half - n_in * reps)
-        reps *= 2
+    for st in I.replication_steps(n_in, half):
+        o.galois_keygen(st)
     for i in range(1, n_in):
         o.galois_keygen(i)
     cx = o.encrypt(o.encode(xv, o.scale, 3), 2)
@@ -360,7 +358,8 @@ def test_cnn_vs_fp64_full_size():
     o = O.Oracle(p["log_n"], p["bits"], p["scale"], p["seed"])
     o.keygen()
     steps = I.cnn_rotation_steps()
-    assert len(steps) == 265
+    # conv 6, packing 3, FC1 15 + 255, FC2 63 + 63 steps; their union
+    assert len(steps) == 315
     for st, lv in sorted(steps.items()):
         o.galois_keygen(st, lv)
     d = I.cnn_inputs()
