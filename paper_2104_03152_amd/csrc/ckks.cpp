@@ -1906,9 +1906,8 @@ he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t
       }
     }
   }
-  // device buffer: [n_in][Lp][N] diagonals (NTT domain), then their Shoup
-  // companions floor(d 2^64 / q) for the fused multiply-accumulate
-  p->diags = (u64*)c->pool.get(2 * words * sizeof(u64));
+  // device buffer: [n_in][Lp][N] diagonals (NTT domain)
+  p->diags = (u64*)c->pool.get(words * sizeof(u64));
   he_status s = p->diags ? HE_OK : fail(HE_EOOM, "diagonal allocation failed");
   if (s == HE_OK) {
     hipError_t e = hipMemcpyAsync(p->diags, h.data(), words * sizeof(u64), hipMemcpyHostToDevice, c->st);
@@ -1916,21 +1915,6 @@ he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t
     if (e != hipSuccess) s = fail(HE_EHIP, "diagonal upload: %s", hipGetErrorString(e));
   }
   if (s == HE_OK) s = ntt_rows(c, true, p->diags, p->diags, (int)n_in, Lp, (long long)Lp * n, (long long)Lp * n);
-  if (s == HE_OK) {
-    hipError_t e = hipMemcpyAsync(h.data(), p->diags, words * sizeof(u64), hipMemcpyDeviceToHost, c->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    if (e != hipSuccess) s = fail(HE_EHIP, "diagonal download: %s", hipGetErrorString(e));
-  }
-  if (s == HE_OK) {
-    for (uint32_t i = 0; i < n_in; i++)
-      for (int t = 0; t < Lp; t++) {
-        u64* row = h.data() + ((size_t)i * Lp + t) * n;
-        for (int k = 0; k < n; k++) row[k] = h_shoup(row[k], c->q[t]);
-      }
-    hipError_t e = hipMemcpyAsync(p->diags + words, h.data(), words * sizeof(u64), hipMemcpyHostToDevice, c->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-    if (e != hipSuccess) s = fail(HE_EHIP, "diagonal upload: %s", hipGetErrorString(e));
-  }
   if (s == HE_OK) {
     const double post = like->scale * c->scale / (double)c->q[like->level];
     std::vector<double> b(n_out, 0.0);
@@ -2080,11 +2064,11 @@ static he_status rep_items(he_ctx* c, he_plan* p, int level) {
 // ModUp of x's poly 1, one batched inner product, one batched ModDown NTT
 // fused with the multiply-accumulate (partial sums per chunk of rotations)
 // R hoisted rotations of x by the items' steps; with diagonals (rows of
-// diags, Shoup companions at diags_sh) each rotation is multiplied by its
-// diagonal and the i = 0 term is x * diags[0]; without, the rotations and x
-// are summed.  out_scale: the result's scale.
-static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u64* diags, const u64* diags_sh,
-                              const he_ct* x, double out_scale, he_ct** out) {
+// diags) each rotation is multiplied by its diagonal and the i = 0 term is
+// x * diags[0]; without, the rotations and x are summed.  out_scale: the
+// result's scale.
+static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u64* diags, const he_ct* x,
+                              double out_scale, he_ct** out) {
   const int l = x->level, Lp = l + 1, nm = Lp + 1, n = c->n;
   he_ct* acc = nullptr;
   TRY(new_ct(c, l, out_scale, &acc));
@@ -2151,13 +2135,13 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     M.u = u.p;
     M.c0 = x->d;
     M.diags = diags;
-    M.diags_sh = diags_sh;
     M.items = items;
     M.partial = partial.p;
     M.R = R;
     M.n_dig = Lp;
     M.nm = nm;
     M.chunk = chunk;
+    M.n_units = n_chunks * Lp;
     M.special_prime = c->L;
     M.h_src = (c->q[c->L] - 1) / 2;
     const size_t np = c->q.size();
@@ -2185,14 +2169,13 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
 
 static he_status hoisted_mac(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
   TRY(hoist_items(c, p, x->level));
-  const size_t rows = (size_t)p->n_in * (x->level + 1) * c->n;
-  return hoisted_core(c, p->items, (int)p->n_in - 1, p->diags, p->diags + rows, x, x->scale * c->scale, out);
+  return hoisted_core(c, p->items, (int)p->n_in - 1, p->diags, x, x->scale * c->scale, out);
 }
 
 // x replicated: x plus its hoisted right rotations by n_in * m
 static he_status hoisted_rep(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {
   TRY(rep_items(c, p, x->level));
-  return hoisted_core(c, p->rep_items, replication_count(c, p->n_in) - 1, nullptr, nullptr, x, x->scale, out);
+  return hoisted_core(c, p->rep_items, replication_count(c, p->n_in) - 1, nullptr, x, x->scale, out);
 }
 
 static he_status matmul_apply(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out) {

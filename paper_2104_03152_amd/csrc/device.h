@@ -258,15 +258,18 @@ hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev
 // (chunk c, poly k, modulus t) sums over its items r:
 //   ((u[r][k][t] - NTT(r_r - h)) p^-1 + [k == 0] c0[t][src_r]) * diag[r][t]
 // into partial[c][k][t] (without the diagonal factor when diags is NULL).
+// The two workgroups (k = 0, 1) of one (chunk, t) run on the same XCD, one
+// after the other in dispatch order, so the second reads the diagonals
+// from that XCD's L2.
 struct HoistMac {
   const u64* ucoef;  // [R][2][N] special-prime limb of u, coefficient form
   const u64* u;      // [R][2][nm][N]
   const u64* c0;     // [n_dig][N] poly 0 of the input (NTT domain)
-  const u64* diags;     // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
-  const u64* diags_sh;  // their Shoup companions, same layout
+  const u64* diags;  // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
   const HoistItem* items;
   u64* partial;      // [n_chunks][2][n_dig][N]
   int R, n_dig, nm, chunk, special_prime;
+  int n_units;       // n_chunks * n_dig
   u64 h_src;
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
 };

@@ -1095,15 +1095,16 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
     const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
     if constexpr (DIAG) {
+      // Barrett product with the diagonal: no precomputed companion, so
+      // one diagonal word per output word is read
       const u64* __restrict__ dg = J.diags + ((size_t)it.diag * J.n_dig + t) * N;
-      const u64* __restrict__ dgs = J.diags_sh + ((size_t)it.diag * J.n_dig + t) * N;
 #pragma unroll
       for (int e = 0; e < C::E; e++) {
         const int idx = tid + C::T * e;
         const u64 v = lds[pad(idx)];
         u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
         if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
-        acc[e] = addmod(acc[e], shoup(ks, dg[idx], dgs[idx], q), q);
+        acc[e] = addmod(acc[e], mulmod(ks, dg[idx], P), q);
       }
     } else {
       // a replication: the rotations are only summed
@@ -1129,10 +1130,14 @@ __global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::T / 256)
 k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = Cfg<LOGN>::N;
   extern __shared__ u64 lds[];
-  const int pairs = 2 * J.n_dig;
-  const int chunk = blockIdx.x / pairs;
-  const int kt = blockIdx.x - chunk * pairs;
-  const int k = kt / J.n_dig, t = kt - k * J.n_dig;
+  // block b runs on XCD b % 8: blocks b and b + 8 (same XCD, consecutive
+  // there) are the two polys of one (chunk, t) unit
+  const int b = blockIdx.x;
+  const int slot = b >> 3;
+  const int k = slot & 1;
+  const int unit = ((slot >> 1) << 3) | (b & 7);
+  if (unit >= J.n_units) return;
+  const int chunk = unit / J.n_dig, t = unit - chunk * J.n_dig;
   const PrimeDev P = primes[t];
   if (P.use_fp)
     hoist_body<LOGN, DIAG, FpAr>(J, primes, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P,
@@ -1214,8 +1219,10 @@ hipError_t hoist_launch_as(const HoistMac& J, const PrimeDev* primes, const NttT
   hipError_t e = set_lds(k_hoist_mac<LOGN, DIAG>, shm, attr);
   if (e != hipSuccess) return e;
   const int n_chunks = (J.R + J.chunk - 1) / J.chunk;
-  const int blocks = n_chunks * 2 * J.n_dig;
-  if (blocks <= 0) return hipSuccess;
+  if (n_chunks <= 0 || J.n_units != n_chunks * J.n_dig) return hipErrorInvalidValue;
+  // two blocks per unit, units padded to a multiple of 8 (the padding
+  // blocks exit at once)
+  const int blocks = ((J.n_units + 7) / 8) * 16;
   hipLaunchKernelGGL((k_hoist_mac<LOGN, DIAG>), dim3(blocks), dim3(C::T), shm, st, J, primes, tabs);
   return hipGetLastError();
 }
