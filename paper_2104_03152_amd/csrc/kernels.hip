@@ -335,36 +335,45 @@ __global__ void k_mont(int n, u64* data, long long total, int to, ModList mods,
 }
 
 // batched inner product of hoisted rotations: every item reads the shared
-// ModUp digits at its own Galois source index
+// ModUp digits at its own Galois source index.  Each thread computes two
+// neighbouring words (16-byte key loads and output stores); the digits are
+// gathered word by word (they stay in L2, shared by all items).
 __global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restrict__ primes) {
   const int n = 1 << log_n;
   const int nt = J.t_end - J.t_begin;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)J.R * nt * n) return;
-  const int i = (int)(e & (n - 1));
-  const long long rt = e >> log_n;
+  if (e >= (long long)J.R * nt * (n >> 1)) return;
+  const int i = (int)(e & ((n >> 1) - 1)) << 1;
+  const long long rt = e >> (log_n - 1);
   const int t = J.t_begin + (int)(rt % nt);
   const int r = (int)(rt / nt);
   const HoistItem it = J.items[r];
-  const int src = gal_src(i, log_n, it.g);
+  const int src0 = gal_src(i, log_n, it.g), src1 = gal_src(i + 1, log_n, it.g);
   const int kt = t < J.n_dig ? t : it.km - 1;
   const PrimeDev P = primes[t < J.n_dig ? t : J.special_prime];
   const size_t ks_k = (size_t)it.km * n, ks_j = 2 * ks_k;
   const u64* kp = it.key + (size_t)kt * n + i;
-  u64 r0 = 0, r1 = 0;
+  u64 r00 = 0, r01 = 0, r10 = 0, r11 = 0;  // [poly][word]
   for (int j0 = 0; j0 < J.n_dig; j0 += 8) {
-    U128 acc0 = {0, 0}, acc1 = {0, 0};
+    U128 a00 = {0, 0}, a01 = {0, 0}, a10 = {0, 0}, a11 = {0, 0};
     const int j1 = min(J.n_dig, j0 + 8);
     for (int j = j0; j < j1; j++) {
-      const u64 d = (j == t) ? J.c1[(size_t)t * n + src] : J.ext[((size_t)j * J.nm + t) * n + src];
-      acc0 = add128(acc0, mul_wide(d, kp[j * ks_j]));
-      acc1 = add128(acc1, mul_wide(d, kp[j * ks_j + ks_k]));
+      const u64* dj = (j == t) ? J.c1 + (size_t)t * n : J.ext + ((size_t)j * J.nm + t) * n;
+      const u64 d0 = dj[src0], d1 = dj[src1];
+      const ulonglong2 k0 = *reinterpret_cast<const ulonglong2*>(kp + j * ks_j);
+      const ulonglong2 k1 = *reinterpret_cast<const ulonglong2*>(kp + j * ks_j + ks_k);
+      a00 = add128(a00, mul_wide(d0, k0.x));
+      a01 = add128(a01, mul_wide(d1, k0.y));
+      a10 = add128(a10, mul_wide(d0, k1.x));
+      a11 = add128(a11, mul_wide(d1, k1.y));
     }
-    r0 = addmod(r0, mont_reduce(acc0, P), P.q);
-    r1 = addmod(r1, mont_reduce(acc1, P), P.q);
+    r00 = addmod(r00, mont_reduce(a00, P), P.q);
+    r01 = addmod(r01, mont_reduce(a01, P), P.q);
+    r10 = addmod(r10, mont_reduce(a10, P), P.q);
+    r11 = addmod(r11, mont_reduce(a11, P), P.q);
   }
-  J.u[(((size_t)r * 2 + 0) * J.nm + t) * n + i] = r0;
-  J.u[(((size_t)r * 2 + 1) * J.nm + t) * n + i] = r1;
+  *reinterpret_cast<ulonglong2*>(J.u + (((size_t)r * 2 + 0) * J.nm + t) * n + i) = make_ulonglong2(r00, r01);
+  *reinterpret_cast<ulonglong2*>(J.u + (((size_t)r * 2 + 1) * J.nm + t) * n + i) = make_ulonglong2(r10, r11);
 }
 
 __global__ void k_mac_finish(int log_n, const u64* __restrict__ partial, int n_chunks, const u64* __restrict__ x,
@@ -558,7 +567,8 @@ hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
 }
 
 hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev* primes, hipStream_t st) {
-  const long long total = ((long long)job.R * (job.t_end - job.t_begin)) << log_n;
+  // two words per thread
+  const long long total = ((long long)job.R * (job.t_end - job.t_begin)) << (log_n - 1);
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_inner_hoisted, grid_for(total), dim3(BLK), 0, st, log_n, job, primes);
   return hipGetLastError();
