@@ -229,10 +229,13 @@ struct PassTw {
 // pass's are loaded before this pass's butterflies, so their latency
 // overlaps arithmetic and the exchange (one-wave workgroups have no other
 // waves to hide it); otherwise each stage loads its own.
-template <class S, int LOGS, int P, class Ar, bool PRE>
+// With TWL (PRE false, toff 0), the twiddles of every stage but the last
+// (indices below N/2) come from the LDS copy Wl, the last stage's from W.
+template <class S, int LOGS, int P, class Ar, bool PRE, bool TWL = false>
 __device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, const typename Ar::TW* __restrict__ W,
                                            const Ar& ar, int tid, int toff,
-                                           const PassTw<S, LOGS, P, true, Ar>* tw = nullptr) {
+                                           const PassTw<S, LOGS, P, true, Ar>* tw = nullptr,
+                                           const typename Ar::TW* Wl = nullptr) {
   constexpr int R = S::bits(P);
   constexpr int LO = S::flo(P);
   constexpr int G = S::E >> R;
@@ -256,7 +259,10 @@ __device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, 
           ar.fwd(x[i0], x[i1], tw->t[u * PER + (1 << (R - 1 - pb)) - 1 + (c >> (pb + 1))]);
         } else {
           const int ti = base + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
-          ar.fwd(x[i0], x[i1], W[tw_index<S, LO>(ti)]);
+          if (TWL && lb > 0)
+            ar.fwd(x[i0], x[i1], Wl[tw_index<S, LO>(ti)]);
+          else
+            ar.fwd(x[i0], x[i1], W[tw_index<S, LO>(ti)]);
         }
       }
     }
@@ -264,7 +270,7 @@ __device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, 
   if constexpr (MORE) {
     if (P > 0) __syncthreads();
     exchange<S, LO, R, S::flo(P + 1), S::bits(P + 1), Ar>(x, lds, tid);
-    fwd_passes<S, LOGS, P + 1, Ar, PRE>(x, lds, W, ar, tid, toff, &nxt);
+    fwd_passes<S, LOGS, P + 1, Ar, PRE, TWL>(x, lds, W, ar, tid, toff, &nxt, Wl);
   }
 }
 
@@ -1045,6 +1051,17 @@ k_ks_moddown_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Nt
 // epilogue.  Workgroup (chunk, k, t) loops over its items; each thread
 // keeps the running sums of its E output words in registers and writes
 // them to its workgroup's slice of `partial` once at the end.
+// LDS words of the multiply-accumulate kernel: the exchange buffer, plus
+// the twiddle copy (N/2 entries of 16 bytes) where both fit in 160 KiB
+template <int LOGN>
+constexpr bool hoist_lds_twiddles() {
+  return (Cfg<LOGN>::lds_words() + (1 << LOGN)) * 8 <= 160 * 1024;
+}
+template <int LOGN>
+constexpr int hoist_lds_words() {
+  return Cfg<LOGN>::lds_words() + (hoist_lds_twiddles<LOGN>() ? (1 << LOGN) : 0);
+}
+
 template <int LOGN, bool DIAG, class Ar>
 __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __restrict__ primes,
                                            const typename Ar::TW* __restrict__ W, const PrimeDev& P, int chunk,
@@ -1063,6 +1080,14 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
   u64 acc[C::E];
 #pragma unroll
   for (int e = 0; e < C::E; e++) acc[e] = 0;
+  // this workgroup's prime is fixed: its twiddles below N/2 (every stage
+  // but the last) are copied to LDS once and read from there for all items
+  constexpr bool TWL = hoist_lds_twiddles<LOGN>();
+  typename Ar::TW* Wl = reinterpret_cast<typename Ar::TW*>(lds + C::lds_words());
+  if constexpr (TWL) {
+    for (int i = tid; i < N / 2; i += C::T) Wl[i] = W[i];
+    __syncthreads();
+  }
   for (int r = rb; r < re; r++) {
     const HoistItem it = J.items[r];
     const u64* __restrict__ src = J.ucoef + ((size_t)r * 2 + k) * N;
@@ -1081,7 +1106,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     // every stage's twiddles in registers across items)
     const typename Ar::TW* Wr = W;
     asm volatile("" : "+v"(Wr));
-    fwd_passes<Cfg<LOGN>, LOGN, 0, Ar, false>(x, lds, Wr, ar, tid, 0);
+    fwd_passes<Cfg<LOGN>, LOGN, 0, Ar, false, TWL>(x, lds, Wr, ar, tid, 0, nullptr, Wl);
     // final values through LDS so the epilogue runs in natural order:
     // coalesced accesses and a bounded number of loads in flight
     __syncthreads();
@@ -1214,7 +1239,7 @@ hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const NttTables& 
 template <int LOGN, bool DIAG>
 hipError_t hoist_launch_as(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
   using C = Cfg<LOGN>;
-  const size_t shm = sizeof(u64) * C::lds_words();
+  const size_t shm = sizeof(u64) * hoist_lds_words<LOGN>();
   static bool attr = false;
   hipError_t e = set_lds(k_hoist_mac<LOGN, DIAG>, shm, attr);
   if (e != hipSuccess) return e;
