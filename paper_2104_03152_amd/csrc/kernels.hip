@@ -376,6 +376,20 @@ __global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restr
   *reinterpret_cast<ulonglong2*>(J.u + (((size_t)r * 2 + 1) * J.nm + t) * n + i) = make_ulonglong2(r10, r11);
 }
 
+// s + sum_c p[c * stride] mod q, eight loads in flight at a time
+__device__ __forceinline__ u64 add_partials(u64 s, const u64* __restrict__ p, long long stride, int n, u64 q) {
+  int c = 0;
+  for (; c + 8 <= n; c += 8) {
+    u64 v[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) v[m] = p[(size_t)(c + m) * stride];
+#pragma unroll
+    for (int m = 0; m < 8; m++) s = addmod(s, v[m], q);
+  }
+  for (; c < n; c++) s = addmod(s, p[(size_t)c * stride], q);
+  return s;
+}
+
 __global__ void k_mac_finish(int log_n, const u64* __restrict__ partial, int n_chunks, const u64* __restrict__ x,
                              const u64* __restrict__ diag0, u64* __restrict__ out, int n_dig,
                              const PrimeDev* __restrict__ primes) {
@@ -387,8 +401,7 @@ __global__ void k_mac_finish(int log_n, const u64* __restrict__ partial, int n_c
   const int i = (int)(e & (n - 1));
   const PrimeDev P = primes[t];
   u64 s = mulmod(x[e], diag0[(size_t)t * n + i], P);
-  for (int c = 0; c < n_chunks; c++) s = addmod(s, partial[(size_t)c * per + e], P.q);
-  out[e] = s;
+  out[e] = add_partials(s, partial + e, per, n_chunks, P.q);
 }
 
 // out[k][t] = x[k][t] + sum_c partial[c][k][t] (the replication: no diagonal)
@@ -400,9 +413,7 @@ __global__ void k_rep_finish(int log_n, const u64* __restrict__ partial, int n_c
   if (e >= per) return;
   const int t = (int)((e >> log_n) % n_dig);
   const u64 q = primes[t].q;
-  u64 s = x[e];
-  for (int c = 0; c < n_chunks; c++) s = addmod(s, partial[(size_t)c * per + e], q);
-  out[e] = s;
+  out[e] = add_partials(x[e], partial + e, per, n_chunks, q);
 }
 
 inline dim3 grid_for(long long total) { return dim3((unsigned)((total + BLK - 1) / BLK)); }
