@@ -898,6 +898,8 @@ __device__ __forceinline__ void ks_inner(const KsJob& J, const PrimeDev& P, int 
 #pragma unroll
     for (int e = 0; e < E; e++) acc[e] = U128{0, 0};
     const int j1 = min(J.Lp, j0 + 8);
+    // unrolled so that the key loads of several digits are in flight at once
+#pragma unroll 2
     for (int j = j0; j < j1; j++) {
       u64 dj[E], kj[E];
 #pragma unroll
