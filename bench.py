@@ -9,7 +9,7 @@ path: NTT/INTT, pointwise products, key switching (ModUp, inner product,
 ModDown) for 357 rotations/relinearisations, automorphisms and rescales.
 
 Prints one JSON line (see the field list at the bottom).  --gpus N with N > 1
-exits: this build measures one GPU.
+exits: the library runs on one GPU.
 """
 import argparse
 import json
@@ -110,7 +110,7 @@ def main():
                     help="only copy a 2 GiB buffer three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(requests/ciphertexts would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 

@@ -1053,22 +1053,31 @@ k_ks_moddown_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Nt
 // epilogue.  Workgroup (chunk, k, t) loops over its items; each thread
 // keeps the running sums of its E output words in registers and writes
 // them to its workgroup's slice of `partial` once at the end.
+// words per thread of the multiply-accumulate kernel's NTT
+#ifndef HE_HOIST_LOGE
+#define HE_HOIST_LOGE 0
+#endif
+constexpr int hoist_loge(int logn) { return HE_HOIST_LOGE > 0 ? HE_HOIST_LOGE : single_loge(logn); }
+template <int LOGN>
+struct HCfg : Sched<LOGN, 0, LOGN, hoist_loge(LOGN)> {
+  static constexpr int N = 1 << LOGN;
+};
 // LDS words of the multiply-accumulate kernel: the exchange buffer, plus
 // the twiddle copy (N/2 entries of 16 bytes) where both fit in 160 KiB
 template <int LOGN>
 constexpr bool hoist_lds_twiddles() {
-  return (Cfg<LOGN>::lds_words() + (1 << LOGN)) * 8 <= 160 * 1024;
+  return (HCfg<LOGN>::lds_words() + (1 << LOGN)) * 8 <= 160 * 1024;
 }
 template <int LOGN>
 constexpr int hoist_lds_words() {
-  return Cfg<LOGN>::lds_words() + (hoist_lds_twiddles<LOGN>() ? (1 << LOGN) : 0);
+  return HCfg<LOGN>::lds_words() + (hoist_lds_twiddles<LOGN>() ? (1 << LOGN) : 0);
 }
 
 template <int LOGN, bool DIAG, class Ar>
 __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __restrict__ primes,
                                            const typename Ar::TW* __restrict__ W, const PrimeDev& P, int chunk,
                                            int k, int t, u64* lds) {
-  using C = Cfg<LOGN>;
+  using C = HCfg<LOGN>;
   constexpr int N = C::N;
   constexpr int R0 = C::bits(0), LO0 = LOGN - R0, G0 = C::E >> R0;
   constexpr int RF = C::bits(C::NP - 1), GF = C::E >> RF;
@@ -1108,7 +1117,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     // every stage's twiddles in registers across items)
     const typename Ar::TW* Wr = W;
     asm volatile("" : "+v"(Wr));
-    fwd_passes<Cfg<LOGN>, LOGN, 0, Ar, false, TWL>(x, lds, Wr, ar, tid, 0, nullptr, Wl);
+    fwd_passes<C, LOGN, 0, Ar, false, TWL>(x, lds, Wr, ar, tid, 0, nullptr, Wl);
     // final values through LDS so the epilogue runs in natural order:
     // coalesced accesses and a bounded number of loads in flight
     __syncthreads();
@@ -1153,9 +1162,9 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
 // one workgroup per compute unit: the registers hold the running sums
 // (two workgroups would spill them)
 template <int LOGN, bool DIAG>
-__global__ void __launch_bounds__(Cfg<LOGN>::T, Cfg<LOGN>::T / 256)
+__global__ void __launch_bounds__(HCfg<LOGN>::T, HCfg<LOGN>::T / 256)
 k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
-  constexpr int N = Cfg<LOGN>::N;
+  constexpr int N = HCfg<LOGN>::N;
   extern __shared__ u64 lds[];
   // block b runs on XCD b % 8: blocks b and b + 8 (same XCD, consecutive
   // there) are the two polys of one (chunk, t) unit
@@ -1240,7 +1249,7 @@ hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const NttTables& 
 
 template <int LOGN, bool DIAG>
 hipError_t hoist_launch_as(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
-  using C = Cfg<LOGN>;
+  using C = HCfg<LOGN>;
   const size_t shm = sizeof(u64) * hoist_lds_words<LOGN>();
   static bool attr = false;
   hipError_t e = set_lds(k_hoist_mac<LOGN, DIAG>, shm, attr);

@@ -110,7 +110,7 @@ def trace(db_path, out_md, command, bench_out=None):
     for name, dur in _window(rows):
         per[short(name)].append(float(dur))
     tot = sum(sum(v) for v in per.values())
-    lines = ["# Kernel-trace statistics", "", "Command (repo root on the GPU box):", "",
+    lines = ["# Kernel-trace statistics", "", "Command (run from the repository root):", "",
              "    " + command, "",
              "## Launch families (N = 8192)", "",
              "Kernel time per family launch over the timed steps (sum of its kernels); beside it "
@@ -153,7 +153,7 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, out_json, out_md, command)
     ffam, wfam = _families(fe), _families(wr)
     fams = {}
     lines = ["# HBM traffic from PMC counters (MNIST-shaped CNN at N = 8192)", "",
-             "Commands (repo root on the GPU box):", "", "    " + command, "",
+             "Commands (run from the repository root):", "", "    " + command, "",
              "Calibration: a plain 2 GiB device copy reads FETCH_SIZE = %.0f KiB and "
              "WRITE_SIZE = %.0f KiB per dispatch; scale factors %.4f (fetch) and %.4f (write)."
              % (cf, cw, fetch_scale, write_scale), "",
