@@ -229,9 +229,9 @@ struct PassTw {
 // pass's are loaded before this pass's butterflies, so their latency
 // overlaps arithmetic and the exchange (one-wave workgroups have no other
 // waves to hide it); otherwise each stage loads its own.
-// With TWL (PRE false, toff 0), the twiddles of every stage but the last
-// (indices below N/2) come from the LDS copy Wl, the last stage's from W.
-template <class S, int LOGS, int P, class Ar, bool PRE, bool TWL = false>
+// With PRE false and toff 0, the twiddles of the stages lb >= TWLB (indices
+// below 2^(LOGS - TWLB)) come from the LDS copy Wl, the others' from W.
+template <class S, int LOGS, int P, class Ar, bool PRE, int TWLB = 99>
 __device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, const typename Ar::TW* __restrict__ W,
                                            const Ar& ar, int tid, int toff,
                                            const PassTw<S, LOGS, P, true, Ar>* tw = nullptr,
@@ -259,7 +259,7 @@ __device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, 
           ar.fwd(x[i0], x[i1], tw->t[u * PER + (1 << (R - 1 - pb)) - 1 + (c >> (pb + 1))]);
         } else {
           const int ti = base + (((gi >> LO) << (R - 1 - pb)) | (c >> (pb + 1)));
-          if (TWL && lb > 0)
+          if (lb >= TWLB)
             ar.fwd(x[i0], x[i1], Wl[tw_index<S, LO>(ti)]);
           else
             ar.fwd(x[i0], x[i1], W[tw_index<S, LO>(ti)]);
@@ -270,7 +270,7 @@ __device__ __forceinline__ void fwd_passes(typename Ar::T (&x)[S::E], u64* lds, 
   if constexpr (MORE) {
     if (P > 0) __syncthreads();
     exchange<S, LO, R, S::flo(P + 1), S::bits(P + 1), Ar>(x, lds, tid);
-    fwd_passes<S, LOGS, P + 1, Ar, PRE, TWL>(x, lds, W, ar, tid, toff, &nxt, Wl);
+    fwd_passes<S, LOGS, P + 1, Ar, PRE, TWLB>(x, lds, W, ar, tid, toff, &nxt, Wl);
   }
 }
 
@@ -1062,15 +1062,27 @@ template <int LOGN>
 struct HCfg : Sched<LOGN, 0, LOGN, hoist_loge(LOGN)> {
   static constexpr int N = 1 << LOGN;
 };
-// LDS words of the multiply-accumulate kernel: the exchange buffer, plus
-// the twiddle copy (N/2 entries of 16 bytes) where both fit in 160 KiB
+// LDS of the multiply-accumulate kernel (160 KiB per workgroup at most):
+// the NTT exchange buffer, then a copy of the prime's first TWN twiddles
+// (16 bytes each), TWN the largest power of two up to N/2 that fits: the
+// stages lb >= TWLB read their twiddles there.
 template <int LOGN>
-constexpr bool hoist_lds_twiddles() {
-  return (HCfg<LOGN>::lds_words() + (1 << LOGN)) * 8 <= 160 * 1024;
-}
+struct HoistLds {
+  static constexpr int BUDGET = 160 * 1024 / 8;
+  static constexpr int EXW = HCfg<LOGN>::lds_words();
+  static constexpr int twn() {
+    int n = 1 << (LOGN - 1);
+    while (n > 1 && EXW + 2 * n > BUDGET) n >>= 1;
+    return EXW + 2 * n <= BUDGET ? n : 0;
+  }
+  static constexpr int TWN = twn();
+  static constexpr int log2i(int v) { return v <= 1 ? 0 : 1 + log2i(v >> 1); }
+  static constexpr int TWLB = TWN >= 2 ? LOGN - log2i(TWN) : 99;
+  static constexpr int WORDS = EXW + 2 * TWN;
+};
 template <int LOGN>
 constexpr int hoist_lds_words() {
-  return HCfg<LOGN>::lds_words() + (hoist_lds_twiddles<LOGN>() ? (1 << LOGN) : 0);
+  return HoistLds<LOGN>::WORDS;
 }
 
 template <int LOGN, bool DIAG, class Ar>
@@ -1091,12 +1103,12 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
   u64 acc[C::E];
 #pragma unroll
   for (int e = 0; e < C::E; e++) acc[e] = 0;
-  // this workgroup's prime is fixed: its twiddles below N/2 (every stage
-  // but the last) are copied to LDS once and read from there for all items
-  constexpr bool TWL = hoist_lds_twiddles<LOGN>();
-  typename Ar::TW* Wl = reinterpret_cast<typename Ar::TW*>(lds + C::lds_words());
-  if constexpr (TWL) {
-    for (int i = tid; i < N / 2; i += C::T) Wl[i] = W[i];
+  // this workgroup's prime is fixed: its first TWN twiddles are copied to
+  // LDS once and read from there for all items
+  using Lay = HoistLds<LOGN>;
+  typename Ar::TW* Wl = reinterpret_cast<typename Ar::TW*>(lds + Lay::EXW);
+  if constexpr (Lay::TWN > 0) {
+    for (int i = tid; i < Lay::TWN; i += C::T) Wl[i] = W[i];
     __syncthreads();
   }
   for (int r = rb; r < re; r++) {
@@ -1117,7 +1129,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     // every stage's twiddles in registers across items)
     const typename Ar::TW* Wr = W;
     asm volatile("" : "+v"(Wr));
-    fwd_passes<C, LOGN, 0, Ar, false, TWL>(x, lds, Wr, ar, tid, 0, nullptr, Wl);
+    fwd_passes<C, LOGN, 0, Ar, false, Lay::TWLB>(x, lds, Wr, ar, tid, 0, nullptr, Wl);
     // final values through LDS so the epilogue runs in natural order:
     // coalesced accesses and a bounded number of loads in flight
     __syncthreads();
@@ -1128,7 +1140,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
       for (int c = 0; c < (1 << RF); c++) lds[pad((gi << RF) | c)] = ar.fwd_res(x[u * (1 << RF) + c]);
     }
     __syncthreads();
-    const u64* __restrict__ uu = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
+    const u64* __restrict__ uw = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
     const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
     if constexpr (DIAG) {
       // Barrett product with the diagonal: no precomputed companion, so
@@ -1138,7 +1150,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
       for (int e = 0; e < C::E; e++) {
         const int idx = tid + C::T * e;
         const u64 v = lds[pad(idx)];
-        u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+        u64 ks = shoup(submod(uw[idx], v, q), inv, inv_sh, q);
         if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
         acc[e] = addmod(acc[e], mulmod(ks, dg[idx], P), q);
       }
@@ -1148,7 +1160,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
       for (int e = 0; e < C::E; e++) {
         const int idx = tid + C::T * e;
         const u64 v = lds[pad(idx)];
-        u64 ks = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+        u64 ks = shoup(submod(uw[idx], v, q), inv, inv_sh, q);
         if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
         acc[e] = addmod(acc[e], ks, q);
       }

@@ -136,3 +136,30 @@ def test_cnn_bit_exact_and_logits():
     P.ct_equal(gy, oy, "cnn output")
     logits = P.H.he_decode(P.g, P.H.he_decrypt(P.g, gy), 10)
     assert np.abs(logits - cnn_fp64(d)).max() < 1e-3
+
+
+def test_matmul_n16384_decrypts():
+    # the hoisted replication and product at N = 16384 (their kernels use a
+    # different workgroup shape and LDS plan than at N = 8192): decrypted
+    # result against plaintext arithmetic; bit-exact parity of the same
+    # kernels is covered at N = 4096 and 8192
+    from tests.gpu_common import hip
+    H = hip()
+    n_in, n_out = 256, 8
+    half = 8192
+    g = H.he_ctx_create(14, [60, 40, 40, 60], 2.0 ** 40, 17, auto_rescale=True, stream=None)
+    H.he_keygen(g, [])
+    for st in sorted(set(I.replication_steps(n_in, half) + list(range(1, n_in)))):
+        H.he_keygen_galois(g, st, -1)
+    rng = np.random.default_rng(16384)
+    W = rng.normal(0, 0.1, (n_in, n_out))
+    b = rng.normal(0, 0.1, n_out)
+    x = rng.uniform(-1, 1, n_in)
+    say("matmul n16384")
+    gx = H.he_encrypt(g, H.he_encode(g, x, 2.0 ** 40, g.L - 1), 3, False)
+    gy = H.he_enc_matmul(g, gx, W, b)
+    dec = H.he_decode(g, H.he_decrypt(g, gy), half)
+    assert np.abs(dec[:n_out] - (x @ W + b)).max() < 1e-6
+    assert np.abs(dec[n_out:]).max() < 1e-6
+    del gx, gy
+    g.close()
