@@ -423,48 +423,35 @@ PAPER_OPS_MS = {
 def op_sweep(H, I, shapes=(256, 1024, 4096, 8192, 16384), reps=10):
     """Each operation of the appendix tables on encrypted vectors of the
     given lengths at N = 8192 with a 200-bit chain (60, 40, 40, 60) and
-    automatic rescaling; vectors longer than N/2 span several ciphertexts
-    (their key switches batched).  `_plain` operands are encoded inside the
-    timed call, as a plain tensor operand is; polyval evaluates 2X^2 + X; dot
-    is the product followed by a slot sum.  Milliseconds per call, wall clock
-    between synchronisations (host work included)."""
+    automatic rescaling.  A vector is a rank-1 tensor (he_tensor_*): lengths
+    above N/2 span several ciphertexts (products as one batch).  `_plain`
+    operands are encoded inside the timed call, as a plain tensor operand
+    is; polyval evaluates 2X^2 + X; dot is the product followed by the sum
+    over the vector.  Milliseconds per call, wall clock between
+    synchronisations (host work included)."""
     import numpy as np
     g = H.he_ctx_create(13, [60, 40, 40, 60], 2.0 ** 40, 4, auto_rescale=True, stream=None)
     H.he_keygen(g, [1 << t for t in range(12)])
-    half = g.n // 2
     rng = np.random.default_rng(4)
     out = {op: [] for op in PAPER_OPS_MS}
+    top = g.L - 1
     for shape in shapes:
-        n_ct = (shape + half - 1) // half
-        parts = [min(half, shape - i * half) for i in range(n_ct)]
-        xv = [rng.uniform(-1, 1, m) for m in parts]
-        yv = [rng.uniform(-1, 1, m) for m in parts]
-        top = g.L - 1
-        X = [H.he_encrypt(g, H.he_encode(g, v, 2.0 ** 40, top), i, False) for i, v in enumerate(xv)]
-        Y = [H.he_encrypt(g, H.he_encode(g, v, 2.0 ** 40, top), 100 + i, False) for i, v in enumerate(yv)]
+        xv, yv = rng.uniform(-1, 1, shape), rng.uniform(-1, 1, shape)
+        X = H.he_tensor_encrypt(g, xv, 2.0 ** 40, top, 0)
+        Y = H.he_tensor_encrypt(g, yv, 2.0 ** 40, top, 100)
         H.he_sync(g)
-
-        def enc(vs):
-            return [H.he_encode(g, v, 2.0 ** 40, top) for v in vs]
-
-        def dot(prods):
-            acc = prods[0]
-            for p in prods[1:]:
-                acc = H.he_add(g, acc, p)
-            return H.he_sum_slots(g, acc, min(shape, half))
-
         ops = {
-            "negate": lambda: [H.he_negate(g, a) for a in X],
-            "square": lambda: H.he_mul_relin_many(g, X, X),
-            "polyval": lambda: [H.he_polyval(g, a, [0.0, 1.0, 2.0]) for a in X],
-            "add": lambda: [H.he_add(g, a, b) for a, b in zip(X, Y)],
-            "multiply": lambda: H.he_mul_relin_many(g, X, Y),
-            "sub": lambda: [H.he_sub(g, a, b) for a, b in zip(X, Y)],
-            "dot": lambda: dot(H.he_mul_relin_many(g, X, Y)),
-            "add_plain": lambda: [H.he_add_plain(g, a, p) for a, p in zip(X, enc(yv))],
-            "multiply_plain": lambda: [H.he_mul_plain(g, a, p) for a, p in zip(X, enc(yv))],
-            "sub_plain": lambda: [H.he_sub_plain(g, a, p) for a, p in zip(X, enc(yv))],
-            "dot_plain": lambda: dot([H.he_mul_plain(g, a, p) for a, p in zip(X, enc(yv))]),
+            "negate": lambda: H.he_tensor_negate(g, X),
+            "square": lambda: H.he_tensor_square(g, X),
+            "polyval": lambda: H.he_tensor_polyval(g, X, [0.0, 1.0, 2.0]),
+            "add": lambda: H.he_tensor_add(g, X, Y),
+            "multiply": lambda: H.he_tensor_mul(g, X, Y),
+            "sub": lambda: H.he_tensor_sub(g, X, Y),
+            "dot": lambda: H.he_tensor_dot(g, X, Y),
+            "add_plain": lambda: H.he_tensor_add_plain(g, X, yv),
+            "multiply_plain": lambda: H.he_tensor_mul_plain(g, X, yv),
+            "sub_plain": lambda: H.he_tensor_sub_plain(g, X, yv),
+            "dot_plain": lambda: H.he_tensor_dot_plain(g, X, yv),
         }
         for name, fn in ops.items():
             r = fn()
@@ -479,7 +466,7 @@ def op_sweep(H, I, shapes=(256, 1024, 4096, 8192, 16384), reps=10):
         del X, Y
     g.close()
     return {"shapes": list(shapes), "ms": out, "paper_ms_8vcpu": PAPER_OPS_MS,
-            "params": "N=8192, primes (60, 40, 40, 60), scale 2^40, auto rescale"}
+            "params": "N=8192, primes (60, 40, 40, 60), scale 2^40, auto rescale; rank-1 tensors"}
 
 
 def serving_bench(H, I, d, qps_list=(10, 20, 50, 100, 200, 500, 1000, 2000), n_clients=8,

@@ -287,6 +287,54 @@ he_status he_export_secret(he_ctx* ctx, int64_t* s); /* N ternary coeffs */
 he_status he_export_key(he_ctx* ctx, int32_t kind, int32_t step,
                         uint64_t* out, size_t cap, int32_t* max_level);
 
+/* ---- tensors of several ciphertexts (section 2: the CKKSTensor flavour,
+ * which batches one axis into the slots; the appendix operation tables at
+ * vector sizes above N/2) ----
+ * A tensor of shape d_0 x ... x d_{r-1} (1 <= r <= HE_TENSOR_MAX_DIMS) keeps
+ * its last axis in the slots, in chunks of N/2, and indexes ciphertexts by
+ * the other axes: ciphertext i = row * chunks + chunk holds the values
+ * row * d_{r-1} + chunk * N/2 + j, j < N/2, of the row-major value array.
+ * The tensor owns its ciphertexts; every operation returns a new tensor
+ * (he_tensor_free) and applies the one-ciphertext operation above to each
+ * ciphertext (products as batches), so each result ciphertext is
+ * bit-identical to the one-ciphertext call.  Shapes of the operands must
+ * match (HE_EINVAL); level and scale rules are those of the operations. */
+typedef struct he_tensor he_tensor;
+#define HE_TENSOR_MAX_DIMS 8
+/* encode + encrypt values[prod(shape)] (host, row-major) at scale / level;
+ * ciphertext i uses enc_index0 + i */
+he_status he_tensor_encrypt(he_ctx* ctx, const double* values, const int64_t* shape,
+                            int32_t ndim, double scale, int32_t level,
+                            uint32_t enc_index0, int32_t use_secret_key, he_tensor** out);
+/* decrypt + decode into out[prod(shape)] (host, row-major; n = capacity) */
+he_status he_tensor_decrypt(he_ctx* ctx, const he_tensor* t, double* out, size_t n);
+/* shape (HE_TENSOR_MAX_DIMS entries of room), rank and ciphertext count */
+he_status he_tensor_shape(const he_tensor* t, int64_t* shape, int32_t* ndim, size_t* n_ct);
+/* ciphertext i, still owned by the tensor */
+he_status he_tensor_ct(const he_tensor* t, size_t i, const he_ct** out);
+he_status he_tensor_add(he_ctx* ctx, const he_tensor* a, const he_tensor* b, he_tensor** out);
+he_status he_tensor_sub(he_ctx* ctx, const he_tensor* a, const he_tensor* b, he_tensor** out);
+he_status he_tensor_negate(he_ctx* ctx, const he_tensor* a, he_tensor** out);
+/* element-wise product / square: he_mul_relin_many over all ciphertexts */
+he_status he_tensor_mul(he_ctx* ctx, const he_tensor* a, const he_tensor* b, he_tensor** out);
+he_status he_tensor_square(he_ctx* ctx, const he_tensor* a, he_tensor** out);
+/* plain operand v[prod(shape)] (host), each chunk encoded at its
+ * ciphertext's level: at the ciphertext's scale for add/sub, at the
+ * context's scale Delta for mul */
+he_status he_tensor_add_plain(he_ctx* ctx, const he_tensor* a, const double* v, he_tensor** out);
+he_status he_tensor_sub_plain(he_ctx* ctx, const he_tensor* a, const double* v, he_tensor** out);
+he_status he_tensor_mul_plain(he_ctx* ctx, const he_tensor* a, const double* v, he_tensor** out);
+he_status he_tensor_power(he_ctx* ctx, const he_tensor* a, uint32_t k, he_tensor** out);
+he_status he_tensor_polyval(he_ctx* ctx, const he_tensor* a, const double* coeffs,
+                            size_t n_coeffs, he_tensor** out);
+/* sum over the last axis: each row's chunks added in chunk order, then
+ * he_sum_slots over min(d_{r-1}, N/2) slots; result shape [..., 1] */
+he_status he_tensor_sum(he_ctx* ctx, const he_tensor* a, he_tensor** out);
+/* he_tensor_sum(he_tensor_mul(a, b)) and he_tensor_sum(he_tensor_mul_plain(a, w)) */
+he_status he_tensor_dot(he_ctx* ctx, const he_tensor* a, const he_tensor* b, he_tensor** out);
+he_status he_tensor_dot_plain(he_ctx* ctx, const he_tensor* a, const double* w, he_tensor** out);
+void he_tensor_free(he_tensor* t);
+
 /* ---- housekeeping ---- */
 void he_ct_free(he_ct* ct);
 void he_pt_free(he_pt* pt);

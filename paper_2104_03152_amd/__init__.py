@@ -17,6 +17,7 @@ LIBPATH = os.path.join(HERE, "libckks_hip.so")
 HE_OK, HE_EINVAL, HE_ERANGE, HE_ELEVEL, HE_ESCALE, HE_ENOKEY, HE_EOOM, HE_EHIP = (
     0, -1, -2, -3, -4, -5, -6, -7)
 HE_MAX_PRIMES = 32
+HE_TENSOR_MAX_DIMS = 8
 
 
 class HeError(RuntimeError):
@@ -91,6 +92,25 @@ _SIGS = {
     "he_ct_free": (None, [_vp]),
     "he_pt_free": (None, [_vp]),
     "he_plan_free": (None, [_vp]),
+    "he_tensor_encrypt": (C.c_int32, [_vp, _dp, _i64p, C.c_int32, C.c_double, C.c_int32, C.c_uint32,
+                                      C.c_int32, _pvp]),
+    "he_tensor_decrypt": (C.c_int32, [_vp, _vp, _dp, C.c_size_t]),
+    "he_tensor_shape": (C.c_int32, [_vp, _i64p, _i32p, _P(C.c_size_t)]),
+    "he_tensor_ct": (C.c_int32, [_vp, C.c_size_t, _pvp]),
+    "he_tensor_add": (C.c_int32, [_vp, _vp, _vp, _pvp]),
+    "he_tensor_sub": (C.c_int32, [_vp, _vp, _vp, _pvp]),
+    "he_tensor_mul": (C.c_int32, [_vp, _vp, _vp, _pvp]),
+    "he_tensor_dot": (C.c_int32, [_vp, _vp, _vp, _pvp]),
+    "he_tensor_negate": (C.c_int32, [_vp, _vp, _pvp]),
+    "he_tensor_square": (C.c_int32, [_vp, _vp, _pvp]),
+    "he_tensor_sum": (C.c_int32, [_vp, _vp, _pvp]),
+    "he_tensor_add_plain": (C.c_int32, [_vp, _vp, _dp, _pvp]),
+    "he_tensor_sub_plain": (C.c_int32, [_vp, _vp, _dp, _pvp]),
+    "he_tensor_mul_plain": (C.c_int32, [_vp, _vp, _dp, _pvp]),
+    "he_tensor_dot_plain": (C.c_int32, [_vp, _vp, _dp, _pvp]),
+    "he_tensor_power": (C.c_int32, [_vp, _vp, C.c_uint32, _pvp]),
+    "he_tensor_polyval": (C.c_int32, [_vp, _vp, _dp, C.c_size_t, _pvp]),
+    "he_tensor_free": (None, [_vp]),
     "he_sync": (C.c_int32, [_vp]),
     "he_last_error": (C.c_char_p, []),
     "he_ct_bytes": (C.c_size_t, [_vp]),
@@ -172,6 +192,41 @@ class Pt(_Handle):
 
 class Plan(_Handle):
     _free = "he_plan_free"
+
+
+class _BorrowedCt(Ct):
+    """A ciphertext owned by a tensor (kept alive through `owner`)."""
+
+    def __init__(self, ctx, ptr, owner):
+        super().__init__(ctx, ptr)
+        self.owner = owner
+
+    def free(self):
+        self.ptr = None
+
+
+class Tensor(_Handle):
+    """Tensor of several ciphertexts, last axis in the slots (he_tensor_*)."""
+    _free = "he_tensor_free"
+
+    def _info(self):
+        shape = (C.c_int64 * HE_TENSOR_MAX_DIMS)()
+        nd, nct = C.c_int32(), C.c_size_t()
+        _chk(lib().he_tensor_shape(self.ptr, shape, C.byref(nd), C.byref(nct)), "he_tensor_shape")
+        return tuple(int(shape[i]) for i in range(nd.value)), nct.value
+
+    @property
+    def shape(self):
+        return self._info()[0]
+
+    @property
+    def n_ct(self):
+        return self._info()[1]
+
+    def ct(self, i):
+        out = C.c_void_p()
+        _chk(lib().he_tensor_ct(self.ptr, int(i), C.byref(out)), "he_tensor_ct")
+        return _BorrowedCt(self.ctx, out.value, self)
 
 
 class Ctx:
@@ -496,3 +551,69 @@ def he_profile_read(ctx, family):
     _chk(lib().he_profile_read(ctx.ptr, family.encode(), C.byref(n), C.byref(ms), C.byref(units),
                                C.byref(by)), "he_profile_read")
     return n.value, ms.value, units.value, by.value
+
+
+# ---- tensors of several ciphertexts (he_tensor_*) ----
+
+def he_tensor_encrypt(ctx, values, scale, level, enc_index0=0, use_sk=False):
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    if v.ndim == 0:
+        v = v.reshape(1)
+    shape = np.asarray(v.shape, dtype=np.int64)
+    return _new(Tensor, ctx, lib().he_tensor_encrypt, "he_tensor_encrypt", ctx.ptr, _ptr(v, C.c_double),
+                _ptr(shape, C.c_int64), v.ndim, float(scale), int(level), int(enc_index0),
+                1 if use_sk else 0)
+
+
+def he_tensor_decrypt(ctx, t):
+    shape = t.shape
+    out = np.empty(int(np.prod(shape)), dtype=np.float64)
+    _chk(lib().he_tensor_decrypt(ctx.ptr, t.ptr, _ptr(out, C.c_double), out.size), "he_tensor_decrypt")
+    return out.reshape(shape)
+
+
+def _tensor_binary(name):
+    def f(ctx, a, b):
+        return _new(Tensor, ctx, getattr(lib(), name), name, ctx.ptr, a.ptr, b.ptr)
+    f.__name__ = name
+    return f
+
+
+def _tensor_unary(name):
+    def f(ctx, a):
+        return _new(Tensor, ctx, getattr(lib(), name), name, ctx.ptr, a.ptr)
+    f.__name__ = name
+    return f
+
+
+def _tensor_plain(name):
+    def f(ctx, a, values):
+        v = np.ascontiguousarray(values, dtype=np.float64).reshape(-1)
+        if v.size != int(np.prod(a.shape)):
+            raise ValueError("plain operand has %d values, tensor %d" % (v.size, int(np.prod(a.shape))))
+        return _new(Tensor, ctx, getattr(lib(), name), name, ctx.ptr, a.ptr, _ptr(v, C.c_double))
+    f.__name__ = name
+    return f
+
+
+he_tensor_add = _tensor_binary("he_tensor_add")
+he_tensor_sub = _tensor_binary("he_tensor_sub")
+he_tensor_mul = _tensor_binary("he_tensor_mul")
+he_tensor_dot = _tensor_binary("he_tensor_dot")
+he_tensor_negate = _tensor_unary("he_tensor_negate")
+he_tensor_square = _tensor_unary("he_tensor_square")
+he_tensor_sum = _tensor_unary("he_tensor_sum")
+he_tensor_add_plain = _tensor_plain("he_tensor_add_plain")
+he_tensor_sub_plain = _tensor_plain("he_tensor_sub_plain")
+he_tensor_mul_plain = _tensor_plain("he_tensor_mul_plain")
+he_tensor_dot_plain = _tensor_plain("he_tensor_dot_plain")
+
+
+def he_tensor_power(ctx, a, k):
+    return _new(Tensor, ctx, lib().he_tensor_power, "he_tensor_power", ctx.ptr, a.ptr, int(k))
+
+
+def he_tensor_polyval(ctx, a, coeffs):
+    cf = np.ascontiguousarray(coeffs, dtype=np.float64)
+    return _new(Tensor, ctx, lib().he_tensor_polyval, "he_tensor_polyval", ctx.ptr, a.ptr,
+                _ptr(cf, C.c_double), cf.size)

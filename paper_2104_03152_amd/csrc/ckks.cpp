@@ -2616,4 +2616,290 @@ he_status he_profile_read(he_ctx* c, const char* fam, uint64_t* launches, double
   return HE_OK;
 }
 
+
+// ---------------------------------------------------------------- tensors
+// CKKSTensor with a batched axis (section 2, the tensor flavours): the last
+// axis of a shape d_0 x ... x d_{r-1} lies in the slots, in chunks of N/2;
+// the other axes index ciphertexts.  Ciphertext (row, chunk) holds elements
+// row * d_{r-1} + chunk * N/2 + j, j < N/2, of the row-major value array.
+struct he_tensor {
+  he_ctx* ctx = nullptr;
+  std::vector<int64_t> shape;
+  size_t rows = 0, chunks = 0;
+  int64_t last = 0;
+  std::vector<he_ct*> cts;  // [rows][chunks], owned
+};
+
+static void tensor_release(he_tensor* t) {
+  for (he_ct* x : t->cts) he_ct_free(x);
+  delete t;
+}
+
+static he_status tensor_alloc(he_ctx* c, const std::vector<int64_t>& shape, he_tensor** out) {
+  if (shape.empty() || shape.size() > HE_TENSOR_MAX_DIMS) return fail(HE_EINVAL, "tensor rank %zu", shape.size());
+  size_t rows = 1;
+  for (size_t i = 0; i + 1 < shape.size(); i++) {
+    if (shape[i] <= 0) return fail(HE_EINVAL, "tensor axis %zu has size %lld", i, (long long)shape[i]);
+    rows *= (size_t)shape[i];
+  }
+  const int64_t last = shape.back();
+  if (last <= 0) return fail(HE_EINVAL, "tensor last axis has size %lld", (long long)last);
+  const int64_t half = c->n / 2;
+  he_tensor* t = new he_tensor();
+  t->ctx = c;
+  t->shape = shape;
+  t->rows = rows;
+  t->last = last;
+  t->chunks = (size_t)((last + half - 1) / half);
+  t->cts.assign(rows * t->chunks, nullptr);
+  *out = t;
+  return HE_OK;
+}
+
+// values of chunk (row, j): offset into the row-major array and count
+static void chunk_span(const he_tensor* t, size_t row, size_t j, size_t* off, size_t* cnt) {
+  const int64_t half = t->ctx->n / 2;
+  *off = row * (size_t)t->last + j * (size_t)half;
+  *cnt = (size_t)std::min<int64_t>(half, t->last - (int64_t)j * half);
+}
+
+static he_status tensor_check(he_ctx* c, const he_tensor* a) {
+  if (!c || !a) return fail(HE_EINVAL, "NULL argument");
+  if (a->ctx != c) return fail(HE_EINVAL, "tensor of another context");
+  return HE_OK;
+}
+
+static he_status tensor_same_shape(const he_tensor* a, const he_tensor* b) {
+  if (a->shape != b->shape) return fail(HE_EINVAL, "tensor shapes differ");
+  return HE_OK;
+}
+
+he_status he_tensor_encrypt(he_ctx* c, const double* values, const int64_t* shape, int32_t ndim, double scale,
+                            int32_t level, uint32_t enc_index0, int32_t use_secret_key, he_tensor** out) {
+  if (!c || !values || !shape || !out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (ndim < 1) return fail(HE_EINVAL, "tensor rank %d", ndim);
+  he_tensor* t = nullptr;
+  TRY(tensor_alloc(c, std::vector<int64_t>(shape, shape + ndim), &t));
+  for (size_t r = 0; r < t->rows; r++)
+    for (size_t j = 0; j < t->chunks; j++) {
+      size_t off, cnt;
+      chunk_span(t, r, j, &off, &cnt);
+      he_pt* pt = nullptr;
+      he_status s = he_encode(c, values + off, cnt, scale, level, &pt);
+      const size_t i = r * t->chunks + j;
+      if (s == HE_OK) s = he_encrypt(c, pt, enc_index0 + (uint32_t)i, use_secret_key, &t->cts[i]);
+      he_pt_free(pt);
+      if (s != HE_OK) {
+        tensor_release(t);
+        return s;
+      }
+    }
+  *out = t;
+  return HE_OK;
+}
+
+he_status he_tensor_decrypt(he_ctx* c, const he_tensor* t, double* out, size_t n) {
+  TRY(tensor_check(c, t));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  if (n < t->rows * (size_t)t->last) return fail(HE_EINVAL, "output holds %zu of %zu values", n,
+                                                 t->rows * (size_t)t->last);
+  for (size_t r = 0; r < t->rows; r++)
+    for (size_t j = 0; j < t->chunks; j++) {
+      size_t off, cnt;
+      chunk_span(t, r, j, &off, &cnt);
+      he_pt* pt = nullptr;
+      TRY(he_decrypt(c, t->cts[r * t->chunks + j], &pt));
+      he_status s = he_decode(c, pt, out + off, cnt);
+      he_pt_free(pt);
+      if (s != HE_OK) return s;
+    }
+  return HE_OK;
+}
+
+he_status he_tensor_shape(const he_tensor* t, int64_t* shape, int32_t* ndim, size_t* n_ct) {
+  if (!t) return fail(HE_EINVAL, "NULL argument");
+  if (ndim) *ndim = (int32_t)t->shape.size();
+  if (shape)
+    for (size_t i = 0; i < t->shape.size(); i++) shape[i] = t->shape[i];
+  if (n_ct) *n_ct = t->cts.size();
+  return HE_OK;
+}
+
+he_status he_tensor_ct(const he_tensor* t, size_t i, const he_ct** out) {
+  if (!t || !out) return fail(HE_EINVAL, "NULL argument");
+  if (i >= t->cts.size()) return fail(HE_EINVAL, "ciphertext %zu of %zu", i, t->cts.size());
+  *out = t->cts[i];
+  return HE_OK;
+}
+
+void he_tensor_free(he_tensor* t) {
+  if (t) tensor_release(t);
+}
+
+// result tensor of a's shape, ciphertext i = f(i)
+extern "C++" {
+template <class F>
+static he_status tensor_map(he_ctx* c, const he_tensor* a, he_tensor** out, F f) {
+  *out = nullptr;
+  he_tensor* t = nullptr;
+  TRY(tensor_alloc(c, a->shape, &t));
+  for (size_t i = 0; i < t->cts.size(); i++) {
+    he_status s = f(i, &t->cts[i]);
+    if (s != HE_OK) {
+      tensor_release(t);
+      return s;
+    }
+  }
+  *out = t;
+  return HE_OK;
+}
+}  // extern "C++"
+
+he_status he_tensor_add(he_ctx* c, const he_tensor* a, const he_tensor* b, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  TRY(tensor_check(c, b));
+  TRY(tensor_same_shape(a, b));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_map(c, a, out, [&](size_t i, he_ct** o) { return he_add(c, a->cts[i], b->cts[i], o); });
+}
+
+he_status he_tensor_sub(he_ctx* c, const he_tensor* a, const he_tensor* b, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  TRY(tensor_check(c, b));
+  TRY(tensor_same_shape(a, b));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_map(c, a, out, [&](size_t i, he_ct** o) { return he_sub(c, a->cts[i], b->cts[i], o); });
+}
+
+he_status he_tensor_negate(he_ctx* c, const he_tensor* a, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_map(c, a, out, [&](size_t i, he_ct** o) { return he_negate(c, a->cts[i], o); });
+}
+
+// products of all ciphertext pairs as batches (shared key reads)
+static he_status tensor_products(he_ctx* c, const he_tensor* a, const he_tensor* b, he_tensor** out) {
+  *out = nullptr;
+  he_tensor* t = nullptr;
+  TRY(tensor_alloc(c, a->shape, &t));
+  he_status s = he_mul_relin_many(c, a->cts.data(), b->cts.data(), a->cts.size(), t->cts.data());
+  if (s != HE_OK) {
+    tensor_release(t);
+    return s;
+  }
+  *out = t;
+  return HE_OK;
+}
+
+he_status he_tensor_mul(he_ctx* c, const he_tensor* a, const he_tensor* b, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  TRY(tensor_check(c, b));
+  TRY(tensor_same_shape(a, b));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_products(c, a, b, out);
+}
+
+he_status he_tensor_square(he_ctx* c, const he_tensor* a, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_products(c, a, a, out);
+}
+
+// plain operand of a's shape, chunk i encoded at ciphertext i's level, at
+// the ciphertext's scale (sums) or at the context's (products)
+enum PlainOp { PLAIN_ADD, PLAIN_SUB, PLAIN_MUL };
+static he_status tensor_plain(he_ctx* c, const he_tensor* a, const double* v, PlainOp op, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  if (!v || !out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_map(c, a, out, [&](size_t i, he_ct** o) {
+    size_t off, cnt;
+    chunk_span(a, i / a->chunks, i % a->chunks, &off, &cnt);
+    const he_ct* x = a->cts[i];
+    he_pt* pt = nullptr;
+    TRY(he_encode(c, v + off, cnt, op == PLAIN_MUL ? c->scale : x->scale, x->level, &pt));
+    he_status s = op == PLAIN_ADD ? he_add_plain(c, x, pt, o)
+                  : op == PLAIN_SUB ? he_sub_plain(c, x, pt, o)
+                                    : he_mul_plain(c, x, pt, o);
+    he_pt_free(pt);
+    return s;
+  });
+}
+
+he_status he_tensor_add_plain(he_ctx* c, const he_tensor* a, const double* v, he_tensor** out) {
+  return tensor_plain(c, a, v, PLAIN_ADD, out);
+}
+he_status he_tensor_sub_plain(he_ctx* c, const he_tensor* a, const double* v, he_tensor** out) {
+  return tensor_plain(c, a, v, PLAIN_SUB, out);
+}
+he_status he_tensor_mul_plain(he_ctx* c, const he_tensor* a, const double* v, he_tensor** out) {
+  return tensor_plain(c, a, v, PLAIN_MUL, out);
+}
+
+he_status he_tensor_power(he_ctx* c, const he_tensor* a, uint32_t k, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_map(c, a, out, [&](size_t i, he_ct** o) { return he_power(c, a->cts[i], k, o); });
+}
+
+he_status he_tensor_polyval(he_ctx* c, const he_tensor* a, const double* coeffs, size_t n_coeffs,
+                            he_tensor** out) {
+  TRY(tensor_check(c, a));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  return tensor_map(c, a, out,
+                    [&](size_t i, he_ct** o) { return he_polyval(c, a->cts[i], coeffs, n_coeffs, o); });
+}
+
+// sum over the batched (last) axis: each row's chunks added in order, then
+// the rotate-and-sum of its slots; the result has last axis 1 (slot 0)
+he_status he_tensor_sum(he_ctx* c, const he_tensor* a, he_tensor** out) {
+  TRY(tensor_check(c, a));
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  *out = nullptr;
+  std::vector<int64_t> shape = a->shape;
+  shape.back() = 1;
+  he_tensor* t = nullptr;
+  TRY(tensor_alloc(c, shape, &t));
+  const uint32_t width = (uint32_t)std::min<int64_t>(a->last, c->n / 2);
+  for (size_t r = 0; r < a->rows; r++) {
+    CtGuard acc;
+    he_status s = HE_OK;
+    const he_ct* cur = a->cts[r * a->chunks];
+    for (size_t j = 1; j < a->chunks && s == HE_OK; j++) {
+      he_ct* nxt = nullptr;
+      s = he_add(c, cur, a->cts[r * a->chunks + j], &nxt);
+      if (s == HE_OK) {
+        he_ct_free(acc.p);
+        acc.p = nxt;
+        cur = nxt;
+      }
+    }
+    if (s == HE_OK) s = he_sum_slots(c, cur, width, &t->cts[r]);
+    if (s != HE_OK) {
+      tensor_release(t);
+      return s;
+    }
+  }
+  *out = t;
+  return HE_OK;
+}
+
+he_status he_tensor_dot(he_ctx* c, const he_tensor* a, const he_tensor* b, he_tensor** out) {
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  he_tensor* p = nullptr;
+  TRY(he_tensor_mul(c, a, b, &p));
+  he_status s = he_tensor_sum(c, p, out);
+  tensor_release(p);
+  return s;
+}
+
+he_status he_tensor_dot_plain(he_ctx* c, const he_tensor* a, const double* w, he_tensor** out) {
+  if (!out) return fail(HE_EINVAL, "NULL argument");
+  he_tensor* p = nullptr;
+  TRY(he_tensor_mul_plain(c, a, w, &p));
+  he_status s = he_tensor_sum(c, p, out);
+  tensor_release(p);
+  return s;
+}
+
 }  // extern "C"
