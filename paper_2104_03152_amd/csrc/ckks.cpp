@@ -461,7 +461,7 @@ static bool ks_fusable(const he_ctx* c, int B, int Lp) {
 }
 
 struct KsBufs {
-  DBuf t1, t2, ext, t3, t4;
+  DBuf t1, t2, ext, t3, t4, t5;
 };
 
 // fills K for B items at level l; allocates the intermediates
@@ -474,6 +474,7 @@ static he_status ks_prepare(he_ctx* c, int B, const u64* d, long long ds, int l,
   if (moddown) {
     TRY(dalloc(c, bufs.t3, (size_t)2 * B * n));
     TRY(dalloc(c, bufs.t4, (size_t)2 * B * Lp * n));
+    TRY(dalloc(c, bufs.t5, (size_t)2 * B * Lp * n));
   }
   K = KsJob{};
   K.B = B;
@@ -492,6 +493,7 @@ static he_status ks_prepare(he_ctx* c, int B, const u64* d, long long ds, int l,
   K.ext = bufs.ext.p;
   K.t3 = bufs.t3.p;
   K.t4 = bufs.t4.p;
+  K.t5 = bufs.t5.p;
   const size_t np = c->q.size();
   K.h_src = (c->q[c->L] - 1) / 2;
   for (int t = 0; t < Lp; t++) {

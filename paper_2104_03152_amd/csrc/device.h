@@ -105,6 +105,7 @@ struct KsJob {
   u64* ext;                       // [B][Lp][nm][N]; slots [b][j][j] unused
   u64* t3;                        // [2B][N]
   u64* t4;                        // [2B*Lp][N]
+  u64* t5;                        // [2B*Lp][N]: data-limb inner products (ModDown)
   u64* out;                       // poly a = 2b + k at out + a*oa: [Lp][N]
   long long oa;
   const u64* add;                 // addend poly a at add + a*aa (every a, or even a only)
@@ -115,8 +116,10 @@ struct KsJob {
   u64 h_src;                      // (p - 1) / 2
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];  // per data prime t: h mod q_t, p^-1 mod q_t
 };
-// ModUp columns (t1 -> t2), ModDown inner + blocks (ext -> t3), ModDown
-// columns (t3 -> t4), ModDown blocks + epilogue (t4 -> out).  The column
+// ModUp columns (t1 -> t2), ModDown inner + blocks (ext -> t3, and the
+// data-limb inner products ext -> t5 by extra workgroups of the same
+// launch), ModDown columns (t3 -> t4), ModDown blocks + epilogue (t4, t5 ->
+// out).  The column
 // kernels also serve a rescale: `special` is then the dropped limb's prime,
 // t3 its inverse block phase, and the block phase runs as a plain NTT job.
 hipError_t launch_ks_modup_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,

@@ -958,9 +958,30 @@ template <int LOGN>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ks_special_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = 1 << LOGN;
-  __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
-  const int a = blockIdx.x / Split<LOGN>::WB;
-  const int sub = blockIdx.x - a * Split<LOGN>::WB;
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  __shared__ u64 lds[S::lds_words()];
+  const int n_special = 2 * J.B * Sp::WB;
+  if ((int)blockIdx.x >= n_special) {
+    // the data-limb inner products of poly a = 2b + k, limb t, on one
+    // block of 2^LOGMB words: no transform, so they run beside the special
+    // limb's workgroups instead of in the ModDown blocks kernel
+    const int w = (blockIdx.x - n_special) / Sp::WB;
+    const int sub = blockIdx.x - n_special - w * Sp::WB;
+    const int a = w / J.Lp, t = w - a * J.Lp;
+    const int toff = sub << Sp::LOGMB;
+    int idx[S::E];
+    u64 v[S::E];
+#pragma unroll
+    for (int e = 0; e < S::E; e++) idx[e] = toff + threadIdx.x + S::T * e;
+    ks_inner<S::E>(J, primes[t], LOGN, a >> 1, a & 1, t, t, idx, true, v);
+    u64* __restrict__ dst = J.t5 + ((size_t)w << LOGN);
+#pragma unroll
+    for (int e = 0; e < S::E; e++) dst[idx[e]] = v[e];
+    return;
+  }
+  const int a = blockIdx.x / Sp::WB;
+  const int sub = blockIdx.x - a * Sp::WB;
   const PrimeDev P = primes[J.special];
   if (P.use_fp)
     special_blocks_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)J.special * N, P, a,
@@ -996,16 +1017,15 @@ __device__ __forceinline__ void moddown_blocks_body(const KsJob& J, const typena
       for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = Ar::unbits(tin[gidx(gi, c, LO, R)]);
     }
   }
-  // the data-limb inner products at this thread's output indices, computed
-  // before the transform so that their loads overlap it
+  // the data-limb inner products at this thread's output indices (computed
+  // by the special-limb launch), loaded before the transform
   constexpr int RL = S::bits(S::NP - 1), GL = E >> RL;
-  int oidx[E];
   u64 uu[E];
+  const u64* __restrict__ tu = J.t5 + ((size_t)w << LOGN);
 #pragma unroll
   for (int u = 0; u < GL; u++)
 #pragma unroll
-    for (int c = 0; c < (1 << RL); c++) oidx[u * (1 << RL) + c] = toff + (((tid + S::T * u) << RL) | c);
-  ks_inner<E>(J, P, LOGN, b, k, t, t, oidx, true, uu);
+    for (int c = 0; c < (1 << RL); c++) uu[u * (1 << RL) + c] = tu[toff + (((tid + S::T * u) << RL) | c)];
   fwd_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
   {
     constexpr int R = S::bits(S::NP - 1), G = E >> R;
@@ -1346,8 +1366,9 @@ hipError_t ks_launch(int which, const KsJob& J, const PrimeDev* primes, const Nt
                          tabs);
       break;
     case 1:
-      hipLaunchKernelGGL((k_ks_special_blocks<LOGN>), dim3(2 * B * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes,
-                         tabs);
+      // the special limb's blocks, then the data limbs' inner products
+      hipLaunchKernelGGL((k_ks_special_blocks<LOGN>), dim3(2 * B * (1 + Lp) * Sp::WB), dim3(Sp::SB::T), 0, st, J,
+                         primes, tabs);
       break;
     case 2:
       hipLaunchKernelGGL((k_ks_moddown_cols<LOGN, 0>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
