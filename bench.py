@@ -206,7 +206,7 @@ def main():
 
     log("kernel profile (HIP events on the library stream)")
     fams = ["ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "keyswitch_inner", "hoisted_inner",
-            "hoisted_moddown", "hoisted_replication", "pointwise", "sample"]
+            "hoisted_cols", "hoisted_moddown", "hoisted_replication", "pointwise", "sample"]
     H.he_profile_enable(g, True)
     prof_steps = 5
     for _ in range(prof_steps):
@@ -300,8 +300,10 @@ def main():
 # about 27).  The inner products are bound by HBM (their key reads).
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 BUTTERFLY_INSTR = 11
-SINGLE_KERNEL_FAMILIES = ("hoisted_moddown", "hoisted_replication", "hoisted_inner", "keyswitch_inner")
-NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "hoisted_moddown", "hoisted_replication")
+SINGLE_KERNEL_FAMILIES = ("hoisted_cols", "hoisted_moddown", "hoisted_replication", "hoisted_inner",
+                          "keyswitch_inner")
+NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "hoisted_cols", "hoisted_moddown",
+                "hoisted_replication")
 
 
 def roofline_entry(fam, p, n):

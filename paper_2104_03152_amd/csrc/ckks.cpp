@@ -184,6 +184,7 @@ struct he_ctx {
   NttTables tabs{};
   bool capturing = false;  // a graph capture of st is open
   int fuse_max = 256;      // fused key switch when B*Lp^2 <= this, fused rescale when 2*n_ct*l <= this
+  int hoist_split_wgs = 2048;  // two-phase hoisted multiply-accumulate, about this many workgroups (0: one kernel)
   bool have_keys = false;
   u64* d_s = nullptr;   // [L+1][N]
   u64* d_pk = nullptr;  // [2][L][N]
@@ -1063,6 +1064,7 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
   int split_jobs = 256;
   if (const char* env = getenv("HE_NTT_SPLIT_JOBS")) split_jobs = atoi(env);
   if (const char* env = getenv("HE_FUSE_MAX")) c->fuse_max = atoi(env);
+  if (const char* env = getenv("HE_HOIST_SPLIT_WGS")) c->hoist_split_wgs = atoi(env);
   u64* tmp = nullptr;
   if (split_jobs > 0) {
     tmp = (u64*)c->pool.get((size_t)split_jobs * n * sizeof(u64));
@@ -2126,12 +2128,19 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted intt: %s", hipGetErrorString(e));
     }
-    // chunks of rotations so that chunks x 2 x Lp workgroups fill the chip
-    const int target = 512;
-    n_chunks = std::max(1, std::min(R, (target + 2 * Lp - 1) / (2 * Lp)));
+    // chunks of rotations so that the multiply-accumulate's workgroups fill
+    // the chip: chunks x 2 x Lp of the one-kernel form (one per compute
+    // unit), chunks x 2 x Lp x blocks of the two-phase form (several per
+    // compute unit)
+    const bool split = c->hoist_split_wgs > 0;
+    const int per_chunk = 2 * Lp * (split ? hoist_split_blocks(c->log_n) : 1);
+    const int target = split ? c->hoist_split_wgs : 512;
+    n_chunks = std::max(1, std::min(R, (target + per_chunk - 1) / per_chunk));
     const int chunk = (R + n_chunks - 1) / n_chunks;
     n_chunks = (R + chunk - 1) / chunk;
     TRY(dalloc(c, partial, (size_t)n_chunks * 2 * Lp * n));
+    DBuf mid;
+    if (split) TRY(dalloc(c, mid, (size_t)R * 2 * Lp * n));
     HoistMac M{};
     M.ucoef = ucoef.p;
     M.u = u.p;
@@ -2139,6 +2148,7 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     M.diags = diags;
     M.items = items;
     M.partial = partial.p;
+    M.mid = mid.p;
     M.R = R;
     M.n_dig = Lp;
     M.nm = nm;
@@ -2152,10 +2162,22 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       M.inv[t] = c->rd_inv[c->L * np + t];
       M.inv_sh[t] = c->rd_inv_sh[c->L * np + t];
     }
-    // per (item, poly, limb): special limb, u limb and diagonal read, and the
+    // work units: limb-NTT equivalents of butterflies (the two-phase form's
+    // column phase runs the first log N - K stages, its block phase the
+    // last K = ceil(log N / 2))
+    const double nt = 2.0 * R * Lp;
+    const int kb = (c->log_n + 1) / 2;
+    if (split) {
+      // special limb of every (item, poly) read, every (item, poly, limb) written
+      Prof pa(c, "hoisted_cols", nt * (c->log_n - kb) / c->log_n, 8.0 * n * (2.0 * R + nt));
+      hipError_t e = launch_hoisted_cols(c->log_n, M, c->d_primes, c->tabs, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "hoisted columns: %s", hipGetErrorString(e));
+    }
+    // per (item, poly, limb): the special limb's transform (its column-phase
+    // output in the two-phase form), u limb and diagonal read, and the
     // partial sums written once per chunk
-    Prof pr(c, diags ? "hoisted_moddown" : "hoisted_replication", 2.0 * R * Lp,
-            8.0 * n * ((diags ? 3.0 : 2.0) * 2 * R * Lp + 2.0 * n_chunks * Lp));
+    Prof pr(c, diags ? "hoisted_moddown" : "hoisted_replication", split ? nt * kb / c->log_n : nt,
+            8.0 * n * ((diags ? 3.0 : 2.0) * nt + 2.0 * n_chunks * Lp));
     hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "hoisted moddown: %s", hipGetErrorString(e));
   }

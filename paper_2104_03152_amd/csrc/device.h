@@ -263,7 +263,10 @@ hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev
 // into partial[c][k][t] (without the diagonal factor when diags is NULL).
 // The two workgroups (k = 0, 1) of one (chunk, t) run on the same XCD, one
 // after the other in dispatch order, so the second reads the diagonals
-// from that XCD's L2.
+// from that XCD's L2.  The two-phase form splits each transform as the
+// two-phase NTTs do: a column kernel over every (item, poly, modulus) into
+// mid, then a block kernel whose workgroups (chunk, poly, modulus, block)
+// finish their block's stages item after item and accumulate.
 struct HoistMac {
   const u64* ucoef;  // [R][2][N] special-prime limb of u, coefficient form
   const u64* u;      // [R][2][nm][N]
@@ -271,13 +274,22 @@ struct HoistMac {
   const u64* diags;  // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
   const HoistItem* items;
   u64* partial;      // [n_chunks][2][n_dig][N]
+  // two-phase form when non-NULL: [R][2][n_dig][N] column-phase output of
+  // every (item, poly, modulus) forward transform
+  u64* mid;
   int R, n_dig, nm, chunk, special_prime;
-  int n_units;       // n_chunks * n_dig
+  int n_units;       // n_chunks * n_dig (one-kernel form); set by the launcher in the two-phase form
   u64 h_src;
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];
 };
 hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const PrimeDev* primes,
                                       const NttTables& tabs, hipStream_t st);
+// the two-phase form: launch_hoisted_cols runs the column phase, then
+// launch_hoisted_moddown_mac the block phase with the multiply-accumulate
+hipError_t launch_hoisted_cols(int log_n, const HoistMac& job, const PrimeDev* primes,
+                               const NttTables& tabs, hipStream_t st);
+// workgroups per (chunk, poly, modulus) of the two-phase form's block phase
+int hoist_split_blocks(int log_n);
 // out[k][t] = x[k][t] * diag0[t] + sum_c partial[c][k][t] (x[k][t] itself
 // when diag0 is NULL)
 hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const u64* x,

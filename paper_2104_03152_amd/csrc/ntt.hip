@@ -1002,7 +1002,7 @@ __device__ __forceinline__ void moddown_blocks_body(const KsJob& J, const typena
   const Ar ar(P);
   const int tid = threadIdx.x;
   const int toff = sub << Sp::LOGMB;
-  const int b = a >> 1, k = a & 1;
+  const int b = a >> 1;
   const u64 q = P.q;
   PassTw<S, LOGN, 0, true, Ar> tw0;
   tw0.load(W, tid, toff);
@@ -1215,6 +1215,123 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTabl
                                   chunk, k, t, lds);
 }
 
+// ---------------- hoisted multiply-accumulate, two-phase form ----------------
+// Column phase: the lifted special-prime limb of item a / 2, poly a % 2, in
+// modulus b, through the first (row) stages into mid (the forward column
+// kernel with the divide-and-round lift; a kernel of its own so that
+// profiles name it).
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_hoist_cols(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Split<LOGN>::SA::lds_words()];
+  const int w = blockIdx.x / Split<LOGN>::WA;
+  const int sub = blockIdx.x - w * Split<LOGN>::WA;
+  int a, b;
+  decode_job(J, w, a, b);
+  const int dp = J.dst_prime[b];
+  const PrimeDev P = primes[dp];
+  if (P.use_fp)
+    fwd_a_body<LOGN, PRO_ROUNDDIV_LIFT, FpAr>(J, primes, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)dp * N,
+                                              P, w, a, b, sub, J.mid, lds);
+  else
+    fwd_a_body<LOGN, PRO_ROUNDDIV_LIFT, IntAr>(J, primes, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)dp * N,
+                                               P, w, a, b, sub, J.mid, lds);
+}
+
+// Block phase: workgroup (chunk, k, t, sub) finishes block sub of every
+// item's transform in modulus t, poly k, and keeps the running sums of its
+// E words in registers.
+template <int LOGN, bool DIAG, class Ar>
+__device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename Ar::TW* __restrict__ W,
+                                             const PrimeDev& P, int chunk, int k, int t, int sub, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  constexpr int N = 1 << LOGN;
+  constexpr int R0 = S::bits(0), LO0 = S::flo(0), G0 = S::E >> R0;
+  constexpr int RF = S::bits(S::NP - 1), GF = S::E >> RF;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const u64 q = P.q;
+  const u64 inv = J.inv[t], inv_sh = J.inv_sh[t];
+  const int toff = sub << Sp::LOGMB;
+  const int rb = chunk * J.chunk, re = min(J.R, rb + J.chunk);
+  const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
+  u64 acc[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; e++) acc[e] = 0;
+  // the first pass's twiddles depend on the block only: loaded once
+  PassTw<S, LOGN, 0, true, Ar> tw0;
+  tw0.load(W, tid, toff);
+  for (int r = rb; r < re; r++) {
+    const HoistItem it = J.items[r];
+    const u64* __restrict__ src = J.mid + (((size_t)r * 2 + k) * J.n_dig + t) * N + toff;
+    typename Ar::T x[S::E];
+#pragma unroll
+    for (int u = 0; u < G0; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R0); c++) x[u * (1 << R0) + c] = Ar::unbits(src[gidx(gi, c, LO0, R0)]);
+    }
+    // the epilogue's operands, all loads issued together
+    const u64* __restrict__ uw = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
+    const u64* __restrict__ dg = DIAG ? J.diags + ((size_t)it.diag * J.n_dig + t) * N : nullptr;
+    u64 uv[S::E], dv[S::E], cv[S::E];
+#pragma unroll
+    for (int u = 0; u < GF; u++) {
+#pragma unroll
+      for (int c = 0; c < (1 << RF); c++) {
+        const int e = u * (1 << RF) + c;
+        const int idx = toff + (((tid + S::T * u) << RF) | c);
+        uv[e] = uw[idx];
+        dv[e] = DIAG ? dg[idx] : 0;
+        cv[e] = k == 0 ? c0[gal_src(idx, LOGN, it.g)] : 0;
+      }
+    }
+    fwd_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+#pragma unroll
+    for (int e = 0; e < S::E; e++) {
+      u64 ks = addmod(shoup(submod(uv[e], ar.fwd_res(x[e]), q), inv, inv_sh, q), cv[e], q);
+      if constexpr (DIAG) ks = mulmod(ks, dv[e], P);
+      acc[e] = addmod(acc[e], ks, q);
+    }
+    // the next item's first exchange reuses the LDS buffer
+    __syncthreads();
+  }
+  u64* __restrict__ out = J.partial + (((size_t)chunk * 2 + k) * J.n_dig + t) * N;
+#pragma unroll
+  for (int u = 0; u < GF; u++) {
+    const int gi = tid + S::T * u;
+#pragma unroll
+    for (int c = 0; c < (1 << RF); c++) out[toff + ((gi << RF) | c)] = acc[u * (1 << RF) + c];
+  }
+}
+
+// unit = (chunk * n_dig + t) * WB + sub; block b runs on XCD b % 8, and
+// blocks b and b + 8 are the two polys of one unit (the diagonal block is
+// read twice from that XCD's L2)
+template <int LOGN, bool DIAG>
+__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+k_hoist_mac_b(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  using Sp = Split<LOGN>;
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Sp::SB::lds_words()];
+  const int b = blockIdx.x;
+  const int slot = b >> 3;
+  const int k = slot & 1;
+  const int unit = ((slot >> 1) << 3) | (b & 7);
+  if (unit >= J.n_units) return;
+  const int ct = unit / Sp::WB, sub = unit - ct * Sp::WB;
+  const int chunk = ct / J.n_dig, t = ct - chunk * J.n_dig;
+  const PrimeDev P = primes[t];
+  if (P.use_fp)
+    hoist_b_body<LOGN, DIAG, FpAr>(J, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P, chunk, k,
+                                   t, sub, lds);
+  else
+    hoist_b_body<LOGN, DIAG, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P, chunk, k,
+                                    t, sub, lds);
+}
+
 // ---------------- launchers ----------------
 int n_jobs(const NttJob& J) { return J.na * (J.skip_diag ? J.nb - 1 : J.nb); }
 
@@ -1295,10 +1412,49 @@ hipError_t hoist_launch_as(const HoistMac& J, const PrimeDev* primes, const NttT
   return hipGetLastError();
 }
 
+// column phase: job a * n_dig + b = (item a / 2, poly a % 2, modulus b),
+// its output at mid + (a * n_dig + b) * N
+template <int LOGN>
+hipError_t hoist_cols_launch(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+  using Sp = Split<LOGN>;
+  if (J.R <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || !J.mid) return hipErrorInvalidValue;
+  NttJob A{};
+  A.src = J.ucoef;
+  A.sa = 1LL << LOGN;
+  A.sb = 0;
+  A.na = 2 * J.R;
+  A.nb = J.n_dig;
+  A.src_prime = J.special_prime;
+  A.mid = J.mid;
+  for (int b = 0; b < J.n_dig; b++) {
+    A.dst_prime[b] = (unsigned char)b;
+    A.hq[b] = J.hq[b];
+  }
+  hipLaunchKernelGGL((k_hoist_cols<LOGN>), dim3(A.na * A.nb * Sp::WA), dim3(Sp::SA::T), 0, st, A, primes,
+                     tabs);
+  return hipGetLastError();
+}
+
+// block phase with the multiply-accumulate (after the column phase)
+template <int LOGN, bool DIAG>
+hipError_t hoist_split_launch_as(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+  using Sp = Split<LOGN>;
+  const int n_chunks = J.chunk > 0 ? (J.R + J.chunk - 1) / J.chunk : 0;
+  if (n_chunks <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || !J.mid) return hipErrorInvalidValue;
+  HoistMac B = J;
+  B.n_units = n_chunks * J.n_dig * Sp::WB;
+  const int blocks = ((B.n_units + 7) / 8) * 16;
+  hipLaunchKernelGGL((k_hoist_mac_b<LOGN, DIAG>), dim3(blocks), dim3(Sp::SB::T), 0, st, B, primes, tabs);
+  return hipGetLastError();
+}
+
 // the diagonal product and the plain sum (a replication) are separate
 // instantiations: no branch on the diagonal pointer inside the kernel
 template <int LOGN>
 hipError_t hoist_launch(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
+  if (J.mid)
+    return J.diags ? hoist_split_launch_as<LOGN, true>(J, primes, tabs, st)
+                   : hoist_split_launch_as<LOGN, false>(J, primes, tabs, st);
   return J.diags ? hoist_launch_as<LOGN, true>(J, primes, tabs, st)
                  : hoist_launch_as<LOGN, false>(J, primes, tabs, st);
 }
@@ -1469,6 +1625,29 @@ hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes, 
     case 13: return inv_dispatch<13>(job, primes, tabs, st);
     case 14: return inv_dispatch<14>(job, primes, tabs, st);
     default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_hoisted_cols(int log_n, const HoistMac& job, const PrimeDev* primes, const NttTables& tabs,
+                               hipStream_t st) {
+  switch (log_n) {
+    case 10: return hoist_cols_launch<10>(job, primes, tabs, st);
+    case 11: return hoist_cols_launch<11>(job, primes, tabs, st);
+    case 12: return hoist_cols_launch<12>(job, primes, tabs, st);
+    case 13: return hoist_cols_launch<13>(job, primes, tabs, st);
+    case 14: return hoist_cols_launch<14>(job, primes, tabs, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int hoist_split_blocks(int log_n) {
+  switch (log_n) {
+    case 10: return Split<10>::WB;
+    case 11: return Split<11>::WB;
+    case 12: return Split<12>::WB;
+    case 13: return Split<13>::WB;
+    case 14: return Split<14>::WB;
+    default: return 0;
   }
 }
 
