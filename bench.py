@@ -300,8 +300,7 @@ def main():
 # about 27).  The inner products are bound by HBM (their key reads).
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 BUTTERFLY_INSTR = 11
-SINGLE_KERNEL_FAMILIES = ("hoisted_cols", "hoisted_moddown", "hoisted_replication", "hoisted_inner",
-                          "keyswitch_inner")
+SINGLE_KERNEL_FAMILIES = ("hoisted_moddown", "hoisted_replication", "hoisted_inner", "keyswitch_inner")
 NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "hoisted_cols", "hoisted_moddown",
                 "hoisted_replication")
 

@@ -2115,7 +2115,10 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       hipError_t e = launch_inner_hoisted(c->log_n, I, c->d_primes, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted inner: %s", hipGetErrorString(e));
     }
-    {
+    const bool split = c->hoist_split_wgs > 0;
+    if (!split) {
+      // the special-prime limbs to coefficient form (the two-phase form's
+      // column phase runs this transform itself)
       NttJob J{};
       J.src = u.p + (size_t)Lp * n;
       J.sa = (long long)nm * n;
@@ -2132,7 +2135,6 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     // the chip: chunks x 2 x Lp of the one-kernel form (one per compute
     // unit), chunks x 2 x Lp x blocks of the two-phase form (several per
     // compute unit)
-    const bool split = c->hoist_split_wgs > 0;
     const int per_chunk = 2 * Lp * (split ? hoist_split_blocks(c->log_n) : 1);
     const int target = split ? c->hoist_split_wgs : 512;
     n_chunks = std::max(1, std::min(R, (target + per_chunk - 1) / per_chunk));
@@ -2168,8 +2170,10 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     const double nt = 2.0 * R * Lp;
     const int kb = (c->log_n + 1) / 2;
     if (split) {
-      // special limb of every (item, poly) read, every (item, poly, limb) written
-      Prof pa(c, "hoisted_cols", nt * (c->log_n - kb) / c->log_n, 8.0 * n * (2.0 * R + nt));
+      // the inverse transform of every (item, poly) special limb, the column
+      // stages of every (item, poly, limb); the special limbs read, every
+      // (item, poly, limb) written
+      Prof pa(c, "hoisted_cols", 2.0 * R + nt * (c->log_n - kb) / c->log_n, 8.0 * n * (2.0 * R + nt));
       hipError_t e = launch_hoisted_cols(c->log_n, M, c->d_primes, c->tabs, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted columns: %s", hipGetErrorString(e));
     }

@@ -264,11 +264,15 @@ hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev
 // The two workgroups (k = 0, 1) of one (chunk, t) run on the same XCD, one
 // after the other in dispatch order, so the second reads the diagonals
 // from that XCD's L2.  The two-phase form splits each transform as the
-// two-phase NTTs do: a column kernel over every (item, poly, modulus) into
-// mid, then a block kernel whose workgroups (chunk, poly, modulus, block)
-// finish their block's stages item after item and accumulate.
+// two-phase NTTs do: the column phase (the special limb's inverse transform,
+// then for every modulus the lift and the forward column stages, into mid),
+// then a block kernel whose workgroups (chunk, poly, modulus, block) finish
+// their block's stages item after item and accumulate.
 struct HoistMac {
-  const u64* ucoef;  // [R][2][N] special-prime limb of u, coefficient form
+  // [R][2][N] special-prime limb of u: coefficient form (one-kernel form);
+  // the two-phase form's column phase writes there the inverse transform's
+  // block-phase output
+  const u64* ucoef;
   const u64* u;      // [R][2][nm][N]
   const u64* c0;     // [n_dig][N] poly 0 of the input (NTT domain)
   const u64* diags;  // [n_diag][n_dig][N] plaintext diagonals (NTT domain)

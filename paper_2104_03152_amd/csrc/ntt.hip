@@ -717,7 +717,8 @@ k_ntt_fwd_b(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
 }
 
 // TAG names the launch family: 0 plain inverse, 1 the first kernel of a
-// fused key-switch ModUp, 2 that of a fused rescale
+// fused key-switch ModUp, 2 that of a fused rescale, 3 that of the hoisted
+// multiply-accumulate's column phase
 template <int LOGN, bool GATHER, int TAG>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ntt_inv_1(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
@@ -1216,27 +1217,109 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTabl
 }
 
 // ---------------- hoisted multiply-accumulate, two-phase form ----------------
-// Column phase: the lifted special-prime limb of item a / 2, poly a % 2, in
-// modulus b, through the first (row) stages into mid (the forward column
-// kernel with the divide-and-round lift; a kernel of its own so that
-// profiles name it).
+// Column phase, workgroup (a, sub) for item a / 2, poly a % 2 and the 16
+// columns of group sub: the inverse transform's column stages finish the
+// special-prime limb's coefficients in these columns (its block stages ran
+// before, into ucoef), kept in LDS; then for every modulus t the lift and
+// the forward transform's column stages, into mid (job a * n_dig + t).
+template <int LOGN, class Ar>
+__device__ __forceinline__ void hoist_cols_inv(const HoistMac& J, const typename Ar::TW* __restrict__ W,
+                                               const PrimeDev& P, int a, int sub, u64* coef, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const u64* __restrict__ t = J.ucoef + ((size_t)a << LOGN);
+  typename Ar::T x[S::E];
+  PassTw<S, Sp::LOGMA, 0, false, Ar> tw0;
+  tw0.load(W, tid, 0);
+  {
+    constexpr int R = S::bits(0), LO = S::ilo(0), G = S::E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = Ar::unbits(t[col_g<LOGN>(gidx(gi, c, LO, R), sub)]);
+    }
+  }
+  inv_passes<S, Sp::LOGMA, 0, Ar, true>(x, lds, W, ar, tid, 0, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = S::E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) coef[gidx(gi, c, LO, R)] = ar.inv_res(x[u * (1 << R) + c], P);
+    }
+  }
+}
+
+template <int LOGN, class Ar>
+__device__ __forceinline__ void hoist_cols_fwd(const HoistMac& J, const typename Ar::TW* __restrict__ W,
+                                               const PrimeDev& P, int a, int t, int sub, u64 sq, const u64* coef,
+                                               u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const u64 q = P.q, sh = J.h_src, hq = J.hq[t];
+  typename Ar::T x[S::E];
+  PassTw<S, Sp::LOGMA, 0, true, Ar> tw0;
+  tw0.load(W, tid, 0);
+  {
+    constexpr int R = S::bits(0), LO = S::flo(0), G = S::E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) {
+        u64 v = coef[gidx(gi, c, LO, R)] + sh;
+        v = v >= sq ? v - sq : v;
+        x[u * (1 << R) + c] = ar.from_res(submod(red64(v, P), hq, q));
+      }
+    }
+  }
+  fwd_passes<S, Sp::LOGMA, 0, Ar, true>(x, lds, W, ar, tid, 0, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::flo(S::NP - 1), G = S::E >> R;
+    u64* __restrict__ out = J.mid + ((size_t)(a * J.n_dig + t) << LOGN);
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) out[col_g<LOGN>(gidx(gi, c, LO, R), sub)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
 template <int LOGN>
 __global__ void __launch_bounds__(Split<LOGN>::SA::T)
-k_hoist_cols(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+k_hoist_cols(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  using Sp = Split<LOGN>;
   constexpr int N = 1 << LOGN;
-  __shared__ u64 lds[Split<LOGN>::SA::lds_words()];
-  const int w = blockIdx.x / Split<LOGN>::WA;
-  const int sub = blockIdx.x - w * Split<LOGN>::WA;
-  int a, b;
-  decode_job(J, w, a, b);
-  const int dp = J.dst_prime[b];
-  const PrimeDev P = primes[dp];
-  if (P.use_fp)
-    fwd_a_body<LOGN, PRO_ROUNDDIV_LIFT, FpAr>(J, primes, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)dp * N,
-                                              P, w, a, b, sub, J.mid, lds);
+  __shared__ u64 lds[Sp::SA::lds_words()];
+  __shared__ u64 coef[Sp::SA::M];
+  const int a = blockIdx.x / Sp::WA;
+  const int sub = blockIdx.x - a * Sp::WA;
+  const int sp = J.special_prime;
+  const PrimeDev Ps = primes[sp];
+  if (Ps.use_fp)
+    hoist_cols_inv<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)sp * N, Ps, a, sub, coef,
+                               lds);
   else
-    fwd_a_body<LOGN, PRO_ROUNDDIV_LIFT, IntAr>(J, primes, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)dp * N,
-                                               P, w, a, b, sub, J.mid, lds);
+    hoist_cols_inv<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)sp * N, Ps, a, sub, coef,
+                                lds);
+  for (int t = 0; t < J.n_dig; t++) {
+    // the coefficients are complete, and the exchange buffer is free again
+    __syncthreads();
+    const PrimeDev P = primes[t];
+    if (P.use_fp)
+      hoist_cols_fwd<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P, a, t, sub,
+                                 Ps.q, coef, lds);
+    else
+      hoist_cols_fwd<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P, a, t, sub,
+                                  Ps.q, coef, lds);
+  }
 }
 
 // Block phase: workgroup (chunk, k, t, sub) finishes block sub of every
@@ -1412,26 +1495,24 @@ hipError_t hoist_launch_as(const HoistMac& J, const PrimeDev* primes, const NttT
   return hipGetLastError();
 }
 
-// column phase: job a * n_dig + b = (item a / 2, poly a % 2, modulus b),
-// its output at mid + (a * n_dig + b) * N
+// column phase: the inverse transform's block stages of every (item, poly)
+// special-prime limb of u into ucoef, then k_hoist_cols
 template <int LOGN>
 hipError_t hoist_cols_launch(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
   using Sp = Split<LOGN>;
-  if (J.R <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || !J.mid) return hipErrorInvalidValue;
-  NttJob A{};
-  A.src = J.ucoef;
-  A.sa = 1LL << LOGN;
-  A.sb = 0;
-  A.na = 2 * J.R;
-  A.nb = J.n_dig;
-  A.src_prime = J.special_prime;
-  A.mid = J.mid;
-  for (int b = 0; b < J.n_dig; b++) {
-    A.dst_prime[b] = (unsigned char)b;
-    A.hq[b] = J.hq[b];
-  }
-  hipLaunchKernelGGL((k_hoist_cols<LOGN>), dim3(A.na * A.nb * Sp::WA), dim3(Sp::SA::T), 0, st, A, primes,
-                     tabs);
+  if (J.R <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || J.nm != J.n_dig + 1 || !J.mid || !J.ucoef)
+    return hipErrorInvalidValue;
+  NttJob I{};
+  I.src = J.u + ((size_t)J.n_dig << LOGN);
+  I.sa = (long long)J.nm << LOGN;
+  I.na = 2 * J.R;
+  I.nb = 1;
+  I.dst_prime[0] = (unsigned char)J.special_prime;
+  I.mid = const_cast<u64*>(J.ucoef);
+  hipLaunchKernelGGL((k_ntt_inv_1<LOGN, false, 3>), dim3(I.na * Sp::WB), dim3(Sp::SB::T), 0, st, I, primes, tabs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_hoist_cols<LOGN>), dim3(2 * J.R * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes, tabs);
   return hipGetLastError();
 }
 

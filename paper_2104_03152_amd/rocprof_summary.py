@@ -43,7 +43,7 @@ FAMILIES = [
     ("rescale", ["k_ntt_inv_1<13, false, 2>"], ["k_ks_moddown_cols<13, 1>", "k_ntt_fwd_b<13, 3, 1>"]),
     ("moddown+rescale (one workgroup per limb)", ["k_ntt_fwd_a<13, 2>", "k_ntt_fwd<13, 2, 1>"],
      ["k_ntt_fwd_b<13, 2, 1>"]),
-    ("hoisted_cols", ["k_hoist_cols<13>"], []),
+    ("hoisted_cols", ["k_ntt_inv_1<13, false, 3>"], ["k_hoist_cols<13>"]),
     ("hoisted_moddown", ["k_hoist_mac<13, true>", "k_hoist_mac_b<13, true>"], []),
     ("hoisted_replication", ["k_hoist_mac<13, false>", "k_hoist_mac_b<13, false>"], []),
     ("hoisted_inner", ["k_inner_hoisted"], []),
