@@ -2102,6 +2102,11 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       HoistInner I{};
       I.ext = extp;
       I.c1 = c1;
+      I.c0 = x->d;
+      for (int t = 0; t < Lp; t++) {
+        I.pq[t] = c->q[c->L] % c->q[t];
+        I.pq_sh[t] = h_shoup(I.pq[t], c->q[t]);
+      }
       I.items = items;
       I.u = u.p;
       I.R = R;
@@ -2146,7 +2151,6 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     HoistMac M{};
     M.ucoef = ucoef.p;
     M.u = u.p;
-    M.c0 = x->d;
     M.diags = diags;
     M.items = items;
     M.partial = partial.p;

@@ -247,19 +247,24 @@ struct HoistItem {
   int km;
   int diag;
 };
-// u[r][k][t][n] = sum_j D_{j,t}[src_r(n)] * key_r[j][k][kt][n]  (t < nm)
+// u[r][k][t][n] = sum_j D_{j,t}[src_r(n)] * key_r[j][k][kt][n]  (t < nm),
+// plus p c0[t][src_r(n)] for k = 0 and t < n_dig: the ModDown then yields
+// (u - v) p^-1 + c0[t][src_r(n)], the rotation's poly 0, exactly
 struct HoistInner {
   const u64* ext;   // [n_dig][nm][N] ModUp digits (diagonal slots unused)
   const u64* c1;    // [n_dig][N] poly 1 of the input (NTT domain)
+  const u64* c0;    // [n_dig][N] poly 0 of the input (NTT domain)
   const HoistItem* items;
   u64* u;           // [R][2][nm][N]
   int R, n_dig, nm, t_begin, t_end, special_prime;
+  u64 pq[HE_MAXM], pq_sh[HE_MAXM];  // p mod q_t and its Shoup companion
 };
 hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev* primes,
                                 hipStream_t st);
 // ModDown of every item fused with the diagonal multiply-accumulate: WG
 // (chunk c, poly k, modulus t) sums over its items r:
-//   ((u[r][k][t] - NTT(r_r - h)) p^-1 + [k == 0] c0[t][src_r]) * diag[r][t]
+//   (u[r][k][t] - NTT(r_r - h)) p^-1 * diag[r][t]
+// (u[r][0] carries the rotated c0, see HoistInner)
 // into partial[c][k][t] (without the diagonal factor when diags is NULL).
 // The two workgroups (k = 0, 1) of one (chunk, t) run on the same XCD, one
 // after the other in dispatch order, so the second reads the diagonals
@@ -274,7 +279,6 @@ struct HoistMac {
   // block-phase output
   const u64* ucoef;
   const u64* u;      // [R][2][nm][N]
-  const u64* c0;     // [n_dig][N] poly 0 of the input (NTT domain)
   const u64* diags;  // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
   const HoistItem* items;
   u64* partial;      // [n_chunks][2][n_dig][N]

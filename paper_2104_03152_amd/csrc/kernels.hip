@@ -335,7 +335,8 @@ __global__ void k_mont(int n, u64* data, long long total, int to, ModList mods,
 }
 
 // batched inner product of hoisted rotations: every item reads the shared
-// ModUp digits at its own Galois source index.  Each thread computes two
+// ModUp digits (and, for poly 0, the input's c0) at its own Galois source
+// index.  Each thread computes two
 // neighbouring words (16-byte key loads and output stores); the digits are
 // gathered word by word (they stay in L2, shared by all items).
 __global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restrict__ primes) {
@@ -371,6 +372,11 @@ __global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restr
     r01 = addmod(r01, mont_reduce(a01, P), P.q);
     r10 = addmod(r10, mont_reduce(a10, P), P.q);
     r11 = addmod(r11, mont_reduce(a11, P), P.q);
+  }
+  if (t < J.n_dig) {
+    const u64* c0 = J.c0 + (size_t)t * n;
+    r00 = addmod(r00, shoup(c0[src0], J.pq[t], J.pq_sh[t], P.q), P.q);
+    r01 = addmod(r01, shoup(c0[src1], J.pq[t], J.pq_sh[t], P.q), P.q);
   }
   *reinterpret_cast<ulonglong2*>(J.u + (((size_t)r * 2 + 0) * J.nm + t) * n + i) = make_ulonglong2(r00, r01);
   *reinterpret_cast<ulonglong2*>(J.u + (((size_t)r * 2 + 1) * J.nm + t) * n + i) = make_ulonglong2(r10, r11);

@@ -1162,7 +1162,6 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
     }
     __syncthreads();
     const u64* __restrict__ uw = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
-    const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
     if constexpr (DIAG) {
       // Barrett product with the diagonal: no precomputed companion, so
       // one diagonal word per output word is read
@@ -1171,8 +1170,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
       for (int e = 0; e < C::E; e++) {
         const int idx = tid + C::T * e;
         const u64 v = lds[pad(idx)];
-        u64 ks = shoup(submod(uw[idx], v, q), inv, inv_sh, q);
-        if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
+        const u64 ks = shoup(submod(uw[idx], v, q), inv, inv_sh, q);
         acc[e] = addmod(acc[e], mulmod(ks, dg[idx], P), q);
       }
     } else {
@@ -1181,9 +1179,7 @@ __device__ __forceinline__ void hoist_body(const HoistMac& J, const PrimeDev* __
       for (int e = 0; e < C::E; e++) {
         const int idx = tid + C::T * e;
         const u64 v = lds[pad(idx)];
-        u64 ks = shoup(submod(uw[idx], v, q), inv, inv_sh, q);
-        if (k == 0) ks = addmod(ks, c0[gal_src(idx, LOGN, it.g)], q);
-        acc[e] = addmod(acc[e], ks, q);
+        acc[e] = addmod(acc[e], shoup(submod(uw[idx], v, q), inv, inv_sh, q), q);
       }
     }
     __syncthreads();
@@ -1339,7 +1335,6 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
   const u64 inv = J.inv[t], inv_sh = J.inv_sh[t];
   const int toff = sub << Sp::LOGMB;
   const int rb = chunk * J.chunk, re = min(J.R, rb + J.chunk);
-  const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
   u64 acc[S::E];
 #pragma unroll
   for (int e = 0; e < S::E; e++) acc[e] = 0;
@@ -1359,7 +1354,7 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
     // the epilogue's operands, all loads issued together
     const u64* __restrict__ uw = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
     const u64* __restrict__ dg = DIAG ? J.diags + ((size_t)it.diag * J.n_dig + t) * N : nullptr;
-    u64 uv[S::E], dv[S::E], cv[S::E];
+    u64 uv[S::E], dv[S::E];
 #pragma unroll
     for (int u = 0; u < GF; u++) {
 #pragma unroll
@@ -1368,13 +1363,12 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
         const int idx = toff + (((tid + S::T * u) << RF) | c);
         uv[e] = uw[idx];
         dv[e] = DIAG ? dg[idx] : 0;
-        cv[e] = k == 0 ? c0[gal_src(idx, LOGN, it.g)] : 0;
       }
     }
     fwd_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
 #pragma unroll
     for (int e = 0; e < S::E; e++) {
-      u64 ks = addmod(shoup(submod(uv[e], ar.fwd_res(x[e]), q), inv, inv_sh, q), cv[e], q);
+      u64 ks = shoup(submod(uv[e], ar.fwd_res(x[e]), q), inv, inv_sh, q);
       if constexpr (DIAG) ks = mulmod(ks, dv[e], P);
       acc[e] = addmod(acc[e], ks, q);
     }
