@@ -336,7 +336,8 @@ __global__ void k_mont(int n, u64* data, long long total, int to, ModList mods,
 
 // batched inner product of hoisted rotations: every item reads the shared
 // ModUp digits (and, for poly 0, the input's c0) at its own Galois source
-// index.  Each thread computes two
+// index.  Keys and outputs pass once: non-temporal loads and stores, so
+// that L2 keeps the gathered digits.  Each thread computes two
 // neighbouring words (16-byte key loads and output stores); the digits are
 // gathered word by word (they stay in L2, shared by all items).
 __global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restrict__ primes) {
@@ -361,12 +362,11 @@ __global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restr
     for (int j = j0; j < j1; j++) {
       const u64* dj = (j == t) ? J.c1 + (size_t)t * n : J.ext + ((size_t)j * J.nm + t) * n;
       const u64 d0 = dj[src0], d1 = dj[src1];
-      const ulonglong2 k0 = *reinterpret_cast<const ulonglong2*>(kp + j * ks_j);
-      const ulonglong2 k1 = *reinterpret_cast<const ulonglong2*>(kp + j * ks_j + ks_k);
-      a00 = add128(a00, mul_wide(d0, k0.x));
-      a01 = add128(a01, mul_wide(d1, k0.y));
-      a10 = add128(a10, mul_wide(d0, k1.x));
-      a11 = add128(a11, mul_wide(d1, k1.y));
+      const u64* kq = kp + j * ks_j;  // poly 0; poly 1 at kq + ks_k
+      a00 = add128(a00, mul_wide(d0, __builtin_nontemporal_load(kq)));
+      a01 = add128(a01, mul_wide(d1, __builtin_nontemporal_load(kq + 1)));
+      a10 = add128(a10, mul_wide(d0, __builtin_nontemporal_load(kq + ks_k)));
+      a11 = add128(a11, mul_wide(d1, __builtin_nontemporal_load(kq + ks_k + 1)));
     }
     r00 = addmod(r00, mont_reduce(a00, P), P.q);
     r01 = addmod(r01, mont_reduce(a01, P), P.q);
@@ -378,8 +378,12 @@ __global__ void k_inner_hoisted(int log_n, HoistInner J, const PrimeDev* __restr
     r00 = addmod(r00, shoup(c0[src0], J.pq[t], J.pq_sh[t], P.q), P.q);
     r01 = addmod(r01, shoup(c0[src1], J.pq[t], J.pq_sh[t], P.q), P.q);
   }
-  *reinterpret_cast<ulonglong2*>(J.u + (((size_t)r * 2 + 0) * J.nm + t) * n + i) = make_ulonglong2(r00, r01);
-  *reinterpret_cast<ulonglong2*>(J.u + (((size_t)r * 2 + 1) * J.nm + t) * n + i) = make_ulonglong2(r10, r11);
+  u64* u0 = J.u + (((size_t)r * 2 + 0) * J.nm + t) * n + i;
+  u64* u1 = J.u + (((size_t)r * 2 + 1) * J.nm + t) * n + i;
+  __builtin_nontemporal_store(r00, u0);
+  __builtin_nontemporal_store(r01, u0 + 1);
+  __builtin_nontemporal_store(r10, u1);
+  __builtin_nontemporal_store(r11, u1 + 1);
 }
 
 // s + sum_c p[c * stride] mod q, eight loads in flight at a time
