@@ -184,7 +184,7 @@ struct he_ctx {
   NttTables tabs{};
   bool capturing = false;  // a graph capture of st is open
   int fuse_max = 256;      // fused key switch when B*Lp^2 <= this, fused rescale when 2*n_ct*l <= this
-  int hoist_split_wgs = 2048;  // two-phase hoisted multiply-accumulate, about this many workgroups (0: one kernel)
+  int hoist_split_wgs = 1536;  // two-phase hoisted multiply-accumulate, about this many workgroups (0: one kernel)
   bool have_keys = false;
   u64* d_s = nullptr;   // [L+1][N]
   u64* d_pk = nullptr;  // [2][L][N]
