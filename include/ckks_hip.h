@@ -78,6 +78,12 @@ typedef struct {
 
 /* Create a context: prime chain, NTT tables.  hip_stream: a hipStream_t to
  * enqueue on (NULL: the library creates a stream of default priority).
+ * Kernel-shape settings read from the environment here (results do not
+ * depend on them): HE_NTT_SPLIT_JOBS (two-phase transforms for launches of
+ * up to this many limbs, default 256), HE_FUSE_MAX (fused key switch while
+ * items x digits^2 stays within it, default 256), HE_HOIST_SPLIT_WGS (about
+ * this many workgroups for the hoisted multiply-accumulate's block phase,
+ * default 1536; 0 selects the one-kernel form).
  * Errors: HE_EINVAL for bad parameters, HE_EHIP, HE_EOOM. */
 he_status he_ctx_create(const he_params* params, he_alloc_fn alloc,
                         he_free_fn free_fn, void* alloc_user, void* hip_stream,
