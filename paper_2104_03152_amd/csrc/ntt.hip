@@ -1341,15 +1341,31 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
   // the first pass's twiddles depend on the block only: loaded once
   PassTw<S, LOGN, 0, true, Ar> tw0;
   tw0.load(W, tid, toff);
-  for (int r = rb; r < re; r++) {
-    const HoistItem it = J.items[r];
-    const u64* __restrict__ src = J.mid + (((size_t)r * 2 + k) * J.n_dig + t) * N + toff;
-    typename Ar::T x[S::E];
+  // the column-phase output of the next rotation is loaded while the
+  // current one is transformed
+  u64 nx[S::E];
+  if (rb < re) {
+    const u64* __restrict__ src = J.mid + (((size_t)rb * 2 + k) * J.n_dig + t) * N + toff;
 #pragma unroll
     for (int u = 0; u < G0; u++) {
       const int gi = tid + S::T * u;
 #pragma unroll
-      for (int c = 0; c < (1 << R0); c++) x[u * (1 << R0) + c] = Ar::unbits(src[gidx(gi, c, LO0, R0)]);
+      for (int c = 0; c < (1 << R0); c++) nx[u * (1 << R0) + c] = src[gidx(gi, c, LO0, R0)];
+    }
+  }
+  for (int r = rb; r < re; r++) {
+    const HoistItem it = J.items[r];
+    typename Ar::T x[S::E];
+#pragma unroll
+    for (int e = 0; e < S::E; e++) x[e] = Ar::unbits(nx[e]);
+    if (r + 1 < re) {
+      const u64* __restrict__ src = J.mid + (((size_t)(r + 1) * 2 + k) * J.n_dig + t) * N + toff;
+#pragma unroll
+      for (int u = 0; u < G0; u++) {
+        const int gi = tid + S::T * u;
+#pragma unroll
+        for (int c = 0; c < (1 << R0); c++) nx[u * (1 << R0) + c] = src[gidx(gi, c, LO0, R0)];
+      }
     }
     // the epilogue's operands, all loads issued together
     const u64* __restrict__ uw = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
@@ -1386,9 +1402,9 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
 
 // unit = (chunk * n_dig + t) * WB + sub; block b runs on XCD b % 8, and
 // blocks b and b + 8 are the two polys of one unit (the diagonal block is
-// read twice from that XCD's L2)
+// read twice from that XCD's L2).  Four waves per SIMD: at most 128 VGPRs.
 template <int LOGN, bool DIAG>
-__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+__global__ void __launch_bounds__(Split<LOGN>::SB::T, 4)
 k_hoist_mac_b(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   using Sp = Split<LOGN>;
   constexpr int N = 1 << LOGN;
