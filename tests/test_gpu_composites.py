@@ -8,6 +8,7 @@ import pytest
 from oracle import oracle as O
 from paper_2104_03152_amd import inputs as I
 from tests.gpu_common import Pair, say
+from tests.plain_ref import cnn_fp64
 
 pytestmark = pytest.mark.gpu
 
@@ -97,14 +98,6 @@ def test_pack_and_sum_bit_exact(deep):
     P.ct_equal(gp, op, "pack")
     say("sum")
     P.ct_equal(P.H.he_sum_slots(P.g, pairs[0][0], 48), P.o.sum_slots(pairs[0][1], 48), "sum48")
-
-
-def cnn_fp64(d):
-    v = O.im2col(d["img"], 7, 3).reshape(49, 64)
-    conv = d["conv_k"] @ v + d["conv_b"][:, None]
-    x = conv.reshape(256) ** 2
-    h = (x @ d["w1"] + d["b1"]) ** 2
-    return h @ d["w2"] + d["b2"]
 
 
 def run_cnn_gpu(H, g, x, d):

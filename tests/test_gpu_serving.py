@@ -7,16 +7,9 @@ import pytest
 from oracle import oracle as O
 from paper_2104_03152_amd import inputs as I
 from tests.gpu_common import hip, say
+from tests.plain_ref import cnn_fp64
 
 pytestmark = pytest.mark.gpu
-
-
-def cnn_fp64(d, img):
-    v = O.im2col(img, 7, 3).reshape(49, 64)
-    conv = d["conv_k"] @ v + d["conv_b"][:, None]
-    x = conv.reshape(256) ** 2
-    h = (x @ d["w1"] + d["b1"]) ** 2
-    return h @ d["w2"] + d["b2"]
 
 
 def test_alone_equals_mix():

@@ -14,6 +14,7 @@ import pytest
 from oracle import oracle as O
 from paper_2104_03152_amd import inputs as I
 from tests.bigint_ref import centered, crt, negacyclic_int, residues
+from tests.plain_ref import cnn_fp64
 
 
 @pytest.fixture(scope="module")
@@ -342,14 +343,6 @@ def test_composites_vs_fp64(deep):
         o.galois_keygen(1 << t)
     s = o.sum_slots(o.encrypt(o.encode(xv, o.scale, 3), 3), 48)
     assert abs(_dec(o, s, 1)[0] - xv.sum()) < 1e-6
-
-
-def cnn_fp64(d):
-    v = O.im2col(d["img"], 7, 3).reshape(49, 64)
-    conv = d["conv_k"] @ v + d["conv_b"][:, None]
-    x = conv.reshape(256) ** 2
-    h = (x @ d["w1"] + d["b1"]) ** 2
-    return h @ d["w2"] + d["b2"]
 
 
 def test_cnn_vs_fp64_full_size():
