@@ -13,9 +13,17 @@
  *  - Handles are opaque.  Every `out` handle is new and owned by the caller,
  *    who frees it with the matching he_*_free.  Inputs are never consumed or
  *    modified.
+ *  - Handles belong to the context that made them; a call given a handle of
+ *    another context fails with HE_EINVAL before anything is enqueued (the
+ *    context's stream is what orders the work on a handle's memory).
  *  - Device memory comes from the allocator callbacks given to he_ctx_create
  *    (NULL: the library's own caching pool over hipMalloc).  Freed blocks are
- *    cached by the context and reused in stream order.
+ *    cached by the context and reused in stream order; they go back to the
+ *    allocator only after the context's stream has drained (when a failed
+ *    allocation trims the cache, and at he_ctx_destroy).  An allocator that
+ *    returns NULL makes the call fail with HE_EOOM after the cache has been
+ *    trimmed and the allocation retried; the call's partial results are
+ *    released and the context stays usable.
  *  - Every operation is enqueued on the context's HIP stream and returns
  *    before the GPU finishes, except the calls that return host data
  *    (export, decode, decrypt+decode paths), which synchronise the stream.

@@ -3,9 +3,10 @@ the C ABI, argument marshalling only.  Every step of every operation runs in
 the HIP library; there is no fallback: if the library is not built, loading
 raises.  Build it with `python -m paper_2104_03152_amd.build`.
 
-PyTorch is used for plumbing only: the context enqueues on torch's current
-HIP stream when torch sees a GPU, and raw device buffers for he_ntt_* may be
-torch tensors."""
+PyTorch is used for plumbing only: device memory comes from torch's caching
+allocator (through the he_alloc_fn / he_free_fn callbacks, on the context's
+stream), the context enqueues on a torch stream, and raw device buffers for
+he_ntt_* may be torch tensors."""
 import ctypes as C
 import os
 
@@ -229,9 +230,46 @@ class Tensor(_Handle):
         return _BorrowedCt(self.ctx, out.value, self)
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class Allocator:
+    """Device-memory callbacks for he_ctx_create.  alloc(nbytes) returns a
+    device address (int) or None; free(ptr, nbytes) releases it.  A failing
+    alloc makes the library return HE_EOOM."""
+
+    def __init__(self, alloc, free):
+        self._alloc, self._free = alloc, free
+
+        def a(nbytes, user):
+            try:
+                return self._alloc(int(nbytes))
+            except Exception:  # out of memory: the library reports HE_EOOM
+                return None
+
+        def f(ptr, nbytes, user):
+            try:
+                self._free(ptr, int(nbytes))
+            except Exception:
+                pass
+
+        self.c_alloc, self.c_free = _ALLOC_FN(a), _FREE_FN(f)
+
+
+def torch_allocator(stream_handle, device=None):
+    """torch's caching allocator, blocks associated with the given stream (the
+    context's): torch reuses a freed block only for work on that stream."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+    return Allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev, stream_handle),
+                     lambda ptr, n: torch.cuda.caching_allocator_delete(ptr))
+
+
 class Ctx:
-    def __init__(self, ptr):
+    def __init__(self, ptr, keep=()):
         self.ptr = ptr
+        self._keep = keep  # callbacks and the stream object outlive the context
         lg, L = C.c_int32(), C.c_int32()
         primes = (C.c_uint64 * (HE_MAX_PRIMES + 1))()
         _chk(lib().he_ctx_info(ptr, C.byref(lg), C.byref(L), primes), "he_ctx_info")
@@ -251,17 +289,12 @@ class Ctx:
             pass
 
 
-def _torch_stream():
-    try:
-        import torch
-        if torch.cuda.is_available():
-            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
-    except Exception:
-        pass
-    return None
-
-
-def he_ctx_create(log_n, prime_bits, scale, seed, auto_rescale=True, stream="torch"):
+def he_ctx_create(log_n, prime_bits, scale, seed, auto_rescale=True, stream="torch", allocator="torch"):
+    """stream: "torch" (torch's current stream, or a new torch stream when
+    that is the null stream), None (a new torch stream when the allocator is
+    torch's, else one the library creates) or a raw hipStream_t.
+    allocator: "torch" (torch's caching allocator on the context's stream),
+    None (the library's pool over hipMalloc) or an Allocator."""
     p = he_params()
     p.log_n = log_n
     p.n_primes = len(prime_bits)
@@ -270,10 +303,28 @@ def he_ctx_create(log_n, prime_bits, scale, seed, auto_rescale=True, stream="tor
     p.scale = float(scale)
     p.auto_rescale = 1 if auto_rescale else 0
     p.seed = seed
-    st = _torch_stream() if stream == "torch" else stream
+    keep = []
+    st = stream
+    if stream == "torch" or (stream is None and allocator == "torch"):
+        import torch
+        ts = torch.cuda.current_stream() if stream == "torch" else None
+        if ts is None or ts.cuda_stream == 0:
+            ts = torch.cuda.Stream()  # default priority
+        keep.append(ts)
+        st = ts.cuda_stream
+    if isinstance(st, C.c_void_p):
+        st = st.value
+    if allocator == "torch":
+        allocator = torch_allocator(st or 0)
+    if allocator is not None:
+        keep.append(allocator)
+        fa, ff = allocator.c_alloc, allocator.c_free
+    else:
+        fa = ff = None
     out = C.c_void_p()
-    _chk(lib().he_ctx_create(C.byref(p), None, None, None, st, C.byref(out)), "he_ctx_create")
-    return Ctx(out.value)
+    _chk(lib().he_ctx_create(C.byref(p), fa, ff, None, C.c_void_p(st) if st else None, C.byref(out)),
+         "he_ctx_create")
+    return Ctx(out.value, tuple(keep))
 
 
 def he_ctx_destroy(ctx):

@@ -90,6 +90,9 @@ struct Pool {
   he_alloc_fn alloc = nullptr;
   he_free_fn release = nullptr;
   void* user = nullptr;
+  // the context's stream: every use of a block is ordered on it, so a block
+  // goes back to the allocator only once the stream has drained
+  hipStream_t st = nullptr;
   std::unordered_map<size_t, std::vector<void*>> cache;
   std::unordered_map<void*, size_t> live;
   size_t bytes_live = 0;
@@ -106,6 +109,8 @@ struct Pool {
       (void)hipFree(p);
   }
   void trim() {
+    if (cache.empty()) return;
+    if (st) (void)hipStreamSynchronize(st);
     for (auto& kv : cache)
       for (void* p : kv.second) raw_free(p, kv.first);
     cache.clear();
@@ -120,7 +125,7 @@ struct Pool {
       it->second.pop_back();
     } else {
       p = raw_alloc(bytes);
-      if (!p) {
+      if (!p && !retain) {  // no stream synchronisation inside a graph capture
         trim();
         p = raw_alloc(bytes);
       }
@@ -230,6 +235,24 @@ struct he_plan {
   HoistItem* rep_items = nullptr;  // device table of the replication rotations
   uint64_t rep_epoch = ~0ull;
 };
+
+// Every handle passed to a call must belong to that call's context.  A
+// context's stream is the only thing that orders the kernels writing a
+// handle's memory before the kernels reading it; a handle of another context
+// would be read on this stream while its own stream may still be writing it
+// (a race that shows only when the two streams overlap), and its buffers
+// would return to the wrong pool.
+template <class H>
+static he_status own(const he_ctx* c, const H* h) {
+  if (c && h && h->ctx != c) return fail(HE_EINVAL, "handle of another context");
+  return HE_OK;
+}
+template <class H>
+static he_status own_all(const he_ctx* c, const H* const* hs, size_t n) {
+  if (hs)
+    for (size_t i = 0; i < n; i++) TRY(own(c, hs[i]));
+  return HE_OK;
+}
 
 namespace {
 
@@ -988,6 +1011,7 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
     }
     c->own_stream = true;
   }
+  c->pool.st = c->st;
   // per-prime constants and twiddles
   const int np = (int)q.size();
   std::vector<PrimeDev> hp(np);
@@ -1051,11 +1075,16 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
     he_ctx_destroy(c);
     return fail(HE_EOOM, "table allocation failed");
   }
-  if (hipMemcpy(c->d_primes, hp.data(), sizeof(PrimeDev) * np, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_fwd, fwd.data(), fwd.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_inv, inv.data(), inv.size() * sizeof(u64), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_fwd_fp, fwd_fp.data(), fwd_fp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_inv_fp, inv_fp.data(), inv_fp.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+  // uploads on the context's stream: a block from the caller's allocator may
+  // still be in use by earlier work on that stream
+  if (hipMemcpyAsync(c->d_primes, hp.data(), sizeof(PrimeDev) * np, hipMemcpyHostToDevice, c->st) != hipSuccess ||
+      hipMemcpyAsync(c->d_fwd, fwd.data(), fwd.size() * sizeof(u64), hipMemcpyHostToDevice, c->st) != hipSuccess ||
+      hipMemcpyAsync(c->d_inv, inv.data(), inv.size() * sizeof(u64), hipMemcpyHostToDevice, c->st) != hipSuccess ||
+      hipMemcpyAsync(c->d_fwd_fp, fwd_fp.data(), fwd_fp.size() * sizeof(double), hipMemcpyHostToDevice, c->st) !=
+          hipSuccess ||
+      hipMemcpyAsync(c->d_inv_fp, inv_fp.data(), inv_fp.size() * sizeof(double), hipMemcpyHostToDevice, c->st) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess) {
     he_ctx_destroy(c);
     return fail(HE_EHIP, "table upload failed");
   }
@@ -1120,8 +1149,11 @@ he_status he_keygen(he_ctx* c, const int32_t* steps, size_t n_steps) {
   const int n = c->n, L = c->L;
   if (!c->have_keys) {
     u64* s = (u64*)c->pool.get((size_t)(L + 1) * n * sizeof(u64));
-    u64* pk = (u64*)c->pool.get(2 * (size_t)L * n * sizeof(u64));
-    if (!s || !pk) return fail(HE_EOOM, "key allocation failed");
+    u64* pk = s ? (u64*)c->pool.get(2 * (size_t)L * n * sizeof(u64)) : nullptr;
+    if (!s || !pk) {
+      c->pool.put(s);
+      return fail(HE_EOOM, "key allocation failed");
+    }
     c->d_s = s;
     c->d_pk = pk;
     ModList all = mods_range(L + 1), data = mods_range(L);
@@ -1180,6 +1212,7 @@ he_status he_pt_import(he_ctx* c, const int64_t* coeffs, double scale, int32_t l
 }
 
 he_status he_pt_export(he_ctx* c, const he_pt* pt, uint64_t* h, size_t cap, int32_t* level, double* scale) {
+  TRY(own(c, pt));
   NO_CAPTURE(c);
   if (!c || !pt || !h) return fail(HE_EINVAL, "NULL argument");
   const size_t words = pt_words(c, pt->level);
@@ -1193,6 +1226,7 @@ he_status he_pt_export(he_ctx* c, const he_pt* pt, uint64_t* h, size_t cap, int3
 }
 
 he_status he_decode(he_ctx* c, const he_pt* pt, double* out, size_t nv) {
+  TRY(own(c, pt));
   NO_CAPTURE(c);
   if (!c || !pt || (!out && nv)) return fail(HE_EINVAL, "NULL argument");
   if (nv > (size_t)c->n / 2) return fail(HE_ERANGE, "%zu values exceed N/2", nv);
@@ -1205,6 +1239,7 @@ he_status he_decode(he_ctx* c, const he_pt* pt, double* out, size_t nv) {
 }
 
 he_status he_encrypt(he_ctx* c, const he_pt* pt, uint32_t idx, int32_t use_sk, he_ct** out) {
+  TRY(own(c, pt));
   if (!c || !pt || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (!c->have_keys) return fail(HE_ENOKEY, "he_keygen must run first");
@@ -1243,6 +1278,7 @@ he_status he_encrypt(he_ctx* c, const he_pt* pt, uint32_t idx, int32_t use_sk, h
 }
 
 he_status he_decrypt(he_ctx* c, const he_ct* ct, he_pt** out) {
+  TRY(own(c, ct));
   if (!c || !ct || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (!c->have_keys) return fail(HE_ENOKEY, "no secret key");
@@ -1258,6 +1294,7 @@ he_status he_decrypt(he_ctx* c, const he_ct* ct, he_pt** out) {
 }
 
 he_status he_ct_export(he_ctx* c, const he_ct* ct, uint64_t* h, size_t cap, int32_t* level, double* scale) {
+  TRY(own(c, ct));
   NO_CAPTURE(c);
   if (!c || !ct || !h) return fail(HE_EINVAL, "NULL argument");
   const size_t words = ct_words(c, ct->level);
@@ -1305,6 +1342,8 @@ he_status he_ct_info(const he_ct* ct, int32_t* level, double* scale) {
 }
 
 static he_status addsub(he_ctx* c, const he_ct* a, const he_ct* b, int op, he_ct** out) {
+  TRY(own(c, a));
+  TRY(own(c, b));
   if (!c || !a || !b || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (!scales_match(a->scale, b->scale)) return fail(HE_ESCALE, "scales %g and %g differ", a->scale, b->scale);
@@ -1327,6 +1366,7 @@ he_status he_add(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) { retur
 he_status he_sub(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) { return addsub(c, a, b, 1, out); }
 
 he_status he_negate(he_ctx* c, const he_ct* a, he_ct** out) {
+  TRY(own(c, a));
   if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   he_ct* r = nullptr;
@@ -1341,6 +1381,8 @@ he_status he_negate(he_ctx* c, const he_ct* a, he_ct** out) {
 }
 
 static he_status add_plain_impl(he_ctx* c, const he_ct* a, const he_pt* p, int neg, he_ct** out) {
+  TRY(own(c, a));
+  TRY(own(c, p));
   if (!c || !a || !p || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (!scales_match(a->scale, p->scale)) return fail(HE_ESCALE, "scales %g and %g differ", a->scale, p->scale);
@@ -1394,6 +1436,7 @@ static he_status rescale_raw(he_ctx* c, const he_ct* a, he_ct** out) {
 }
 
 he_status he_rescale(he_ctx* c, const he_ct* a, he_ct** out) {
+  TRY(own(c, a));
   if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   return rescale_raw(c, a, out);
@@ -1410,6 +1453,8 @@ static he_status maybe_rescale(he_ctx* c, he_ct* r, he_ct** out) {
 }
 
 he_status he_mul_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
+  TRY(own(c, a));
+  TRY(own(c, p));
   if (!c || !a || !p || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   he_ct* r = nullptr;
@@ -1448,6 +1493,8 @@ static he_status mul_relin_raw(he_ctx* c, const he_ct* a, const he_ct* b, he_ct*
 }
 
 he_status he_mul_relin(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
+  TRY(own(c, a));
+  TRY(own(c, b));
   if (!c || !a || !b || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   he_ct* r = nullptr;
@@ -1458,6 +1505,7 @@ he_status he_mul_relin(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
 he_status he_square(he_ctx* c, const he_ct* a, he_ct** out) { return he_mul_relin(c, a, a, out); }
 
 he_status he_drop_to(he_ctx* c, const he_ct* a, int32_t level, he_ct** out) {
+  TRY(own(c, a));
   if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (level < 0 || level > a->level) return fail(HE_ELEVEL, "cannot drop from level %d to %d", a->level, level);
@@ -1480,6 +1528,7 @@ static he_status rotate_raw(he_ctx* c, const he_ct* a, int step, he_ct** out) {
 }
 
 he_status he_rotate(he_ctx* c, const he_ct* a, int32_t step, he_ct** out) {
+  TRY(own(c, a));
   if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   return rotate_raw(c, a, step, out);
@@ -1550,6 +1599,7 @@ static he_status power_impl(he_ctx* c, const he_ct* a, long long k, Squares& sq,
 }
 
 he_status he_power(he_ctx* c, const he_ct* a, uint32_t k, he_ct** out) {
+  TRY(own(c, a));
   if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   Squares sq;
@@ -1568,6 +1618,7 @@ he_status he_power(he_ctx* c, const he_ct* a, uint32_t k, he_ct** out) {
 // scale(a^i) at a^i's level l and rescaled (every term at scale Delta), cut
 // to the lowest level and summed in increasing i; coeffs[0] added last.
 he_status he_polyval(he_ctx* c, const he_ct* a, const double* coeffs, size_t n_coeffs, he_ct** out) {
+  TRY(own(c, a));
   if (!c || !a || !out || (n_coeffs && !coeffs)) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   std::vector<size_t> idx;
@@ -1668,6 +1719,8 @@ static he_status batch_level(const he_ct* const* a, const he_ct* const* b, size_
 }
 
 he_status he_mul_relin_many(he_ctx* c, const he_ct* const* a, const he_ct* const* b, size_t n, he_ct** out) {
+  TRY(own_all(c, a, n));
+  TRY(own_all(c, b, n));
   if (!c || !out || (n && (!a || !b))) return fail(HE_EINVAL, "NULL argument");
   for (size_t i = 0; i < n; i++) out[i] = nullptr;
   if (n == 0) return HE_OK;
@@ -1729,6 +1782,7 @@ he_status he_mul_relin_many(he_ctx* c, const he_ct* const* a, const he_ct* const
 }
 
 he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps, size_t n, he_ct** out) {
+  TRY(own_all(c, a, n));
   if (!c || !out || (n && (!a || !steps))) return fail(HE_EINVAL, "NULL argument");
   for (size_t i = 0; i < n; i++) out[i] = nullptr;
   if (n == 0) return HE_OK;
@@ -1824,6 +1878,7 @@ static he_status rotate_and_sum(he_ctx* c, he_ct* x, uint32_t count, uint32_t st
 }
 
 he_status he_sum_slots(he_ctx* c, const he_ct* a, uint32_t nv, he_ct** out) {
+  TRY(own(c, a));
   if (!c || !a || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (nv == 0 || nv > (uint32_t)c->n / 2) return fail(HE_ERANGE, "slot count %u outside 1..N/2", nv);
@@ -1839,6 +1894,7 @@ static he_status encode_slots(he_ctx* c, const std::vector<double>& v, double sc
 
 he_status he_conv_plan(he_ctx* c, const he_ct* like, const double* kernel, uint32_t kk, uint32_t windows,
                        double bias, he_plan** out) {
+  TRY(own(c, like));
   NO_CAPTURE(c);
   if (!c || !like || !kernel || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
@@ -1871,6 +1927,7 @@ he_status he_conv_plan(he_ctx* c, const he_ct* like, const double* kernel, uint3
 
 he_status he_matmul_plan(he_ctx* c, const he_ct* like, const double* W, uint32_t n_in, uint32_t n_out,
                          const double* bias, he_plan** out) {
+  TRY(own(c, like));
   NO_CAPTURE(c);
   if (!c || !like || !W || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
@@ -2236,6 +2293,8 @@ static he_status matmul_apply(he_ctx* c, he_plan* p, const he_ct* x, he_ct** out
 }
 
 he_status he_plan_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out) {
+  TRY(own(c, p));
+  TRY(own(c, x));
   if (!c || !p || !x || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   if (x->level != p->level) return fail(HE_ELEVEL, "plan made for level %d, input at %d", p->level, x->level);
@@ -2246,6 +2305,8 @@ he_status he_plan_apply(he_ctx* c, const he_plan* p, const he_ct* x, he_ct** out
 
 he_status he_plan_apply_many(he_ctx* c, const he_plan* const* plans, uint32_t nb, const he_ct* x,
                              he_ct** outs) {
+  TRY(own_all(c, plans, nb));
+  TRY(own(c, x));
   if (!c || !plans || !x || !outs) return fail(HE_EINVAL, "NULL argument");
   for (uint32_t b = 0; b < nb; b++) outs[b] = nullptr;
   if (nb == 0) return HE_OK;
@@ -2292,6 +2353,7 @@ he_status he_enc_matmul(he_ctx* c, const he_ct* x, const double* W, uint32_t n_i
 }
 
 he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t width, he_ct** out) {
+  TRY(own_all(c, (const he_ct* const*)parts, n_parts));
   if (!c || !parts || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   const uint32_t half = (uint32_t)c->n / 2;
@@ -2558,6 +2620,8 @@ void he_graph_free(he_graph* g) {
 }
 
 he_status he_ct_copy(he_ctx* c, he_ct* dst, const he_ct* src) {
+  TRY(own(c, dst));
+  TRY(own(c, src));
   if (!c || !dst || !src) return fail(HE_EINVAL, "NULL argument");
   if (dst->level != src->level) return fail(HE_ELEVEL, "levels %d and %d differ", dst->level, src->level);
   HIPC(launch_copy(src->d, dst->d, (long long)ct_words(c, src->level), c->st));

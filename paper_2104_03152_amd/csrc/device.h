@@ -306,3 +306,13 @@ hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const 
 // Montgomery form of plaintext rows
 hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
                           const PrimeDev* primes, hipStream_t st);
+
+// Job descriptors travel by value in the kernarg segment, which holds at
+// most 4 KiB per launch together with the other arguments (a table pointer,
+// the NttTables block and a few scalars).
+constexpr size_t kKernargBudget = 4096 - sizeof(NttTables) - 64;
+static_assert(sizeof(NttJob) <= kKernargBudget, "NttJob exceeds the kernel-argument budget");
+static_assert(sizeof(KsJob) <= kKernargBudget, "KsJob exceeds the kernel-argument budget");
+static_assert(sizeof(HoistMac) <= kKernargBudget, "HoistMac exceeds the kernel-argument budget");
+static_assert(sizeof(HoistInner) <= kKernargBudget, "HoistInner exceeds the kernel-argument budget");
+static_assert(sizeof(InnerJob) <= kKernargBudget, "InnerJob exceeds the kernel-argument budget");

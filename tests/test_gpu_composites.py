@@ -100,8 +100,29 @@ def test_pack_and_sum_bit_exact(deep):
     P.ct_equal(P.H.he_sum_slots(P.g, pairs[0][0], 48), P.o.sum_slots(pairs[0][1], 48), "sum48")
 
 
+def cnn_plans(H, g, x, d):
+    """The section 5 network's plaintext operands, prepared (and each plan
+    applied once) on the input x."""
+    s = I.CNN_SHAPE
+    conv = [H.he_conv_plan(g, x, d["conv_k"][c], s["windows"], d["conv_b"][c]) for c in range(s["channels"])]
+    s1 = H.he_square(g, H.he_pack(g, H.he_plan_apply_many(g, conv, x), s["windows"]))
+    fc1 = H.he_matmul_plan(g, s1, d["w1"], d["b1"])
+    s2 = H.he_square(g, H.he_plan_apply(g, fc1, s1))
+    fc2 = H.he_matmul_plan(g, s2, d["w2"], d["b2"])
+    H.he_plan_apply(g, fc2, s2)
+    return conv, fc1, fc2
+
+
+def cnn_step(H, g, plans, x):
+    conv, fc1, fc2 = plans
+    p = H.he_pack(g, H.he_plan_apply_many(g, conv, x), I.CNN_SHAPE["windows"])
+    h = H.he_plan_apply(g, fc1, H.he_square(g, p))
+    return H.he_plan_apply(g, fc2, H.he_square(g, h))
+
+
 def run_cnn_gpu(H, g, x, d):
-    """The section 5 network through the C ABI (plans built from x)."""
+    """The section 5 network through the C ABI (one-shot calls, plans built
+    from x inside them)."""
     s = I.CNN_SHAPE
     plans = [H.he_conv_plan(g, x, d["conv_k"][c], s["windows"], d["conv_b"][c])
              for c in range(s["channels"])]
@@ -129,30 +150,41 @@ def test_cnn_bit_exact_and_logits():
     P.ct_equal(gy, oy, "cnn output")
     logits = P.H.he_decode(P.g, P.H.he_decrypt(P.g, gy), 10)
     assert np.abs(logits - cnn_fp64(d)).max() < 1e-3
+    # the same step with prepared plans, eager and replayed from a captured
+    # graph (input: a copy of x), every result against the oracle
+    H, g = P.H, P.g
+    plans = cnn_plans(H, g, gx, d)
+    P.ct_equal(cnn_step(H, g, plans, gx), oy, "cnn step with plans")
+    xin = H.he_drop_to(g, gx, P.o.L - 1)
+    say("cnn graph capture")
+    H.he_graph_begin(g)
+    out = cnn_step(H, g, plans, xin)
+    graph = H.he_graph_end(g)
+    for rep in range(3):
+        H.he_graph_launch(g, graph)
+        H.he_sync(g)
+        P.ct_equal(out, oy, "graph replay %d" % rep)
+        # eager work between the replays
+        P.ct_equal(cnn_step(H, g, plans, gx), oy, "eager step after replay %d" % rep)
+    graph.free()
 
 
-def test_matmul_n16384_decrypts():
-    # the hoisted replication and product at N = 16384 (their kernels use a
-    # different workgroup shape and LDS plan than at N = 8192): decrypted
-    # result against plaintext arithmetic; bit-exact parity of the same
-    # kernels is covered at N = 4096 and 8192
-    from tests.gpu_common import hip
-    H = hip()
+def test_matmul_n16384_bit_exact():
+    # the hoisted replication and product at N = 16384, whose kernels use a
+    # different workgroup shape and LDS plan than at N = 8192, against the
+    # oracle bit for bit, and the decrypted result against plaintext
     n_in, n_out = 256, 8
     half = 8192
-    g = H.he_ctx_create(14, [60, 40, 40, 60], 2.0 ** 40, 17, auto_rescale=True, stream=None)
-    H.he_keygen(g, [])
-    for st in sorted(set(I.replication_steps(n_in, half) + list(range(1, n_in)))):
-        H.he_keygen_galois(g, st, -1)
+    steps = sorted(set(I.replication_steps(n_in, half)) | set(range(1, n_in)))
+    P = Pair(14, [60, 40, 40, 60], 2.0 ** 40, 17, steps=steps, auto_rescale=True)
     rng = np.random.default_rng(16384)
     W = rng.normal(0, 0.1, (n_in, n_out))
     b = rng.normal(0, 0.1, n_out)
     x = rng.uniform(-1, 1, n_in)
+    gx, ox = _enc(P, x, 3, 2)
     say("matmul n16384")
-    gx = H.he_encrypt(g, H.he_encode(g, x, 2.0 ** 40, g.L - 1), 3, False)
-    gy = H.he_enc_matmul(g, gx, W, b)
-    dec = H.he_decode(g, H.he_decrypt(g, gy), half)
+    gy, oy = P.H.he_enc_matmul(P.g, gx, W, b), P.o.matmul(ox, W, b)
+    P.ct_equal(gy, oy, "matmul n16384")
+    dec = P.H.he_decode(P.g, P.H.he_decrypt(P.g, gy), half)
     assert np.abs(dec[:n_out] - (x @ W + b)).max() < 1e-6
     assert np.abs(dec[n_out:]).max() < 1e-6
-    del gx, gy
-    g.close()

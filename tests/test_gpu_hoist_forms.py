@@ -43,7 +43,7 @@ def _product(H, wgs, log_n, n_in, n_out):
     return out
 
 
-@pytest.mark.parametrize("log_n,n_in,n_out", [(12, 256, 64), (13, 300, 1), (13, 64, 10)])
+@pytest.mark.parametrize("log_n,n_in,n_out", [(12, 256, 64), (13, 300, 1), (13, 64, 10), (14, 256, 8)])
 def test_forms_equal(log_n, n_in, n_out):
     H = hip()
     say("hoist forms", log_n, n_in, n_out)
