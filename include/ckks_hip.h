@@ -162,6 +162,23 @@ he_status he_mul_plain(he_ctx* ctx, const he_ct* a, const he_pt* p, he_ct** out)
 he_status he_mul_relin(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct** out);
 /* he_mul_relin(a, a) */
 he_status he_square(he_ctx* ctx, const he_ct* a, he_ct** out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): he_mul_relin
+ * writing into the caller's ciphertext `out`, which must belong to ctx and
+ * already be at the result's level (min(level a, level b), minus one with
+ * auto_rescale).  Every intermediate lives in a fixed device array of
+ * HE_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends), not in the
+ * context's allocator; the call makes no device allocation.  Its result is
+ * bit-identical to he_mul_relin's.  The array is shared by every call on
+ * that GPU and keeps the last call's contents (nothing in it needs to start
+ * at zero): calls on one GPU whose streams overlap race, so serialise them
+ * (one stream, or synchronise between them).  HE_ERANGE when the call would
+ * need more scratch than the maximum (at N = 16384: more than 10 limbs);
+ * HE_ELEVEL when `out` is not at the result's level; HE_EINVAL for handles
+ * of another context. */
+#define HE_NOALLOC_SCRATCH_BYTES (48u * 1024u * 1024u)
+he_status he_mul_relin_noalloc(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out);
 /* round(c / q_l) onto limbs 0..l-1; scale / q_l.  HE_ELEVEL at level 0. */
 he_status he_rescale(he_ctx* ctx, const he_ct* a, he_ct** out);
 /* drop limbs down to `level` (exact) */

@@ -67,6 +67,7 @@ _SIGS = {
     "he_polyval": (C.c_int32, [_vp, _vp, _dp, C.c_size_t, _pvp]),
     "he_mul_relin": (C.c_int32, [_vp, _vp, _vp, _pvp]),
     "he_square": (C.c_int32, [_vp, _vp, _pvp]),
+    "he_mul_relin_noalloc": (C.c_int32, [_vp, _vp, _vp, _vp]),
     "he_rescale": (C.c_int32, [_vp, _vp, _pvp]),
     "he_drop_to": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
     "he_rotate": (C.c_int32, [_vp, _vp, C.c_int32, _pvp]),
@@ -468,6 +469,12 @@ def he_graph_launch(ctx, g):
 
 def he_ct_copy(ctx, dst, src):
     _chk(lib().he_ct_copy(ctx.ptr, dst.ptr, src.ptr), "he_ct_copy")
+
+
+def he_mul_relin_noalloc(ctx, a, b, out):
+    """he_mul_relin into the existing ciphertext `out` (at the result's level),
+    every intermediate in the library's fixed device scratch."""
+    _chk(lib().he_mul_relin_noalloc(ctx.ptr, a.ptr, b.ptr, out.ptr), "he_mul_relin_noalloc")
 
 
 def he_mul_relin_many(ctx, a, b):

@@ -203,6 +203,16 @@ struct he_ctx {
   // divide-and-round constants for divisor prime s and target prime t:
   // (q_s mod q_t)^-1, its Shoup companion, and (q_s - 1)/2 mod q_t
   std::vector<u64> rd_inv, rd_inv_sh, rd_hq;
+  // this device's fixed no-allocation scratch, and while a no-allocation
+  // call runs, the bump arena carved from it (every intermediate of the
+  // call comes from there instead of the pool)
+  u64* scratch = nullptr;
+  size_t scratch_words = 0;
+  struct Arena {
+    u64* base;
+    size_t cap, used;  // words
+  };
+  Arena* arena = nullptr;
 };
 
 struct he_ct {
@@ -264,7 +274,7 @@ struct Prof {
   bool on;
   double units, bytes;
   Prof(he_ctx* c_, const char* f, double units_ = 0, double bytes_ = 0)
-      : c(c_), fam(f), on(c_->prof && !c_->capturing), units(units_), bytes(bytes_) {
+      : c(c_), fam(f), on(c_->prof && !c_->capturing && !c_->arena), units(units_), bytes(bytes_) {
     if (on) {
       (void)hipEventCreate(&a);
       (void)hipEventCreate(&b);
@@ -291,10 +301,32 @@ struct DBuf {
   }
 };
 
+// Device memory for one intermediate: from the pool, or (inside a
+// no-allocation call) the next 256-byte-aligned slice of the scratch arena.
+// Arena slices are never in the pool's table, so handing one to pool.put
+// (DBuf, he_ct_free) does nothing.
+static u64* ctx_alloc(he_ctx* c, size_t words) {
+  if (c->arena) {
+    he_ctx::Arena& a = *c->arena;
+    const size_t w = (words + 31) & ~(size_t)31;
+    if (w > a.cap - a.used) return nullptr;
+    u64* p = a.base + a.used;
+    a.used += w;
+    return p;
+  }
+  return (u64*)c->pool.get(words * sizeof(u64));
+}
+static he_status alloc_failed(he_ctx* c, const char* what, size_t words) {
+  if (c->arena)
+    return fail(HE_ERANGE, "%s of %zu bytes exceeds the %u-byte no-allocation scratch", what,
+                words * sizeof(u64), HE_NOALLOC_SCRATCH_BYTES);
+  return fail(HE_EOOM, "%s of %zu bytes failed", what, words * sizeof(u64));
+}
+
 he_status dalloc(he_ctx* c, DBuf& b, size_t words) {
   b.c = c;
-  b.p = (u64*)c->pool.get(words * sizeof(u64));
-  if (!b.p) return fail(HE_EOOM, "device allocation of %zu bytes failed", words * sizeof(u64));
+  b.p = ctx_alloc(c, words);
+  if (!b.p) return alloc_failed(c, "device allocation", words);
   return HE_OK;
 }
 
@@ -302,14 +334,14 @@ size_t ct_words(const he_ctx* c, int level) { return 2 * (size_t)(level + 1) * c
 size_t pt_words(const he_ctx* c, int level) { return (size_t)(level + 1) * c->n; }
 
 he_status new_ct(he_ctx* c, int level, double scale, he_ct** out) {
-  u64* d = (u64*)c->pool.get(ct_words(c, level) * sizeof(u64));
-  if (!d) return fail(HE_EOOM, "ciphertext allocation failed");
+  u64* d = ctx_alloc(c, ct_words(c, level));
+  if (!d) return alloc_failed(c, "ciphertext allocation", ct_words(c, level));
   *out = new he_ct{c, level, scale, d};
   return HE_OK;
 }
 he_status new_pt(he_ctx* c, int level, double scale, he_pt** out) {
-  u64* d = (u64*)c->pool.get(pt_words(c, level) * sizeof(u64));
-  if (!d) return fail(HE_EOOM, "plaintext allocation failed");
+  u64* d = ctx_alloc(c, pt_words(c, level));
+  if (!d) return alloc_failed(c, "plaintext allocation", pt_words(c, level));
   *out = new he_pt{c, level, scale, d};
   return HE_OK;
 }
@@ -1012,6 +1044,13 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
     c->own_stream = true;
   }
   c->pool.st = c->st;
+  // this device's no-allocation scratch (a fixed array; looked up once per
+  // device, with the device current)
+  if (noalloc_scratch(c->device, &c->scratch, &c->scratch_words) != hipSuccess) {
+    c->scratch = nullptr;
+    c->scratch_words = 0;
+  }
+  c->scratch_words /= sizeof(u64);
   // per-prime constants and twiddles
   const int np = (int)q.size();
   std::vector<PrimeDev> hp(np);
@@ -1503,6 +1542,53 @@ he_status he_mul_relin(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
 }
 
 he_status he_square(he_ctx* c, const he_ct* a, he_ct** out) { return he_mul_relin(c, a, a, out); }
+
+// Scratch words he_mul_relin needs at operand levels la, lb: every
+// intermediate of the path (level alignment copy, tensor, key switch in
+// either form, rescale) allocated once, none reused.
+static size_t noalloc_mul_relin_words(const he_ctx* c, int la, int lb) {
+  const size_t n = c->n, Lp = (size_t)std::min(la, lb) + 1, nm = Lp + 1;
+  size_t w = 0;
+  if (la != lb) w += 2 * Lp;                                   // aligned copy
+  w += 2 * Lp + Lp;                                            // d0, d1 and d2
+  const size_t fused = Lp + Lp * Lp + Lp * nm + 2 + 4 * Lp;    // t1 t2 ext t3 t4 t5
+  const size_t plain = Lp + Lp * nm + 2 * nm + 2;              // coef ext u ucoef
+  w += std::max(fused, plain);
+  if (c->auto_rescale) w += 2 * (Lp - 1) + std::max<size_t>(2 + 2 * (Lp - 1), 2);
+  return w * n;
+}
+
+he_status he_mul_relin_noalloc(he_ctx* c, const he_ct* a, const he_ct* b, he_ct* out) {
+  TRY(own(c, a));
+  TRY(own(c, b));
+  TRY(own(c, out));
+  if (!c || !a || !b || !out) return fail(HE_EINVAL, "NULL argument");
+  if (c->arena) return fail(HE_EINVAL, "a no-allocation call is already running on this context");
+  if (!c->scratch) return fail(HE_EHIP, "no-allocation scratch unavailable on device %d", c->device);
+  if (!c->have_keys) return fail(HE_ENOKEY, "no relinearisation key");
+  const int l = std::min(a->level, b->level);
+  if (c->auto_rescale && l < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  const int lo = c->auto_rescale ? l - 1 : l;
+  if (out->level != lo) return fail(HE_ELEVEL, "output ciphertext at level %d, the result is at level %d", out->level, lo);
+  const size_t need = noalloc_mul_relin_words(c, a->level, b->level);
+  if (need > c->scratch_words)
+    return fail(HE_ERANGE, "the product at level %d needs %zu bytes of scratch, more than the %u-byte maximum", l,
+                need * sizeof(u64), HE_NOALLOC_SCRATCH_BYTES);
+  he_ctx::Arena arena{c->scratch, c->scratch_words, 0};
+  c->arena = &arena;
+  he_ct* r = nullptr;
+  he_ct* f = nullptr;
+  he_status s = mul_relin_raw(c, a, b, &r);
+  if (s == HE_OK) s = maybe_rescale(c, r, &f);  // frees r when it rescales
+  if (s == HE_OK) {
+    hipError_t e = launch_copy(f->d, out->d, (long long)ct_words(c, lo), c->st);
+    if (e != hipSuccess) s = fail(HE_EHIP, "copy: %s", hipGetErrorString(e));
+    else out->scale = f->scale;
+  }
+  he_ct_free(f);  // host handle only: arena memory is not pooled
+  c->arena = nullptr;
+  return s;
+}
 
 he_status he_drop_to(he_ctx* c, const he_ct* a, int32_t level, he_ct** out) {
   TRY(own(c, a));

@@ -307,6 +307,11 @@ hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const 
 hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
                           const PrimeDev* primes, hipStream_t st);
 
+// Fixed device scratch of the no-allocation entry point: the device address
+// of this device's copy of the array (looked up once per device, with that
+// device current) and its size in bytes.
+hipError_t noalloc_scratch(int device, u64** ptr, size_t* bytes);
+
 // Job descriptors travel by value in the kernarg segment, which holds at
 // most 4 KiB per launch together with the other arguments (a table pointer,
 // the NttTables block and a few scalars).

@@ -3,7 +3,33 @@
 //
 // All polynomials are limb-major [poly][limb][N] u64 rows; a thread owns one
 // coefficient of one row, so every access is a coalesced 8-byte word.
+#include <mutex>
+
+#include "../../include/ckks_hip.h"
 #include "device.h"
+
+// The no-allocation entry point's scratch: every intermediate of one call
+// lives here.  Each device holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress gives
+// for that device (the array's name is a host-side stand-in).
+static __device__ __align__(256) u64 scratch[HE_NOALLOC_SCRATCH_BYTES / sizeof(u64)];
+
+hipError_t noalloc_scratch(int device, u64** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static u64* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<u64*>(p);
+  }
+  *ptr = addr[device];
+  *bytes = HE_NOALLOC_SCRATCH_BYTES;
+  return hipSuccess;
+}
 
 namespace {
 
