@@ -104,19 +104,155 @@ def cpu_baseline(params, d, budget_s):
     return n / dt, n, dt, out
 
 
+def small_ops_table(H, I, torch, runs=1000, oracle_runs=5):
+    """The N=4096 operation set (three primes 40, 20 | 40 bits, scale 2^20,
+    secret-key encryption, x, y, p uniform in [-1, 1]^2048): per operation
+    the GPU latency p50/p99 over `runs` synchronised calls, the oracle's time
+    on this host (one thread, median), the largest error of the decrypted
+    GPU result against plaintext arithmetic beside its tolerance, and whether
+    the GPU ciphertext equals the oracle's bit for bit."""
+    from oracle import oracle as O
+    p = I.SMALL
+    steps = [1 << t for t in range(11)]
+    g = H.he_ctx_create(p["log_n"], p["bits"], p["scale"], p["seed"], auto_rescale=True)
+    H.he_keygen(g, steps)
+    o = O.Oracle(p["log_n"], p["bits"], p["scale"], p["seed"])
+    o.keygen()
+    for st in steps:
+        o.galois_keygen(st)
+    x, y, pv = I.small_vectors()
+    gx = H.he_encrypt(g, H.he_encode(g, x, p["scale"], 1), 0, True)
+    gy = H.he_encrypt(g, H.he_encode(g, y, p["scale"], 1), 1, True)
+    gp = H.he_encode(g, pv, p["scale"], 1)
+    ox = o.encrypt(o.encode(x, p["scale"], 1), 0, True)
+    oy = o.encrypt(o.encode(y, p["scale"], 1), 1, True)
+    op = o.encode(pv, p["scale"], 1)
+    ops = {
+        "add": (lambda: H.he_add(g, gx, gy), lambda: o.add(ox, oy), x + y, 1e-2),
+        "mul_plain+rescale": (lambda: H.he_mul_plain(g, gx, gp), lambda: o.rescale(o.mul_plain(ox, op)),
+                              x * pv, 1e-2),
+        "mul_relin+rescale": (lambda: H.he_mul_relin(g, gx, gy), lambda: o.rescale(o.mul_relin(ox, oy)),
+                              x * y, 1e-2),
+        "rotate_1": (lambda: H.he_rotate(g, gx, 1), lambda: o.rotate(ox, 1), np.roll(x, -1), 2e-2),
+        "sum_slots_2048": (lambda: H.he_sum_slots(g, gx, 2048), lambda: o.sum_slots(ox, 2048),
+                           np.array([x.sum()]), 1.0),
+    }
+    table = {}
+    for name, (gpu, orc, want, tol) in ops.items():
+        r = gpu()
+        H.he_sync(g)
+        lat = []
+        for _ in range(runs):
+            t = time.perf_counter()
+            r = gpu()
+            H.he_sync(g)
+            lat.append((time.perf_counter() - t) * 1e3)
+        ot = []
+        for _ in range(oracle_runs):
+            t = time.perf_counter()
+            ro = orc()
+            ot.append((time.perf_counter() - t) * 1e3)
+        dec = H.he_decode(g, H.he_decrypt(g, r), len(want))
+        table[name] = {"gpu_p50_ms": float(np.percentile(lat, 50)), "gpu_p99_ms": float(np.percentile(lat, 99)),
+                       "gpu_runs": runs, "oracle_ms": float(np.median(ot)), "oracle_runs": oracle_runs,
+                       "max_abs_err": float(np.abs(dec - want).max()), "tolerance": tol,
+                       "bit_exact_vs_oracle": bool(np.array_equal(H.he_ct_export(g, r), ro.data()))}
+        del r
+    del gx, gy, gp
+    g.close()
+    return {"params": "N=4096, primes (40, 20 | 40) bits, scale 2^20, secret-key encryption, 2048 slots",
+            "ops": table}
+
+
+def host_info():
+    """The host the oracle runs on: CPU model, logical CPUs, and the CPUs this
+    process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_parallel_worker(n_workers, budget_s):
+    """(A child process without torch.)  The oracle's keys generated once,
+    then n_workers forked processes each run full encrypted inferences of
+    the same network for budget_s seconds: host throughput with every
+    worker busy.  Prints one JSON line."""
+    import multiprocessing as mp
+    from oracle import oracle as O
+    from paper_2104_03152_amd import inputs as I
+    params, d = I.CNN, I.cnn_inputs()
+    o = O.Oracle(params["log_n"], params["bits"], params["scale"], params["seed"])
+    o.keygen()
+    for st, lv in sorted(I.cnn_rotation_steps().items()):
+        o.galois_keygen(st, lv)
+    ct = o.encrypt(o.encode(O.im2col(d["img"], 7, 3), o.scale, o.L - 1), 0)
+    ref = o.cnn(ct, d["conv_k"], d["conv_b"], d["w1"], d["b1"], d["w2"], d["b2"]).data()
+    q = mp.get_context("fork").Queue()
+
+    def work():
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            y = o.cnn(ct, d["conv_k"], d["conv_b"], d["w1"], d["b1"], d["w2"], d["b2"])
+            n += 1
+        q.put((n, bool(np.array_equal(y.data(), ref))))
+
+    procs = [mp.get_context("fork").Process(target=work) for _ in range(n_workers)]
+    t0 = time.perf_counter()
+    for pr in procs:
+        pr.start()
+    res = [q.get() for _ in procs]
+    for pr in procs:
+        pr.join()
+    dt = time.perf_counter() - t0
+    n = sum(r[0] for r in res)
+    print(json.dumps({"inferences": n, "seconds": dt, "workers": n_workers,
+                      "all_equal": all(r[1] for r in res)}), flush=True)
+
+
+def cpu_baseline_parallel(budget_s):
+    """The oracle on every usable host CPU (at most 16, the GPU's share of
+    the host): independent inferences in parallel processes."""
+    import subprocess
+    info = host_info()
+    workers = max(1, min(16, info["usable_cpus"]))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-workers", str(workers),
+                        "--cpu-budget", str(budget_s)], capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    rec["value"] = rec["inferences"] / rec["seconds"]
+    rec["unit"] = "inferences/s"
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--latency-runs", type=int, default=200)
+    ap.add_argument("--latency-runs", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=8.0)
     ap.add_argument("--no-extra-bench", action="store_true",
                     help="skip the N=16384 NTT and key-switch benches (profiling runs)")
+    ap.add_argument("--probe", action="store_true",
+                    help="only measure the issue rates and copy bandwidth the roofline peaks use")
+    ap.add_argument("--serving-requests", type=int, default=0,
+                    help="requests per serving rate (default: enough for about 2 s per rate, at least 128)")
+    ap.add_argument("--cpu-workers", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 2 GiB buffer three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.cpu_workers:
+        cpu_parallel_worker(args.cpu_workers, args.cpu_budget)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(requests/ciphertexts would shard across GPUs with no exchange)", file=sys.stderr)
@@ -128,6 +264,9 @@ def main():
     from paper_2104_03152_amd import inputs as I
 
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.probe:
+        print(json.dumps(probe(torch)), flush=True)
+        return
     if args.copy_calibration:
         # a plain device-to-device copy of known size: 2 GiB read, 2 GiB written
         src = torch.empty(1 << 28, dtype=torch.int64, device="cuda").random_()
@@ -248,7 +387,7 @@ def main():
         log("uneven batching: 1024 ops over three ring degrees and seven levels")
         uneven = uneven_bench(H, I)
         log("serving: Poisson arrivals, CNN and logistic-regression requests")
-        serving = serving_bench(H, I, d)
+        serving = serving_bench(H, I, d, n_requests=args.serving_requests)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -257,7 +396,12 @@ def main():
         cpu = {"value": rate, "unit": "inferences/s", "cores": 1, "kind": "oracle",
                "sample": "%d full encrypted inference(s) of the same network, %.1f s, single "
                          "thread, keys generated outside the timing" % (n_inf, cdt),
-               "bit_exact_vs_gpu": bool(np.array_equal(oy.data(), ref))}
+               "bit_exact_vs_gpu": bool(np.array_equal(oy.data(), ref)),
+               "host": host_info()}
+        log("cpu baseline, every usable host CPU")
+        cpu["parallel"] = cpu_baseline_parallel(args.cpu_budget)
+        log("cpu baseline: N=4096 operation set, GPU beside the oracle")
+        cpu["small_ops"] = small_ops_table(H, I, torch)
 
     res = {
         "metric": "encrypted-CNN inferences/s (N=8192, batch 1)",
@@ -283,6 +427,7 @@ def main():
         "host_enqueue_ms": enqueue_ms,
         "kernel_profile": prof,
         "roofline": roof,
+        "step_hbm": step_traffic(prof, g.n),
         "graph_replay": graph_res,
         "kernel_bench": kbench,
         "keyswitch_bench": ksbench,
@@ -313,10 +458,41 @@ NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "hoisted_co
                 "hoisted_replication")
 
 
+def cnn_step_algorithmic_bytes(n):
+    """HBM bytes one inference must move at least: every key switch reads its
+    key once at the level of use (2 Lp (Lp + 1) limbs; a key shared by the
+    four conv channels once), every plaintext operand once, the input and
+    output ciphertexts once; 8N bytes per limb."""
+    key = lambda lp: 2 * lp * (lp + 1)
+    uses = [(6, 6),              # conv: six rotation steps, one key each for the 4 channels
+            (3, 5), (1, 5),      # packing rotations, first relinearisation
+            (15 + 255, 4),       # FC1: replication and the 255 diagonal rotations
+            (1, 3),              # second relinearisation
+            (63 + 63, 2)]        # FC2: replication and the 63 diagonal rotations
+    limbs = sum(c * key(lp) for c, lp in uses)
+    limbs += 4 * 7 + 4 * 6 + 4 * 6   # conv kernels, channel masks, conv biases
+    limbs += 256 * 4 + 3 + 64 * 2 + 1  # FC1, FC2 diagonals and biases
+    limbs += 2 * 7 + 2 * 1           # input and output ciphertexts
+    return 8 * n * limbs
+
+
+def step_traffic(prof, n):
+    """Measured HBM bytes per step (PMC counters of every profiled family
+    times its launches per step) beside the algorithmic bytes."""
+    alg = cnn_step_algorithmic_bytes(n)
+    fams = {f: pmc_traffic(f) for f in prof}
+    have = {f: v for f, v in fams.items() if v is not None}
+    meas = sum(v * prof[f]["launches_per_step"] for f, v in have.items()) if have else None
+    return {"algorithmic_bytes": alg, "counter_bytes_profiled_families": meas,
+            "families_with_counters": sorted(have),
+            "ratio": (meas / alg) if meas else None}
+
+
 def roofline_entry(fam, p, n):
     t = p["avg_launch_us"] * 1e-6
     hbm = p["bytes_per_launch"] / t / 1e9
     traffic = pmc_traffic(fam)
+    ratio = traffic / p["bytes_per_launch"] if traffic else None
     if fam in NTT_FAMILIES:
         bfly = p["units_per_launch"] * (n // 2) * (n.bit_length() - 1)
         ach = bfly / t / 1e9
@@ -327,8 +503,9 @@ def roofline_entry(fam, p, n):
                 "avg_launch_us": p["avg_launch_us"], "units_per_launch": p["units_per_launch"],
                 "algorithmic_bytes_per_launch": p["bytes_per_launch"]}
     return {"bound": "hbm", "family": fam, "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": hbm / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_us": p["avg_launch_us"],
-            "algorithmic_bytes_per_launch": p["bytes_per_launch"]}
+            "frac": hbm / HBM_PEAK_GBS, "traffic": traffic, "traffic_over_algorithmic": ratio,
+            "avg_launch_us": p["avg_launch_us"], "algorithmic_bytes_per_launch": p["bytes_per_launch"],
+            "algorithmic": "the keys of the launch's rotations and their shared ModUp digits, read once"}
 
 
 def pmc_traffic(fam):
@@ -375,6 +552,49 @@ def graph_replay(H, g, net, x, width, ref, steps):
     graph.free()
     return {"ms_per_step": dt * 1e3 / steps, "inferences_per_s": steps / dt,
             "host_launch_ms": enq * 1e3 / steps, "bit_exact_vs_eager": exact}
+
+
+def probe(torch, blocks=2048, iters=4096, reps=3):
+    """Issue rates of the instructions the NTT butterflies are built from,
+    and the bandwidth of a plain device copy, on this GPU (the measured
+    counterparts of the published peaks)."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2104_03152_amd", "libckks_probe.so"))
+    lib.probe_rate.restype = C.c_double
+    lib.probe_rate.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p]
+    lib.probe_copy.restype = C.c_double
+    lib.probe_copy.argtypes = [C.c_void_p, C.c_void_p, C.c_longlong, C.c_int]
+    out = torch.empty(blocks * 256, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    kinds = {0: "v_mad_u64_u32", 1: "v_mul_lo_u32", 2: "v_mul_hi_u32", 3: "v_fma_f64", 4: "v_add_u32"}
+    rates = {}
+    for k, name in kinds.items():
+        best = min(lib.probe_rate(k, blocks, iters, out.data_ptr()) for _ in range(reps))
+        assert best > 0, name
+        r = blocks * 256 * iters * 8 / (best * 1e-3)
+        rates[name] = {"t_per_s": r / 1e12, "frac_of_lane_peak": r / VALU_LANE_OPS}
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").random_()
+    dst = torch.empty_like(src)
+    copies = {}
+    for cb in (1024, 4096, 16384):
+        best = min(lib.probe_copy(src.data_ptr(), dst.data_ptr(), nbytes, cb) for _ in range(reps))
+        copies[str(cb)] = 2 * nbytes / (best * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    t = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        t.append(a.elapsed_time(b))
+    return {"probe": "issue rates (one instruction kind, 8 independent chains per lane, %d x 256 lanes)"
+                     % blocks,
+            "lane_peak_t_per_s": VALU_LANE_OPS / 1e12, "rates": rates,
+            "copy_gbs_by_blocks": copies, "torch_copy_gbs": 2 * nbytes / (min(t) * 1e-3) / 1e9,
+            "hbm_peak_gbs": HBM_PEAK_GBS, "copy_bytes": nbytes}
 
 
 def window_marker(torch):
@@ -483,7 +703,7 @@ def op_sweep(H, I, shapes=(256, 1024, 4096, 8192, 16384), reps=10):
 
 
 def serving_bench(H, I, d, qps_list=(10, 20, 50, 100, 200, 500, 1000, 2000), n_clients=8,
-                  budget=8 << 30, seed=5):
+                  budget=8 << 30, seed=5, n_requests=0):
     """Poisson arrivals at each rate, half CNN and half logistic-regression
     requests (N=8192, the CNN's chain; LR feature dimension uniform in
     64..1024, weights and bias N(0, 1), inputs uniform in [-1, 1]); 16
@@ -497,8 +717,15 @@ def serving_bench(H, I, d, qps_list=(10, 20, 50, 100, 200, 500, 1000, 2000), n_c
     setup_s = time.perf_counter() - t0
     out = {"clients": n_clients, "key_bytes_per_client": clients[0].key_bytes,
            "client_setup_s": setup_s, "budget_bytes": budget, "points": []}
+    # warm-up: every client's pool holds the buffers of both request kinds
+    # before either service mode is timed
+    warm = S.make_requests(H, clients, 4 * n_clients * 2, 0, seed, per_client=8)
+    S.serve(H, warm, budget, batched=True)
+    S.reset(warm)
+    S.serve(H, warm, budget, batched=False)
+    del warm
     for qps in qps_list:
-        n = int(min(n_clients * S.REQS_PER_CLIENT, max(24, qps * 0.4)))
+        n = n_requests or int(max(128, min(1000, 2 * qps)))
         reqs = S.make_requests(H, clients, n, qps, seed + qps)
         lat_b = S.serve(H, reqs, budget, batched=True)
         sb = S.summary(lat_b, reqs)

@@ -9,6 +9,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libckks_hip.so")
+# issue-rate and bandwidth probes (bench.py --probe), outside the library ABI
+PROBE_LIB = os.path.join(HERE, "libckks_probe.so")
+PROBE_SRC = "probe.hip"
 SOURCES = ["ntt.hip", "kernels.hip", "ckks.cpp", "encode.cpp"]
 HEADERS = ["modarith.h", "device.h", "encode.h"]
 
@@ -49,6 +52,10 @@ def build(verbose=False):
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs)
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call([hipcc] + FLAGS + [os.path.join(CSRC, PROBE_SRC), "-o", tmp],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

@@ -608,9 +608,18 @@ static he_status moddown_fused(he_ctx* c, KsJob& K, const Addend& add, u64* out)
   K.add_gather = add.gals ? 1 : 0;
   K.add2 = add.p2;
   K.a2a = add.a2a;
-  // per item: digits Lp*nm and key 2*Lp*nm limbs read, 2*Lp written, addends read
+  // algorithmic bytes: each distinct key 2*Lp*nm limbs (read once however
+  // many items share it); per item the digits Lp*nm limbs, addends read and
+  // 2*Lp limbs written
   const double adds = (add.p ? (add.even_only ? 1.0 : 2.0) : 0.0) + (add.p2 ? 2.0 : 0.0);
-  Prof pr(c, "moddown", 2.0 * B * (1 + Lp), 8.0 * n * B * (3.0 * Lp * nm + 2.0 * Lp + adds * Lp));
+  int distinct = 0;
+  for (int b = 0; b < B; b++) {
+    bool seen = false;
+    for (int a = 0; a < b; a++) seen |= K.key[a] == K.key[b];
+    distinct += seen ? 0 : 1;
+  }
+  Prof pr(c, "moddown", 2.0 * B * (1 + Lp),
+          8.0 * n * (2.0 * distinct * Lp * nm + B * (Lp * nm + 2.0 * Lp + adds * Lp)));
   hipError_t e = launch_ks_special_blocks(c->log_n, K, c->d_primes, c->tabs, c->st);
   if (e == hipSuccess) e = launch_ks_moddown_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
   if (e == hipSuccess) e = launch_ks_moddown_blocks(c->log_n, K, c->d_primes, c->tabs, c->st);
@@ -2258,8 +2267,10 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       I.t_begin = 0;
       I.t_end = nm;
       I.special_prime = c->L;
-      // keys of R items + the shared digits once + R outputs
-      Prof pr(c, "hoisted_inner", (double)R, 8.0 * n * (2.0 * R * Lp * nm + Lp * nm + 2.0 * R * nm));
+      // algorithmic bytes: the keys of the R items and the shared digits
+      // once (the u written for the ModDown is an intermediate of this
+      // design, not of the key switch)
+      Prof pr(c, "hoisted_inner", (double)R, 8.0 * n * (2.0 * R * Lp * nm + Lp * nm));
       hipError_t e = launch_inner_hoisted(c->log_n, I, c->d_primes, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted inner: %s", hipGetErrorString(e));
     }
