@@ -520,7 +520,7 @@ def pmc_traffic(fam):
         rec = json.load(f)
     src = os.path.join(ROOT, "paper_2104_03152_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("ntt.hip", "kernels.hip", "modarith.h", "device.h"):
+    for name in ("ntt.hip", "kernels.hip", "modarith.h", "butterfly.h", "device.h"):
         with open(os.path.join(src, name), "rb") as f:
             h.update(f.read())
     if rec.get("source_sha256") != h.hexdigest():

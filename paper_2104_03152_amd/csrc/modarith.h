@@ -41,7 +41,7 @@ __device__ __forceinline__ U128 mul_wide(u64 a, u64 b) {
 
 // high word of a 64x64 product as a chain of 32x32+64 multiply-adds
 // (v_mad_u64_u32): the partial carries ride in the 64-bit addend.
-__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) {
+__host__ __device__ __forceinline__ u64 mulhi64(u64 a, u64 b) {
   const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
   const u64 t = (u64)a0 * b0;
   const u64 x = (u64)a1 * b0 + (t >> 32);
@@ -81,11 +81,11 @@ __device__ __forceinline__ u64 red64(u64 x, const PrimeDev& P) {
 }
 
 // Shoup: w < q, ws = floor(w 2^64 / q); a < 2^64 -> a w mod q in [0, 2q)
-__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 ws, u64 q) {
+__host__ __device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 ws, u64 q) {
   u64 qh = mulhi64(a, ws);
   return a * w - qh * q;
 }
-__device__ __forceinline__ u64 shoup(u64 a, u64 w, u64 ws, u64 q) {
+__host__ __device__ __forceinline__ u64 shoup(u64 a, u64 w, u64 ws, u64 q) {
   u64 r = shoup_lazy(a, w, ws, q);
   return r >= q ? r - q : r;
 }

@@ -53,7 +53,7 @@ FAMILIES = [
 
 def source_sha():
     h = hashlib.sha256()
-    for name in ("ntt.hip", "kernels.hip", "modarith.h", "device.h"):
+    for name in ("ntt.hip", "kernels.hip", "modarith.h", "butterfly.h", "device.h"):
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
