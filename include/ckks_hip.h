@@ -253,6 +253,23 @@ he_status he_mul_relin_many(he_ctx* ctx, const he_ct* const* a, const he_ct* con
 he_status he_rotate_many(he_ctx* ctx, const he_ct* const* a, const int32_t* steps,
                          size_t n, he_ct** out);
 
+/* The same batches across contexts: a server holding one context (and key
+ * set, section 2.1) per client runs the key switches of several clients'
+ * ciphertexts in one set of launches, each item with the keys of its own
+ * context.  a[i] (and b[i], of the same context) may belong to any context
+ * with the same ring degree, primes and auto_rescale as `run`, on the same
+ * device; out[i] belongs to a[i]'s context and equals, bit for bit, what
+ * that context's own he_mul_relin / he_rotate gives.  The batch runs on
+ * run's stream after the work already queued on every involved context's
+ * stream, and each of those streams waits for the batch before its later
+ * work (HIP events), so no synchronisation is needed around the call.
+ * HE_EINVAL for mismatched contexts, NULL items, or an open graph capture on
+ * any involved context. */
+he_status he_mul_relin_across(he_ctx* run, const he_ct* const* a, const he_ct* const* b,
+                              size_t n, he_ct** out);
+he_status he_rotate_across(he_ctx* run, const he_ct* const* a, const int32_t* steps,
+                           size_t n, he_ct** out);
+
 /* ---- composites (sections 3.1, 3.2; appendix A.3, A.4) ---- */
 
 /* x <- x + rot(x, 2^j), j < ceil(log2 n): slot 0 gets the sum of slots

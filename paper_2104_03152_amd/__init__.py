@@ -79,6 +79,8 @@ _SIGS = {
     "he_graph_free": (None, [_vp]),
     "he_ct_copy": (C.c_int32, [_vp, _vp, _vp]),
     "he_rotate_many": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
+    "he_mul_relin_across": (C.c_int32, [_vp, _pvp, _pvp, C.c_size_t, _pvp]),
+    "he_rotate_across": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
     "he_sum_slots": (C.c_int32, [_vp, _vp, C.c_uint32, _pvp]),
     "he_enc_conv_im2col": (C.c_int32, [_vp, _vp, _dp, C.c_uint32, C.c_uint32, C.c_double, _pvp]),
     "he_enc_matmul": (C.c_int32, [_vp, _vp, _dp, C.c_uint32, C.c_uint32, _dp, _pvp]),
@@ -499,6 +501,31 @@ def he_rotate_many(ctx, a, steps):
     outs = (C.c_void_p * n)()
     _chk(lib().he_rotate_many(ctx.ptr, pa, _ptr(st, C.c_int32), n, outs), "he_rotate_many")
     return [Ct(ctx, outs[i]) for i in range(n)]
+
+
+def he_mul_relin_across(run, a, b):
+    """he_mul_relin_many over ciphertexts of several compatible contexts, run
+    on `run`'s stream; each result belongs to its input's context."""
+    n = len(a)
+    if len(b) != n:
+        raise ValueError("operand lists differ in length")
+    pa = (C.c_void_p * n)(*[x.ptr for x in a])
+    pb = (C.c_void_p * n)(*[x.ptr for x in b])
+    outs = (C.c_void_p * n)()
+    _chk(lib().he_mul_relin_across(run.ptr, pa, pb, n, outs), "he_mul_relin_across")
+    return [Ct(a[i].ctx, outs[i]) for i in range(n)]
+
+
+def he_rotate_across(run, a, steps):
+    """he_rotate_many over ciphertexts of several compatible contexts."""
+    n = len(a)
+    st = np.ascontiguousarray(steps, dtype=np.int32)
+    if st.size != n:
+        raise ValueError("one step per ciphertext")
+    pa = (C.c_void_p * n)(*[x.ptr for x in a])
+    outs = (C.c_void_p * n)()
+    _chk(lib().he_rotate_across(run.ptr, pa, _ptr(st, C.c_int32), n, outs), "he_rotate_across")
+    return [Ct(a[i].ctx, outs[i]) for i in range(n)]
 
 
 def he_sum_slots(ctx, a, n):

@@ -11,7 +11,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -198,6 +200,7 @@ struct he_ctx {
   EncodeTables enc;
   std::map<std::pair<int, int>, he_pt*> masks;
   bool prof = false;
+  hipEvent_t ev_cross = nullptr;  // orders this stream against another context's (batches across contexts)
   std::vector<ProfRec> prof_recs;
   uint64_t key_epoch = 0;  // bumped whenever a key is (re)generated
   // divide-and-round constants for divisor prime s and target prime t:
@@ -710,13 +713,16 @@ he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const 
 // by steps[b]: the key switch reads tau_g(c1) by gather and adds tau_g(c0)
 // (gathered) in its last kernel; with add_in, also adds the input itself
 // (x + rot(x), the rotate-and-sum step).  out: [B][2][l+1][N].
-he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps, u64* out, bool add_in = false) {
+// key_ctx (nullable): item b's Galois key comes from key_ctx[b] instead of c
+he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps, u64* out, bool add_in = false,
+                       he_ctx* const* key_ctx = nullptr) {
   const int n = c->n, Lp = l + 1;
   const Key* keys[HE_MAX_BATCH];
   u64 gals[HE_MAX_BATCH];
   for (int b = 0; b < B; b++) {
-    auto it = c->gal.find(steps[b]);
-    if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", steps[b]);
+    const auto& gal = key_ctx ? key_ctx[b]->gal : c->gal;
+    auto it = gal.find(steps[b]);
+    if (it == gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", steps[b]);
     if (it->second.ml < l)
       return fail(HE_ENOKEY, "Galois key for step %d cut at level %d, ciphertext at %d", steps[b], it->second.ml, l);
     keys[b] = &it->second;
@@ -1053,6 +1059,11 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
     c->own_stream = true;
   }
   c->pool.st = c->st;
+  if (hipEventCreateWithFlags(&c->ev_cross, hipEventDisableTiming) != hipSuccess) {
+    if (c->own_stream) (void)hipStreamDestroy(c->st);
+    delete c;
+    return fail(HE_EHIP, "event creation failed");
+  }
   // this device's no-allocation scratch (a fixed array; looked up once per
   // device, with the device current)
   if (noalloc_scratch(c->device, &c->scratch, &c->scratch_words) != hipSuccess) {
@@ -1178,6 +1189,7 @@ void he_ctx_destroy(he_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   c->pool.destroy();
+  if (c->ev_cross) (void)hipEventDestroy(c->ev_cross);
   if (c->own_stream) (void)hipStreamDestroy(c->st);
   delete c;
 }
@@ -1813,13 +1825,15 @@ static he_status batch_level(const he_ct* const* a, const he_ct* const* b, size_
   return HE_OK;
 }
 
-he_status he_mul_relin_many(he_ctx* c, const he_ct* const* a, const he_ct* const* b, size_t n, he_ct** out) {
-  TRY(own_all(c, a, n));
-  TRY(own_all(c, b, n));
-  if (!c || !out || (n && (!a || !b))) return fail(HE_EINVAL, "NULL argument");
+// n products at one level run on c (its stream, pool and tables); item i
+// relinearises with the key of a[i]'s context (c itself unless the batch
+// spans contexts); the results are c's, in shared blocks
+static he_status mul_relin_many_impl(he_ctx* c, const he_ct* const* a, const he_ct* const* b, size_t n,
+                                     he_ct** out) {
   for (size_t i = 0; i < n; i++) out[i] = nullptr;
   if (n == 0) return HE_OK;
-  if (!c->have_keys) return fail(HE_ENOKEY, "no relinearisation key");
+  for (size_t i = 0; i < n; i++)
+    if (!a[i] || !a[i]->ctx->have_keys) return fail(HE_ENOKEY, "no relinearisation key");
   int l = 0;
   TRY(batch_level(a, b, n, &l));
   if (c->auto_rescale && l < 1) return fail(HE_ELEVEL, "no level left to rescale");
@@ -1831,7 +1845,7 @@ he_status he_mul_relin_many(he_ctx* c, const he_ct* const* a, const he_ct* const
     for (int k = 0; k < B; k++) {
       A.p[k] = a[i0 + k]->d;
       Bl.p[k] = b[i0 + k]->d;
-      keys[k] = &c->relin;
+      keys[k] = &a[i0 + k]->ctx->relin;
     }
     u64* R = (u64*)c->pool.get((size_t)B * ct_words(c, l) * sizeof(u64));
     if (!R) return fail(HE_EOOM, "batch allocation failed");
@@ -1876,9 +1890,25 @@ he_status he_mul_relin_many(he_ctx* c, const he_ct* const* a, const he_ct* const
   return HE_OK;
 }
 
+he_status he_mul_relin_many(he_ctx* c, const he_ct* const* a, const he_ct* const* b, size_t n, he_ct** out) {
+  TRY(own_all(c, a, n));
+  TRY(own_all(c, b, n));
+  if (!c || !out || (n && (!a || !b))) return fail(HE_EINVAL, "NULL argument");
+  return mul_relin_many_impl(c, a, b, n, out);
+}
+
+static he_status rotate_many_impl(he_ctx* c, const he_ct* const* a, const int32_t* steps, size_t n,
+                                  he_ct** out);
 he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps, size_t n, he_ct** out) {
   TRY(own_all(c, a, n));
   if (!c || !out || (n && (!a || !steps))) return fail(HE_EINVAL, "NULL argument");
+  return rotate_many_impl(c, a, steps, n, out);
+}
+
+// n rotations at one level run on c; item i uses the Galois key of a[i]'s
+// context; the results are c's, in shared blocks
+static he_status rotate_many_impl(he_ctx* c, const he_ct* const* a, const int32_t* steps, size_t n,
+                                  he_ct** out) {
   for (size_t i = 0; i < n; i++) out[i] = nullptr;
   if (n == 0) return HE_OK;
   int l = 0;
@@ -1888,9 +1918,11 @@ he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps,
     const int B = (int)std::min<size_t>(HE_MAX_BATCH, n - i0);
     CtList A{};
     int st[HE_MAX_BATCH];
+    he_ctx* kc[HE_MAX_BATCH];
     for (int k = 0; k < B; k++) {
       A.p[k] = a[i0 + k]->d;
       st[k] = norm_step(c, steps[i0 + k]);
+      kc[k] = a[i0 + k]->ctx;
     }
     DBuf in;
     he_status s = dalloc(c, in, (size_t)B * per);
@@ -1913,19 +1945,21 @@ he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps,
         }
       }
       if (s == HE_OK && nr == B) {
-        s = rotate_multi(c, in.p, B, l, st, O);
+        s = rotate_multi(c, in.p, B, l, st, O, false, kc);
       } else if (s == HE_OK && nr > 0) {
         // pack the rotating items, rotate, scatter back
         DBuf pin, pout;
         s = dalloc(c, pin, (size_t)nr * per);
         if (s == HE_OK) s = dalloc(c, pout, (size_t)nr * per);
         int pst[HE_MAX_BATCH];
+        he_ctx* pkc[HE_MAX_BATCH];
         for (int r = 0; r < nr && s == HE_OK; r++) {
           pst[r] = st[idx[r]];
+          pkc[r] = kc[idx[r]];
           if (launch_copy(in.p + idx[r] * per, pin.p + r * per, (long long)per, c->st) != hipSuccess)
             s = fail(HE_EHIP, "copy failed");
         }
-        if (s == HE_OK) s = rotate_multi(c, pin.p, nr, l, pst, pout.p);
+        if (s == HE_OK) s = rotate_multi(c, pin.p, nr, l, pst, pout.p, false, pkc);
         for (int r = 0; r < nr && s == HE_OK; r++)
           if (launch_copy(pout.p + r * per, O + idx[r] * per, (long long)per, c->st) != hipSuccess)
             s = fail(HE_EHIP, "copy failed");
@@ -1944,6 +1978,75 @@ he_status he_rotate_many(he_ctx* c, const he_ct* const* a, const int32_t* steps,
     split_block(c, O, B, l, sc, out + i0);
   }
   return HE_OK;
+}
+
+// ---------------------------------------------------------------- batches across contexts
+// Contexts whose ciphertexts can share one batched key switch: same ring,
+// primes, rescaling rule and device (each item keeps its own keys).
+static bool same_params(const he_ctx* a, const he_ctx* b) {
+  return a->n == b->n && a->q == b->q && a->auto_rescale == b->auto_rescale && a->device == b->device;
+}
+
+// The batch runs on run's stream after the work already queued on every
+// other involved context's stream (their inputs, and the previous users of
+// the blocks their results take), and each of those streams then waits for
+// the batch before its later work (which may read the results or reuse the
+// inputs' blocks).
+static he_status across_contexts(he_ctx* run, const he_ct* const* a, const he_ct* const* b, size_t n,
+                                 he_ct** out, const std::function<he_status()>& batch) {
+  if (!run || !out || (n && !a)) return fail(HE_EINVAL, "NULL argument");
+  for (size_t i = 0; i < n; i++) out[i] = nullptr;
+  if (run->capturing) return fail(HE_EINVAL, "a batch across contexts cannot be captured");
+  std::vector<he_ctx*> others;
+  for (size_t i = 0; i < n; i++) {
+    if (!a[i] || (b && !b[i])) return fail(HE_EINVAL, "NULL ciphertext at %zu", i);
+    he_ctx* x = a[i]->ctx;
+    if (b && b[i]->ctx != x) return fail(HE_EINVAL, "operands %zu belong to different contexts", i);
+    if (!same_params(run, x)) return fail(HE_EINVAL, "item %zu: its context has other parameters", i);
+    if (x->capturing) return fail(HE_EINVAL, "item %zu: its context is capturing a graph", i);
+    if (x != run && std::find(others.begin(), others.end(), x) == others.end()) others.push_back(x);
+  }
+  for (he_ctx* o : others) {
+    HIPC(hipEventRecord(o->ev_cross, o->st));
+    HIPC(hipStreamWaitEvent(run->st, o->ev_cross, 0));
+  }
+  he_status s = batch();
+  // results of other contexts' items move into their own context's memory
+  for (size_t i = 0; i < n && s == HE_OK; i++) {
+    he_ctx* x = a[i]->ctx;
+    if (x == run) continue;
+    he_ct* r = nullptr;
+    s = new_ct(x, out[i]->level, out[i]->scale, &r);
+    if (s == HE_OK && launch_copy(out[i]->d, r->d, (long long)ct_words(run, r->level), run->st) != hipSuccess) {
+      he_ct_free(r);
+      r = nullptr;
+      s = fail(HE_EHIP, "result copy failed");
+    }
+    if (s == HE_OK) {
+      he_ct_free(out[i]);
+      out[i] = r;
+    }
+  }
+  const hipError_t e = hipEventRecord(run->ev_cross, run->st);
+  for (he_ctx* o : others)
+    if (e == hipSuccess) (void)hipStreamWaitEvent(o->st, run->ev_cross, 0);
+  if (s == HE_OK && e != hipSuccess) s = fail(HE_EHIP, "event record: %s", hipGetErrorString(e));
+  if (s != HE_OK)
+    for (size_t i = 0; i < n; i++) {
+      he_ct_free(out[i]);
+      out[i] = nullptr;
+    }
+  return s;
+}
+
+he_status he_mul_relin_across(he_ctx* run, const he_ct* const* a, const he_ct* const* b, size_t n, he_ct** out) {
+  if (n && !b) return fail(HE_EINVAL, "NULL argument");
+  return across_contexts(run, a, b, n, out, [&]() { return mul_relin_many_impl(run, a, b, n, out); });
+}
+
+he_status he_rotate_across(he_ctx* run, const he_ct* const* a, const int32_t* steps, size_t n, he_ct** out) {
+  if (n && !steps) return fail(HE_EINVAL, "NULL argument");
+  return across_contexts(run, a, nullptr, n, out, [&]() { return rotate_many_impl(run, a, steps, n, out); });
 }
 
 // x <- x + rot(x, stride 2^j), j < ceil(log2 count); each step is one fused

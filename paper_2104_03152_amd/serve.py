@@ -12,11 +12,11 @@ requests of two kinds share one GPU.
   sets of the requests in service fit in a device-memory budget (key sets
   are admitted with their client); the others wait in arrival order.
 - Continuous batching.  Each scheduling round advances every request in
-  service by one stage; requests of one client at the same stage run as one
-  batched call where the library has one (squares: he_mul_relin_many; the
-  rotations of the slot sums: he_rotate_many), so their key switches share
-  launches.  Requests that arrive while others are on the GPU join the next
-  round.
+  service by one stage; requests at the same stage run as one batched call
+  where the library has one, across clients (squares: he_mul_relin_across;
+  the rotations of the slot sums: he_rotate_across), so their key switches
+  share launches, each item with its own client's keys.  Requests that
+  arrive while others are on the GPU join the next round.
 - One-at-a-time.  The baseline serves requests strictly in arrival order,
   each to completion, on the same contexts.
 
@@ -128,46 +128,47 @@ def make_requests(H, clients, n, qps, seed, cnn_frac=0.5, per_client=REQS_PER_CL
     return reqs
 
 
-def _advance(H, client, kind, stage, reqs):
-    """Run one stage for requests of one client at the same stage."""
-    g = client.g
-    conv, fc1, fc2 = client.plans
+def _advance(H, kind, stage, reqs):
+    """Run one stage for requests at the same stage (of one or several
+    clients): the key switches of squares and slot-sum rotations run as one
+    batch across the requests, each on its own client's keys."""
     s = I.CNN_SHAPE
+    run = reqs[0].client.g
     if kind == "cnn":
         name = CNN_STAGES[stage]
-        if name == "conv":
-            for r in reqs:
-                r.x = H.he_plan_apply_many(g, conv, r.x)
-        elif name == "pack":
-            for r in reqs:
-                r.x = H.he_pack(g, r.x, s["windows"])
-        elif name in ("square1", "square2"):
-            outs = H.he_mul_relin_many(g, [r.x for r in reqs], [r.x for r in reqs])
+        if name in ("square1", "square2"):
+            outs = H.he_mul_relin_across(run, [r.x for r in reqs], [r.x for r in reqs])
             for r, o in zip(reqs, outs):
                 r.x = o
-        elif name == "fc1":
-            for r in reqs:
-                r.x = H.he_plan_apply(g, fc1, r.x)
         else:
             for r in reqs:
-                r.x = H.he_plan_apply(g, fc2, r.x)
+                g = r.client.g
+                conv, fc1, fc2 = r.client.plans
+                if name == "conv":
+                    r.x = H.he_plan_apply_many(g, conv, r.x)
+                elif name == "pack":
+                    r.x = H.he_pack(g, r.x, s["windows"])
+                elif name == "fc1":
+                    r.x = H.he_plan_apply(g, fc1, r.x)
+                else:
+                    r.x = H.he_plan_apply(g, fc2, r.x)
         return stage + 1 == len(CNN_STAGES)
     name = LR_STAGES[stage]
     if name == "mul":
         for r in reqs:
-            r.x = H.he_mul_plain(g, r.x, r.extra["wp"])
+            r.x = H.he_mul_plain(r.client.g, r.x, r.extra["wp"])
     elif name == "sum":
         # slot sums of different lengths: step j rotates every request that
         # still needs it, in one batched call
         steps = {r.rid: lr_steps(r.extra["d"]) for r in reqs}
         for j in range(max(len(v) for v in steps.values())):
             act = [r for r in reqs if j < len(steps[r.rid])]
-            rots = H.he_rotate_many(g, [r.x for r in act], [steps[r.rid][j] for r in act])
+            rots = H.he_rotate_across(run, [r.x for r in act], [steps[r.rid][j] for r in act])
             for r, o in zip(act, rots):
-                r.x = H.he_add(g, r.x, o)
+                r.x = H.he_add(r.client.g, r.x, o)
     else:
         for r in reqs:
-            r.x = H.he_add_plain(g, r.x, r.extra["bp"])
+            r.x = H.he_add_plain(r.client.g, r.x, r.extra["bp"])
     return stage + 1 == len(LR_STAGES)
 
 
@@ -196,10 +197,10 @@ def serve(H, reqs, budget_bytes, batched=True):
             continue
         groups = collections.OrderedDict()
         for r in active:
-            groups.setdefault((r.client.cid, r.kind, r.stage), []).append(r)
+            groups.setdefault((r.kind, r.stage), []).append(r)
         finished = []
-        for (cid, kind, stage), rs in groups.items():
-            last = _advance(H, rs[0].client, kind, stage, rs)
+        for (kind, stage), rs in groups.items():
+            last = _advance(H, kind, stage, rs)
             for r in rs:
                 r.stage += 1
                 if last:
