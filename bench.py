@@ -164,6 +164,24 @@ def small_ops_table(H, I, torch, runs=1000, oracle_runs=5):
             "ops": table}
 
 
+def uneven_oracle_check(sample, seed=4):
+    """The work queue's results for a sample of the N=4096 operations of the
+    uneven mix against the oracle (same primes, seed and keys)."""
+    from oracle import oracle as O
+    o = O.Oracle(12, [50] * 9, 2.0 ** 40, seed)
+    o.keygen()
+    o.galois_keygen(1)
+    ok = []
+    for s in sample:
+        a = o.ct_from_data(s["a"], s["lp"] - 1, 2.0 ** 40)
+        if s["kind"] == 0:
+            ref = o.rescale(o.mul_relin(a, o.ct_from_data(s["b"], s["lp"] - 1, 2.0 ** 40)))
+        else:
+            ref = o.rotate(a, 1)
+        ok.append(bool(np.array_equal(ref.data(), s["out"])))
+    return {"operations": len(ok), "bit_exact": all(ok) if ok else None}
+
+
 def host_info():
     """The host the oracle runs on: CPU model, logical CPUs, and the CPUs this
     process may use."""
@@ -402,7 +420,11 @@ def main():
         cpu["parallel"] = cpu_baseline_parallel(args.cpu_budget)
         log("cpu baseline: N=4096 operation set, GPU beside the oracle")
         cpu["small_ops"] = small_ops_table(H, I, torch)
+        if uneven is not None:
+            cpu["uneven_oracle_sample"] = uneven_oracle_check(uneven.pop("oracle_sample"))
 
+    if uneven is not None:
+        uneven.pop("oracle_sample", None)  # checked by the CPU baseline leg, not reported
     res = {
         "metric": "encrypted-CNN inferences/s (N=8192, batch 1)",
         "value": 1e3 / ms_per_step,
@@ -756,7 +778,7 @@ def uneven_bench(H, I, n_ops=1024, seed=4):
     kinds = rng.integers(0, 2, n_ops)           # 0: multiply, 1: rotate
     logns = rng.choice([12, 13, 14], n_ops)
     lps = rng.integers(2, 9, n_ops)             # data limbs at the op
-    ctxs, tune, inputs = {}, {}, {}
+    ctxs, tune, inputs, input_data = {}, {}, {}, {}
     for ln in (12, 13, 14):
         g = H.he_ctx_create(ln, [50] * 9, 2.0 ** 40, seed, auto_rescale=True, stream=None)
         H.he_keygen(g, [1])
@@ -766,6 +788,8 @@ def uneven_bench(H, I, n_ops=1024, seed=4):
         for lp in range(2, 9):
             data = I.raw_residues(g.primes, 4, lp, g.n, seed=ln * 10 + lp)
             inputs[(ln, lp)] = [H.he_ct_import(g, data[i], lp - 1, 2.0 ** 40) for i in range(4)]
+            if ln == 12:
+                input_data[(ln, lp)] = data
     for g in ctxs.values():
         H.he_sync(g)
     ops = [(int(kinds[i]), int(logns[i]), int(lps[i]), i % 4) for i in range(n_ops)]
@@ -814,13 +838,38 @@ def uneven_bench(H, I, n_ops=1024, seed=4):
             del out
         return best
 
+    qops = [(ctxs[ln], "mul", inputs[(ln, lp)][j], inputs[(ln, lp)][(j + 1) % 4]) if k == 0
+            else (ctxs[ln], "rotate", inputs[(ln, lp)][j], 1) for k, ln, lp, j in ops]
+
+    def queued():
+        return H.he_queue_run(ctxs[13], qops)
+
     t_one = timed(one_by_one)
     t_bat = timed(batched)
-    ref, got = one_by_one(), batched()
+    t_q = timed(queued)
+    # GPU time of the queue's eight launches alone (HIP events on the stream)
+    H.he_profile_enable(ctxs[13], True)
+    for _ in range(3):
+        del_ = queued()
+        del del_
+    qn, qms, qunits, _ = H.he_profile_read(ctxs[13], "queue")
+    H.he_profile_enable(ctxs[13], False)
+    ref, got, qgot = one_by_one(), batched(), queued()
     sample = list(range(0, n_ops, 37))
     exact = all(np.array_equal(H.he_ct_export(ctxs[ops[i][1]], ref[i]), H.he_ct_export(ctxs[ops[i][1]], got[i]))
                 for i in sample)
-    del ref, got
+    qexact = all(np.array_equal(H.he_ct_export(ctxs[ops[i][1]], ref[i]), H.he_ct_export(ctxs[ops[i][1]], qgot[i]))
+                 for i in sample)
+    # a sample of the N=4096 operations for the oracle (checked in the CPU
+    # baseline leg): inputs, kinds and the queue's results
+    oracle_sample = []
+    for i in range(n_ops):
+        k, ln, lp, j = ops[i]
+        if ln == 12 and len(oracle_sample) < 6:
+            oracle_sample.append({"kind": k, "lp": lp, "a": input_data[(ln, lp)][j],
+                                  "b": input_data[(ln, lp)][(j + 1) % 4],
+                                  "out": H.he_ct_export(ctxs[ln], qgot[i])})
+    del ref, got, qgot
     # one graph per ring degree (its own stream), replayed together
     graphs, keep = [], []
     for ln, g in ctxs.items():
@@ -843,8 +892,13 @@ def uneven_bench(H, I, n_ops=1024, seed=4):
             "one_by_one": {"ms": t_one * 1e3, "ops_per_s": n_ops / t_one},
             "batched": {"ms": t_bat * 1e3, "ops_per_s": n_ops / t_bat, "speedup": t_one / t_bat},
             "batched_graph": {"ms": t_graph * 1e3, "ops_per_s": n_ops / t_graph, "speedup": t_one / t_graph},
-            "bit_exact_sample": exact, "ntt_tuning": tune,
-            "note": "grouped batched launches stand in for one persistent launch"}
+            "work_queue": {"ms": t_q * 1e3, "ops_per_s": n_ops / t_q, "speedup": t_one / t_q,
+                           "gpu_ms": qms / 3, "launches": int(qn / 3), "tasks": int(qunits / max(qn, 1)),
+                           "note": "he_queue_run: all 1024 operations as eight launches (one per key-switch "
+                                   "stage), each a resident grid draining a device task queue; ms includes "
+                                   "building and uploading the task descriptors"},
+            "bit_exact_sample": exact, "work_queue_bit_exact_sample": qexact, "ntt_tuning": tune,
+            "oracle_sample": oracle_sample}
 
 
 def keyswitch_bench(H, I, n_ct=256, reps=3):

@@ -270,6 +270,33 @@ he_status he_mul_relin_across(he_ctx* run, const he_ct* const* a, const he_ct* c
 he_status he_rotate_across(he_ctx* run, const he_ct* const* a, const int32_t* steps,
                            size_t n, he_ct** out);
 
+/* ---- one work queue over uneven operations (section 2.1's thread pool of
+ * independent operations, as device work queues) ---- */
+#define HE_QOP_MUL_RELIN 0 /* he_mul_relin(a, b), rescaled if ctx auto_rescale */
+#define HE_QOP_ROTATE 1    /* he_rotate(a, step), step != 0 mod N/2          */
+typedef struct {
+  he_ctx* ctx;     /* the operation's context: its keys, tables and results */
+  int32_t kind;    /* HE_QOP_MUL_RELIN or HE_QOP_ROTATE                     */
+  const he_ct* a;  /* operand (belongs to ctx)                              */
+  const he_ct* b;  /* second factor of a product (same level as a)          */
+  int32_t step;    /* left rotation                                         */
+} he_qop;
+/* Runs n operations of any mix of contexts (ring degrees 2^12..2^14, any
+ * levels) on one device as eight launches in all, one per stage of the key
+ * switch (tensor; inverse transform of the digits; ModUp; inner products;
+ * inverse transform of the special limbs; ModDown; for rescaled products
+ * the top limb's inverse transform and the division).  Each launch is a
+ * resident grid of 1024-thread workgroups that take limb-sized tasks of all
+ * operations from a device queue (an atomic counter) until it is empty,
+ * larger rings first.  out[i] is a new ciphertext of ops[i].ctx, bit-
+ * identical to that context's own he_mul_relin / he_rotate.  The work runs
+ * on run's stream after the work queued on every involved context's stream;
+ * the call returns when it is done (it synchronises run's stream).
+ * HE_EINVAL for NULL or foreign handles, unsupported ring degrees, a zero
+ * rotation, another device or an open capture; HE_ENOKEY, HE_ELEVEL as the
+ * single calls; HE_EOOM. */
+he_status he_queue_run(he_ctx* run, const he_qop* ops, size_t n, he_ct** out);
+
 /* ---- composites (sections 3.1, 3.2; appendix A.3, A.4) ---- */
 
 /* x <- x + rot(x, 2^j), j < ceil(log2 n): slot 0 gets the sum of slots

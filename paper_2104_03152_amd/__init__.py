@@ -79,6 +79,7 @@ _SIGS = {
     "he_graph_free": (None, [_vp]),
     "he_ct_copy": (C.c_int32, [_vp, _vp, _vp]),
     "he_rotate_many": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
+    "he_queue_run": (C.c_int32, [_vp, _vp, C.c_size_t, _pvp]),
     "he_mul_relin_across": (C.c_int32, [_vp, _pvp, _pvp, C.c_size_t, _pvp]),
     "he_rotate_across": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
     "he_sum_slots": (C.c_int32, [_vp, _vp, C.c_uint32, _pvp]),
@@ -526,6 +527,35 @@ def he_rotate_across(run, a, steps):
     outs = (C.c_void_p * n)()
     _chk(lib().he_rotate_across(run.ptr, pa, _ptr(st, C.c_int32), n, outs), "he_rotate_across")
     return [Ct(a[i].ctx, outs[i]) for i in range(n)]
+
+
+HE_QOP_MUL_RELIN, HE_QOP_ROTATE = 0, 1
+
+
+class he_qop(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("kind", C.c_int32), ("a", C.c_void_p), ("b", C.c_void_p),
+                ("step", C.c_int32)]
+
+
+def he_queue_run(run, ops):
+    """ops: (ctx, "mul", a, b) or (ctx, "rotate", a, step) tuples, any mix of
+    contexts, ring degrees and levels, run as one set of work-queue launches
+    on `run`'s stream; returns one new ciphertext per operation, in its
+    context."""
+    n = len(ops)
+    arr = (he_qop * max(1, n))()
+    for i, op in enumerate(ops):
+        ctx, kind, a, x = op
+        arr[i].ctx, arr[i].a = ctx.ptr, a.ptr
+        if kind == "mul":
+            arr[i].kind, arr[i].b, arr[i].step = HE_QOP_MUL_RELIN, x.ptr, 0
+        elif kind == "rotate":
+            arr[i].kind, arr[i].b, arr[i].step = HE_QOP_ROTATE, None, int(x)
+        else:
+            raise ValueError("unknown operation kind %r" % (kind,))
+    outs = (C.c_void_p * max(1, n))()
+    _chk(lib().he_queue_run(run.ptr, arr, n, outs), "he_queue_run")
+    return [Ct(ops[i][0], outs[i]) for i in range(n)]
 
 
 def he_sum_slots(ctx, a, n):

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libckks_hip.so")
 PROBE_LIB = os.path.join(HERE, "libckks_probe.so")
 PROBE_SRC = "probe.hip"
 SOURCES = ["ntt.hip", "kernels.hip", "ckks.cpp", "encode.cpp"]
-HEADERS = ["modarith.h", "butterfly.h", "device.h", "encode.h"]
+HEADERS = ["modarith.h", "butterfly.h", "device.h", "inner.h", "encode.h"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

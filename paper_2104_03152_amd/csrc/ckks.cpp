@@ -15,6 +15,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <string>
 #include <unordered_map>
@@ -434,8 +435,10 @@ struct Addend {
   const u64* p2 = nullptr;     // second addend (every poly)
   long long a2a = 0;
 };
-he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, const u64* u, long long ua,
-                    u64* dst, long long da, int n_t, Addend add, const char* fam) {
+// the divide-and-round transform job: dst[a][t] = (u[a][t] - NTT_t(r - h)) * q_s^-1
+// (+ addends), r the rounding lift of src_coef[a] (coefficients mod q_s)
+static NttJob round_div_job(const he_ctx* c, int n_poly, const u64* src_coef, int src_prime, const u64* u,
+                            long long ua, u64* dst, long long da, int n_t, const Addend& add) {
   NttJob J{};
   J.src = src_coef;
   J.sa = c->n;
@@ -467,6 +470,12 @@ he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, c
     J.inv[t] = c->rd_inv[src_prime * np + t];
     J.inv_sh[t] = c->rd_inv_sh[src_prime * np + t];
   }
+  return J;
+}
+
+he_status round_div(he_ctx* c, int n_poly, const u64* src_coef, int src_prime, const u64* u, long long ua,
+                    u64* dst, long long da, int n_t, Addend add, const char* fam) {
+  const NttJob J = round_div_job(c, n_poly, src_coef, src_prime, u, ua, dst, da, n_t, add);
   // per job: divisor limb, dividend limb, optional addend read; result written
   const double jobs = (double)n_poly * n_t;
   Prof pr(c, fam, jobs, 8.0 * c->n * jobs * (add.p ? 4.0 : 3.0));
@@ -2037,6 +2046,301 @@ static he_status across_contexts(he_ctx* run, const he_ct* const* a, const he_ct
       out[i] = nullptr;
     }
   return s;
+}
+
+// ---------------------------------------------------------------- work queue
+// Key switches (multiply + relinearise (+ rescale), rotate) of any mix of
+// contexts, ring degrees and levels as eight launches in all, each draining
+// one stage's task list with a resident grid: tensor; inverse transform of
+// the digits; ModUp (lift + forward transform); inner products; inverse
+// transform of the special limbs; ModDown; and for rescaled products the
+// inverse transform of the top limb and the division.  A task is one limb
+// of one operation; each stage's tasks are ordered largest ring first.
+namespace {
+struct QueueBuild {
+  std::vector<NttJob> ntt;
+  std::vector<InnerJob> inner;
+  std::vector<QTensor> tensor;
+  std::vector<QTables> tabs;
+  std::vector<const he_ctx*> tab_ctx;
+  std::vector<QTask> stage[8];
+  size_t lds[8] = {0};
+  int tab_of(const he_ctx* c) {
+    for (size_t i = 0; i < tab_ctx.size(); i++)
+      if (tab_ctx[i] == c) return (int)i;
+    tab_ctx.push_back(c);
+    tabs.push_back(QTables{c->d_primes, c->tabs.fwd, c->tabs.inv, c->tabs.fwd_fp, c->tabs.inv_fp});
+    return (int)tabs.size() - 1;
+  }
+  void add(int st, int kind, int log_n, int job, int n_w, int tab) {
+    for (int w = 0; w < n_w; w++) stage[st].push_back(QTask{log_n, job, w, tab});
+    lds[st] = std::max(lds[st], queue_lds_bytes(kind, log_n));
+  }
+};
+const int kQueueKind[8] = {QK_TENSOR, QK_INV, QK_FWD_LIFT, QK_INNER, QK_INV, QK_FWD_RD, QK_INV, QK_FWD_RD};
+}  // namespace
+
+he_status he_queue_run(he_ctx* run, const he_qop* ops, size_t n, he_ct** out) {
+  if (!run || !out || (n && !ops)) return fail(HE_EINVAL, "NULL argument");
+  for (size_t i = 0; i < n; i++) out[i] = nullptr;
+  if (n == 0) return HE_OK;
+  NO_CAPTURE(run);
+  // validation and the operations' own contexts
+  std::vector<he_ctx*> others;
+  std::vector<const Key*> keys(n);
+  std::vector<int> levels(n), steps(n, 0);
+  size_t scratch_words = 0;
+  for (size_t i = 0; i < n; i++) {
+    const he_qop& o = ops[i];
+    he_ctx* c = o.ctx;
+    if (!c || !o.a) return fail(HE_EINVAL, "operation %zu: NULL context or operand", i);
+    if (o.a->ctx != c || (o.b && o.b->ctx != c)) return fail(HE_EINVAL, "operation %zu: handle of another context", i);
+    if (c->device != run->device) return fail(HE_EINVAL, "operation %zu: context on another device", i);
+    if (c->log_n < 12 || c->log_n > 14) return fail(HE_EINVAL, "operation %zu: ring degree 2^%d outside 2^12..2^14", i, c->log_n);
+    if (c->capturing) return fail(HE_EINVAL, "operation %zu: its context is capturing a graph", i);
+    const int l = o.a->level, Lp = l + 1, nm = Lp + 1;
+    const size_t N = (size_t)c->n;
+    levels[i] = l;
+    if (o.kind == HE_QOP_MUL_RELIN) {
+      if (!o.b) return fail(HE_EINVAL, "operation %zu: NULL second factor", i);
+      if (o.b->level != l) return fail(HE_ELEVEL, "operation %zu: factors at levels %d and %d", i, l, o.b->level);
+      if (!c->have_keys) return fail(HE_ENOKEY, "operation %zu: no relinearisation key", i);
+      if (c->relin.ml < l) return fail(HE_ENOKEY, "operation %zu: relinearisation key below level %d", i, l);
+      if (c->auto_rescale && l < 1) return fail(HE_ELEVEL, "operation %zu: no level left to rescale", i);
+      keys[i] = &c->relin;
+      scratch_words += N * (3 * Lp + Lp + Lp * nm + 2 * nm + 2 + (c->auto_rescale ? 2 * Lp + 2 : 0));
+    } else if (o.kind == HE_QOP_ROTATE) {
+      const int st = norm_step(c, o.step);
+      if (st == 0) return fail(HE_EINVAL, "operation %zu: rotation by 0 slots", i);
+      auto it = c->gal.find(st);
+      if (it == c->gal.end()) return fail(HE_ENOKEY, "operation %zu: no Galois key for step %d", i, st);
+      if (it->second.ml < l) return fail(HE_ENOKEY, "operation %zu: Galois key for step %d below level %d", i, st, l);
+      keys[i] = &it->second;
+      steps[i] = st;
+      scratch_words += N * (Lp + Lp * nm + 2 * nm + 2);
+    } else {
+      return fail(HE_EINVAL, "operation %zu: unknown kind %d", i, o.kind);
+    }
+    if (c != run && std::find(others.begin(), others.end(), c) == others.end()) others.push_back(c);
+  }
+  // results, in each operation's own context
+  for (size_t i = 0; i < n; i++) {
+    const he_qop& o = ops[i];
+    const int l = levels[i];
+    const bool resc = o.kind == HE_QOP_MUL_RELIN && o.ctx->auto_rescale;
+    double sc = o.kind == HE_QOP_MUL_RELIN ? o.a->scale * o.b->scale : o.a->scale;
+    if (resc) sc /= (double)o.ctx->q[l];
+    he_status s = new_ct(o.ctx, resc ? l - 1 : l, sc, &out[i]);
+    if (s != HE_OK) {
+      for (size_t k = 0; k < i; k++) {
+        he_ct_free(out[k]);
+        out[k] = nullptr;
+      }
+      return s;
+    }
+  }
+  auto release = [&](he_status s) {
+    for (size_t i = 0; i < n; i++) {
+      he_ct_free(out[i]);
+      out[i] = nullptr;
+    }
+    return s;
+  };
+  DBuf scratch;
+  if (dalloc(run, scratch, scratch_words) != HE_OK) return release(fail(HE_EOOM, "queue intermediates"));
+  // jobs and tasks
+  QueueBuild Q;
+  u64* mem = scratch.p;
+  auto take = [&](size_t words) {
+    u64* p = mem;
+    mem += words;
+    return p;
+  };
+  // operations sharing a key (same context, key and level) form groups of up
+  // to HE_MAX_BATCH whose inner products run as one task per modulus, so
+  // the key words are read once for the group
+  std::vector<size_t> order(n);
+  for (size_t i = 0; i < n; i++) order[i] = i;
+  auto gkey = [&](size_t i) { return std::make_tuple((const void*)ops[i].ctx, (const void*)keys[i]->d, levels[i]); };
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return gkey(x) < gkey(y); });
+  for (size_t g0 = 0; g0 < n;) {
+    size_t g1 = g0 + 1;
+    while (g1 < n && g1 - g0 < HE_MAX_BATCH && gkey(order[g1]) == gkey(order[g0])) g1++;
+    const int B = (int)(g1 - g0);
+    he_ctx* c = ops[order[g0]].ctx;
+    const int l = levels[order[g0]], Lp = l + 1, nm = Lp + 1, N = c->n, L = c->L, ln = c->log_n;
+    const int tab = Q.tab_of(c);
+    u64* ext_g = take((size_t)B * Lp * nm * N);
+    u64* u_g = take((size_t)B * 2 * nm * N);
+    InnerJob I{};
+    I.ext = ext_g;
+    I.u = u_g;
+    I.B = B;
+    I.n_dig = Lp;
+    I.special_prime = L;
+    for (int b = 0; b < B; b++) {
+      const size_t i = order[g0 + b];
+      const he_qop& o = ops[i];
+      const bool mul = o.kind == HE_QOP_MUL_RELIN, resc = mul && c->auto_rescale;
+      const u64* d;
+      u64 g = 1;
+      Addend add;
+      if (mul) {
+        u64* d01 = take((size_t)2 * Lp * N);
+        u64* d2 = take((size_t)Lp * N);
+        Q.tensor.push_back(QTensor{o.a->d, o.b->d, d01, d2, Lp});
+        Q.add(0, QK_TENSOR, ln, (int)Q.tensor.size() - 1, Lp, tab);
+        d = d2;
+        add.p = d01;
+        add.aa = (long long)Lp * N;
+      } else {
+        g = galois_elt(c, steps[i]);
+        d = o.a->d + (size_t)Lp * N;  // tau_g(c1) is read by gather
+        add.p = o.a->d;                // tau_g(c0) joins poly 0
+        add.aa = (long long)Lp * N;
+        add.even_only = 1;
+      }
+      u64 gals[1] = {g};
+      if (!mul) add.gals = gals;
+      u64* coef = take((size_t)Lp * N);
+      u64* ext = ext_g + (size_t)b * Lp * nm * N;
+      u64* u = u_g + (size_t)b * 2 * nm * N;
+      u64* ucoef = take((size_t)2 * N);
+      {  // digits to coefficients (tau_g applied by the gather)
+        NttJob J{};
+        J.src = d;
+        J.dst = coef;
+        J.na = 1;
+        J.nb = Lp;
+        J.sb = N;
+        J.da = (long long)Lp * N;
+        J.db = N;
+        for (int t = 0; t < Lp; t++) J.dst_prime[t] = (unsigned char)t;
+        if (!mul) {
+          J.gather_src = 1;
+          J.gal_div = 1;
+          J.gal[0] = g;
+        }
+        Q.ntt.push_back(J);
+        Q.add(1, QK_INV, ln, (int)Q.ntt.size() - 1, Lp, tab);
+      }
+      {  // ModUp: centred digit j lifted to every other modulus
+        NttJob J{};
+        J.src = coef;
+        J.sa = N;
+        J.dst = ext;
+        J.da = (long long)nm * N;
+        J.db = N;
+        J.na = Lp;
+        J.nb = nm;
+        J.skip_diag = 1;
+        J.src_prime = -1;
+        J.amod = Lp;
+        for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)(t < Lp ? t : L);
+        Q.ntt.push_back(J);
+        Q.add(2, QK_FWD_LIFT, ln, (int)Q.ntt.size() - 1, Lp * (nm - 1), tab);
+      }
+      I.key[b] = keys[i]->d;  // the group's key
+      I.km[b] = keys[i]->ml + 2;
+      I.gal[b] = g;
+      I.diag_p[b] = d;
+      {  // the special limbs to coefficients
+        NttJob J{};
+        J.src = u + (size_t)Lp * N;
+        J.sa = (long long)nm * N;
+        J.dst = ucoef;
+        J.da = N;
+        J.na = 2;
+        J.nb = 1;
+        J.dst_prime[0] = (unsigned char)L;
+        Q.ntt.push_back(J);
+        Q.add(4, QK_INV, ln, (int)Q.ntt.size() - 1, 2, tab);
+      }
+      u64* ks_out = resc ? take((size_t)2 * Lp * N) : out[i]->d;
+      Q.ntt.push_back(round_div_job(c, 2, ucoef, L, u, (long long)nm * N, ks_out, (long long)Lp * N, Lp, add));
+      Q.add(5, QK_FWD_RD, ln, (int)Q.ntt.size() - 1, 2 * Lp, tab);
+      if (resc) {  // rescale: the top limb to coefficients, then the division
+        u64* rcoef = take((size_t)2 * N);
+        NttJob J{};
+        J.src = ks_out + (size_t)l * N;
+        J.sa = (long long)Lp * N;
+        J.dst = rcoef;
+        J.da = N;
+        J.na = 2;
+        J.nb = 1;
+        J.dst_prime[0] = (unsigned char)l;
+        Q.ntt.push_back(J);
+        Q.add(6, QK_INV, ln, (int)Q.ntt.size() - 1, 2, tab);
+        Q.ntt.push_back(round_div_job(c, 2, rcoef, l, ks_out, (long long)Lp * N, out[i]->d, (long long)l * N, l,
+                                      Addend{}));
+        Q.add(7, QK_FWD_RD, ln, (int)Q.ntt.size() - 1, 2 * l, tab);
+      }
+    }
+    Q.inner.push_back(I);
+    Q.add(3, QK_INNER, ln, (int)Q.inner.size() - 1, nm * (N / 1024), tab);
+    g0 = g1;
+  }
+  if ((size_t)(mem - scratch.p) != scratch_words) return release(fail(HE_EINVAL, "queue layout mismatch"));
+  // one device image: stage counters, tables, tasks, job records
+  for (auto& st : Q.stage)
+    std::stable_sort(st.begin(), st.end(), [](const QTask& x, const QTask& y) { return x.log_n > y.log_n; });
+  auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t off = align(8 * sizeof(unsigned));
+  const size_t o_tabs = off;
+  off = align(off + Q.tabs.size() * sizeof(QTables));
+  size_t o_task[8];
+  for (int k = 0; k < 8; k++) {
+    o_task[k] = off;
+    off = align(off + Q.stage[k].size() * sizeof(QTask));
+  }
+  const size_t o_ntt = off;
+  off = align(off + Q.ntt.size() * sizeof(NttJob));
+  const size_t o_inner = off;
+  off = align(off + Q.inner.size() * sizeof(InnerJob));
+  const size_t o_tensor = off;
+  off = align(off + Q.tensor.size() * sizeof(QTensor));
+  std::vector<unsigned char> img(off, 0);
+  std::memcpy(img.data() + o_tabs, Q.tabs.data(), Q.tabs.size() * sizeof(QTables));
+  for (int k = 0; k < 8; k++)
+    if (!Q.stage[k].empty()) std::memcpy(img.data() + o_task[k], Q.stage[k].data(), Q.stage[k].size() * sizeof(QTask));
+  std::memcpy(img.data() + o_ntt, Q.ntt.data(), Q.ntt.size() * sizeof(NttJob));
+  std::memcpy(img.data() + o_inner, Q.inner.data(), Q.inner.size() * sizeof(InnerJob));
+  if (!Q.tensor.empty()) std::memcpy(img.data() + o_tensor, Q.tensor.data(), Q.tensor.size() * sizeof(QTensor));
+  DBuf dimg;
+  if (dalloc(run, dimg, (off + 7) / 8) != HE_OK) return release(fail(HE_EOOM, "queue descriptors"));
+  unsigned char* base = reinterpret_cast<unsigned char*>(dimg.p);
+  // order: run's stream after the other contexts' queued work
+  for (he_ctx* o : others) {
+    if (hipEventRecord(o->ev_cross, o->st) != hipSuccess || hipStreamWaitEvent(run->st, o->ev_cross, 0) != hipSuccess)
+      return release(fail(HE_EHIP, "stream ordering failed"));
+  }
+  he_status s = HE_OK;
+  hipError_t e = hipMemcpyAsync(base, img.data(), off, hipMemcpyHostToDevice, run->st);
+  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<unsigned*>(base), 8, 0u, run->st);
+  {
+    size_t units = 0;
+    for (auto& st : Q.stage) units += st.size();
+    Prof pr(run, "queue", (double)units, 0.0);
+    for (int k = 0; k < 8 && e == hipSuccess; k++) {
+      const int cnt = (int)Q.stage[k].size();
+      if (cnt == 0) continue;
+      const int kind = kQueueKind[k];
+      const void* jobs = kind == QK_INNER    ? (const void*)(base + o_inner)
+                         : kind == QK_TENSOR ? (const void*)(base + o_tensor)
+                                             : (const void*)(base + o_ntt);
+      const int grid = std::min(cnt, queue_grid(run->device, Q.lds[k]));
+      e = launch_queue(kind, reinterpret_cast<const QTask*>(base + o_task[k]), cnt, jobs,
+                       reinterpret_cast<const QTables*>(base + o_tabs), reinterpret_cast<unsigned*>(base) + k, grid,
+                       Q.lds[k], run->st);
+    }
+  }
+  if (e != hipSuccess) s = fail(HE_EHIP, "queue launch: %s", hipGetErrorString(e));
+  // the host image must outlive the copy; later work of the other contexts
+  // waits for the queue
+  const hipError_t e2 = hipStreamSynchronize(run->st);
+  if (s == HE_OK && e2 != hipSuccess) s = fail(HE_EHIP, "queue: %s", hipGetErrorString(e2));
+  if (s != HE_OK) return release(s);
+  return HE_OK;
 }
 
 he_status he_mul_relin_across(he_ctx* run, const he_ct* const* a, const he_ct* const* b, size_t n, he_ct** out) {

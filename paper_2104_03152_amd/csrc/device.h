@@ -217,6 +217,9 @@ struct InnerJob {
   int B, n_dig, special_prime;
   const u64* key[HE_MAX_BATCH];
   int km[HE_MAX_BATCH];  // moduli stored in each key
+  // item b's input limbs at diag_p[b] when set (items not laid out with
+  // one stride), else at diag + b * diag_stride
+  const u64* diag_p[HE_MAX_BATCH];
 };
 hipError_t launch_inner(int log_n, const InnerJob& job, const PrimeDev* primes,
                         hipStream_t st);
@@ -306,6 +309,48 @@ hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const 
 // Montgomery form of plaintext rows
 hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
                           const PrimeDev* primes, hipStream_t st);
+
+// ---- work-queue launches over heterogeneous work ----
+// One task is one limb-sized piece of one job: the job's record (an NttJob,
+// an InnerJob or a QTensor, by the launch's kind), the job-local index w
+// (decoded as a launch decodes its block index; for INNER the modulus, for
+// TENSOR the limb), the task's ring degree and the tables of its context.
+struct QTask {
+  int log_n;
+  int job;
+  int w;
+  int tab;
+};
+struct QTables {
+  const PrimeDev* primes;
+  const u64* fwd;
+  const u64* inv;
+  const u64* fwd_fp;
+  const u64* inv_fp;
+};
+// the tensor of one product: (d0, d1) = (a0 b0, a0 b1 + a1 b0), d2 = a1 b1
+struct QTensor {
+  const u64* a;  // [2][Lp][N]
+  const u64* b;  // [2][Lp][N]
+  u64* out01;    // [2][Lp][N]
+  u64* out2;     // [Lp][N]
+  int Lp;
+};
+enum { QK_TENSOR = 0, QK_INV = 1, QK_FWD_LIFT = 2, QK_INNER = 3, QK_FWD_RD = 4 };
+// Drains tasks[0..n) of one kind: `grid` resident workgroups of 1024
+// threads each take the next task from *head (an atomic counter that must
+// be zero) until none is left; tasks may mix ring degrees 2^12..2^14 and
+// contexts.  INV runs inv_body (gathering when the job asks), FWD_LIFT the
+// forward transform with the centred lift, FWD_RD with the divide-and-round
+// prologue and epilogue.
+hipError_t launch_queue(int kind, const QTask* tasks, int n, const void* jobs, const QTables* tabs,
+                        unsigned* head, int grid, size_t lds_bytes, hipStream_t st);
+// dynamic LDS of a queue task of this kind at ring degree 2^log_n
+size_t queue_lds_bytes(int kind, int log_n);
+// workgroups of a queue launch that fit on the device at once
+int queue_grid(int device, size_t lds_bytes);
+// p[0..n) = v (a kernel, so that graph capture records a kernel node)
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st);
 
 // Fixed device scratch of the no-allocation entry point: the device address
 // of this device's copy of the array (looked up once per device, with that

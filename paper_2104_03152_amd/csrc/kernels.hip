@@ -7,6 +7,7 @@
 
 #include "../../include/ckks_hip.h"
 #include "device.h"
+#include "inner.h"
 
 // The no-allocation entry point's scratch: every intermediate of one call
 // lives here.  Each device holds its own copy for the life of the process;
@@ -276,26 +277,9 @@ __global__ void k_inner(int log_n, InnerJob J, const PrimeDev* __restrict__ prim
   const int i = (int)(e & (n - 1));
   const long long bt = e >> log_n;
   const int t = (int)(bt % nm), b = (int)(bt / nm);
-  const int km = J.km[b];
-  const int kt = t < J.n_dig ? t : km - 1;
   const PrimeDev P = primes[t < J.n_dig ? t : J.special_prime];
-  const size_t ks_k = (size_t)km * n, ks_j = 2 * ks_k;
-  const u64* kp = J.key[b] + (size_t)kt * n + i;
-  const u64* diag = J.diag + b * J.diag_stride;
-  const u64* ext = J.ext + (size_t)b * J.n_dig * nm * n;
-  const int di = J.gal[b] != 1 ? gal_src(i, log_n, J.gal[b]) : i;
-  u64 r0 = 0, r1 = 0;
-  for (int j0 = 0; j0 < J.n_dig; j0 += 8) {
-    U128 acc0 = {0, 0}, acc1 = {0, 0};
-    const int j1 = min(J.n_dig, j0 + 8);
-    for (int j = j0; j < j1; j++) {
-      const u64 d = (j == t) ? diag[(size_t)t * n + di] : ext[((size_t)j * nm + t) * n + i];
-      acc0 = add128(acc0, mul_wide(d, kp[j * ks_j]));
-      acc1 = add128(acc1, mul_wide(d, kp[j * ks_j + ks_k]));
-    }
-    r0 = addmod(r0, mont_reduce(acc0, P), P.q);
-    r1 = addmod(r1, mont_reduce(acc1, P), P.q);
-  }
+  u64 r0, r1;
+  inner_point(J, P, log_n, b, t, i, r0, r1);
   u64* u = J.u + (size_t)b * 2 * nm * n;
   u[(size_t)t * n + i] = r0;
   u[((size_t)nm + t) * n + i] = r1;

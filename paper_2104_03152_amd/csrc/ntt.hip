@@ -25,8 +25,11 @@
 // residue mod another prime: key-switch ModUp) or form r = [x + h]_p (the
 // divide-and-round of ModDown and rescale, less h); the epilogue then finishes
 // the division: dst = (u - NTT(r - h)) * p^-1 mod q (+ an addend).
+#include <algorithm>
+
 #include "butterfly.h"
 #include "device.h"
+#include "inner.h"
 
 namespace {
 
@@ -239,13 +242,16 @@ __device__ __forceinline__ void inv_passes(typename Ar::T (&x)[S::E], u64* lds, 
 }
 
 // ---------------- forward kernel ----------------
-template <int LOGN, int PRO, int EPI, class Ar>
+// C: the thread layout (a Sched over all LOGN bits); the kernels below use
+// Cfg<LOGN>, the work-queue kernels a fixed 1024-thread layout
+// tid: the thread's index (the work-queue kernel passes one the compiler
+// cannot hoist out of its task loop, so that the per-thread exchange
+// addresses are recomputed per task instead of held across tasks)
+template <int LOGN, int PRO, int EPI, class Ar, class C = Cfg<LOGN>>
 __device__ __forceinline__ void fwd_body(const NttJob& J, const PrimeDev* __restrict__ primes,
                                          const typename Ar::TW* __restrict__ W, const PrimeDev& P, int a, int b,
-                                         u64* lds) {
-  using C = Cfg<LOGN>;
+                                         u64* lds, const int tid = threadIdx.x) {
   const Ar ar(P);
-  const int tid = threadIdx.x;
   const u64 q = P.q;
   const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
   typename Ar::T x[C::E];
@@ -282,7 +288,7 @@ __device__ __forceinline__ void fwd_body(const NttJob& J, const PrimeDev* __rest
       }
     }
   }
-  fwd_passes<Cfg<LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
+  fwd_passes<C, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
   {
     constexpr int R = C::bits(C::NP - 1), G = C::E >> R;
     u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
@@ -335,12 +341,10 @@ k_ntt_fwd(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables t
 }
 
 // ---------------- inverse kernel ----------------
-template <int LOGN, bool GATHER, class Ar>
+template <int LOGN, bool GATHER, class Ar, class C = Cfg<LOGN>>
 __device__ __forceinline__ void inv_body(const NttJob& J, const typename Ar::TW* __restrict__ W, const PrimeDev& P,
-                                         int a, int b, u64* lds) {
-  using C = Cfg<LOGN>;
+                                         int a, int b, u64* lds, const int tid = threadIdx.x) {
   const Ar ar(P);
-  const int tid = threadIdx.x;
   const u64* __restrict__ src = J.src + a * J.sa + b * J.sb;
   typename Ar::T x[C::E];
   {
@@ -356,7 +360,7 @@ __device__ __forceinline__ void inv_body(const NttJob& J, const typename Ar::TW*
       }
     }
   }
-  inv_passes<Cfg<LOGN>, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
+  inv_passes<C, LOGN, 0, Ar, false>(x, lds, W, ar, tid, 0);
   {
     constexpr int R = C::bits(C::NP - 1), LO = LOGN - R, G = C::E >> R;
     u64* __restrict__ dst = J.dst + a * J.da + b * J.db;
@@ -1556,6 +1560,101 @@ hipError_t ks_launch(int which, const KsJob& J, const PrimeDev* primes, const Nt
   return hipGetLastError();
 }
 
+// ---------------- work queue over heterogeneous transforms ----------------
+// 1024 threads at every ring degree of the queue (2^12..2^14): 4, 8 or 16
+// words per thread.
+template <int LOGN>
+using QCfg = Sched<LOGN, 0, LOGN, LOGN - 10>;
+constexpr int QT = 1024;
+
+template <int KIND, int LOGN>
+__device__ __forceinline__ void q_transform(const NttJob& J, const QTables& T, int w, u64* lds, int tid) {
+  constexpr int N = 1 << LOGN;
+  int a, b;
+  decode_job(J, w, a, b);
+  const int dp = J.dst_prime[b];
+  const PrimeDev P = T.primes[dp];
+  if constexpr (KIND == QK_INV) {
+    const double2* wf = reinterpret_cast<const double2*>(T.inv_fp) + (size_t)dp * N;
+    const ulonglong2* wi = reinterpret_cast<const ulonglong2*>(T.inv) + (size_t)dp * N;
+    if (J.gather_src) {
+      if (P.use_fp)
+        inv_body<LOGN, true, FpAr, QCfg<LOGN>>(J, wf, P, a, b, lds, tid);
+      else
+        inv_body<LOGN, true, IntAr, QCfg<LOGN>>(J, wi, P, a, b, lds, tid);
+    } else {
+      if (P.use_fp)
+        inv_body<LOGN, false, FpAr, QCfg<LOGN>>(J, wf, P, a, b, lds, tid);
+      else
+        inv_body<LOGN, false, IntAr, QCfg<LOGN>>(J, wi, P, a, b, lds, tid);
+    }
+  } else {
+    constexpr int PRO = KIND == QK_FWD_RD ? PRO_ROUNDDIV_LIFT : PRO_CENTRED_LIFT;
+    constexpr int EPI = KIND == QK_FWD_RD ? EPI_ROUNDDIV : EPI_STORE;
+    if (P.use_fp)
+      fwd_body<LOGN, PRO, EPI, FpAr, QCfg<LOGN>>(J, T.primes, reinterpret_cast<const double2*>(T.fwd_fp) + (size_t)dp * N,
+                                                 P, a, b, lds, tid);
+    else
+      fwd_body<LOGN, PRO, EPI, IntAr, QCfg<LOGN>>(
+          J, T.primes, reinterpret_cast<const ulonglong2*>(T.fwd) + (size_t)dp * N, P, a, b, lds, tid);
+  }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(QT) k_queue(const QTask* __restrict__ tasks, int n, const void* __restrict__ jobs,
+                                             const QTables* __restrict__ tabs, unsigned* head) {
+  extern __shared__ u64 lds[];
+  __shared__ int s_next;
+  for (;;) {
+    if (threadIdx.x == 0) s_next = (int)atomicAdd(head, 1u);
+    __syncthreads();
+    // wave-uniform (scalar registers): the task and job records then come
+    // through scalar loads
+    const int k = __builtin_amdgcn_readfirstlane(s_next);
+    if (k >= n) return;  // the same value in every thread: the workgroup leaves together
+    const QTask t = tasks[k];
+    const QTables T = tabs[t.tab];
+    if constexpr (KIND == QK_TENSOR) {
+      const QTensor& J = static_cast<const QTensor*>(jobs)[t.job];
+      const int nn = 1 << t.log_n, limb = t.w;
+      const PrimeDev P = T.primes[limb];
+      const long long per = (long long)J.Lp * nn;
+      for (int i = threadIdx.x; i < nn; i += QT) {
+        const long long e = (long long)limb * nn + i;
+        const u64 a0 = J.a[e], a1 = J.a[per + e], b0 = J.b[e], b1 = J.b[per + e];
+        J.out01[e] = mulmod(a0, b0, P);
+        J.out01[per + e] = addmod(mulmod(a0, b1, P), mulmod(a1, b0, P), P.q);
+        J.out2[e] = mulmod(a1, b1, P);
+      }
+    } else if constexpr (KIND == QK_INNER) {
+      // modulus t, coefficients [1024 s, 1024 s + 1024) of every item of
+      // the job (items that share one key): each thread reads its key
+      // words once and applies them to every item
+      const InnerJob& J = static_cast<const InnerJob*>(jobs)[t.job];
+      const int nn = 1 << t.log_n, nm = J.n_dig + 1;
+      const int slices = nn / QT, tt = t.w / slices, i = (t.w - tt * slices) * QT + (int)threadIdx.x;
+      const PrimeDev P = T.primes[tt < J.n_dig ? tt : J.special_prime];
+      inner_shared_key(J, P, t.log_n, tt, i);
+    } else {
+      const NttJob& J = static_cast<const NttJob*>(jobs)[t.job];
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));  // opaque per task: no hoisting across tasks
+      if (t.log_n == 12)
+        q_transform<KIND, 12>(J, T, t.w, lds, tid);
+      else if (t.log_n == 13)
+        q_transform<KIND, 13>(J, T, t.w, lds, tid);
+      else
+        q_transform<KIND, 14>(J, T, t.w, lds, tid);
+    }
+    __syncthreads();  // LDS and s_next are free for the next task
+  }
+}
+
+__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 }  // namespace
 
 hipError_t launch_ntt_inv_blocks(int log_n, const NttJob& job, const PrimeDev* primes, const NttTables& tabs,
@@ -1676,4 +1775,62 @@ hipError_t launch_hoisted_moddown_mac(int log_n, const HoistMac& job, const Prim
     case 14: return hoist_launch<14>(job, primes, tabs, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------- work-queue launches ----------------
+size_t queue_lds_bytes(int kind, int log_n) {
+  if (kind == QK_TENSOR || kind == QK_INNER) return 0;
+  switch (log_n) {
+    case 12: return sizeof(u64) * QCfg<12>::lds_words();
+    case 13: return sizeof(u64) * QCfg<13>::lds_words();
+    case 14: return sizeof(u64) * QCfg<14>::lds_words();
+    default: return 0;
+  }
+}
+
+int queue_grid(int device, size_t lds_bytes) {
+  int cus = 0, lds_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+    cus = 256;
+  if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) != hipSuccess ||
+      lds_cu <= 0)
+    lds_cu = 160 * 1024;
+  // at most two 1024-thread workgroups per compute unit (32 waves)
+  int per = 2;
+  if (lds_bytes > 0) per = std::max(1, std::min(2, (int)((size_t)lds_cu / (lds_bytes + 1024))));
+  return cus * per;
+}
+
+template <int KIND>
+static hipError_t queue_launch_as(const QTask* tasks, int n, const void* jobs, const QTables* tabs, unsigned* head,
+                                  int grid, size_t lds, hipStream_t st) {
+  // the attribute allows the largest task's LDS (ring degree 2^14) once
+  static bool attr = false;
+  if (lds > 0) {
+    if (lds > queue_lds_bytes(KIND, 14)) return hipErrorInvalidValue;
+    hipError_t e = set_lds(k_queue<KIND>, queue_lds_bytes(KIND, 14), attr);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_queue<KIND>), dim3(grid), dim3(QT), lds, st, tasks, n, jobs, tabs, head);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue(int kind, const QTask* tasks, int n, const void* jobs, const QTables* tabs, unsigned* head,
+                        int grid, size_t lds_bytes, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (grid <= 0 || !tasks || !jobs || !tabs || !head) return hipErrorInvalidValue;
+  switch (kind) {
+    case QK_TENSOR: return queue_launch_as<QK_TENSOR>(tasks, n, jobs, tabs, head, grid, lds_bytes, st);
+    case QK_INV: return queue_launch_as<QK_INV>(tasks, n, jobs, tabs, head, grid, lds_bytes, st);
+    case QK_FWD_LIFT: return queue_launch_as<QK_FWD_LIFT>(tasks, n, jobs, tabs, head, grid, lds_bytes, st);
+    case QK_INNER: return queue_launch_as<QK_INNER>(tasks, n, jobs, tabs, head, grid, lds_bytes, st);
+    case QK_FWD_RD: return queue_launch_as<QK_FWD_RD>(tasks, n, jobs, tabs, head, grid, lds_bytes, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
 }
