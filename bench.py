@@ -632,6 +632,9 @@ def kernel_bench(H, torch, I, n_ct=256, reps=5):
     p = I.RAW
     g = H.he_ctx_create(p["log_n"], p["bits"], p["scale"], p["seed"], stream=None)
     n, limbs = g.n, g.L
+    # the autotuner picks the form and thread layout per launch size
+    chosen, tune_rows = H.he_tune_ntt(g, n_ct * 2 * limbs)
+    layouts = H.he_ntt_layouts(g)
     buf = torch.empty((n_ct * 2, limbs, n), dtype=torch.int64, device="cuda")
     for i in range(limbs):
         buf[:, i, :] = torch.randint(0, g.primes[i], (n_ct * 2, n), dtype=torch.int64, device="cuda")
@@ -659,6 +662,9 @@ def kernel_bench(H, torch, I, n_ct=256, reps=5):
     torch.cuda.synchronize()
     out["roundtrip_exact"] = bool(torch.equal(buf, ref))
     out["workload"] = "%d ciphertexts x 2 polys x %d limbs, N=%d, 50-bit primes" % (n_ct, limbs, n)
+    out["tuning"] = {"layouts_log2_words_radix": layouts, "split_jobs": chosen,
+                     "rows_us_fwd_plus_inv": [[round(v, 1) for v in r] for r in tune_rows],
+                     "columns": "J, two-phase, layout 0, layout 1, ..."}
     del buf, ref
     g.close()
     return out

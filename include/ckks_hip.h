@@ -207,14 +207,24 @@ he_status he_polyval(he_ctx* ctx, const he_ct* a, const double* coeffs, size_t n
 
 /* ---- NTT autotuner ----
  * Times batched forward + inverse NTTs of J limb-transforms (J = 16, 32, ...
- * up to max_jobs) with one workgroup per limb and with the two-phase
- * kernels (a limb spread over several workgroups), and from then on runs
- * each launch in the form that won for its size (rounded up to the next J;
- * larger launches follow the largest J).  *split_jobs: the largest J won by
- * the two-phase form (0: none).  The choice changes timing only, never
- * results.
- * table (nullable) receives rows (J, us one-workgroup, us two-phase), at
- * most table_cap doubles.  Synchronises; not allowed during a capture. */
+ * up to max_jobs; J limbs are the data limbs of J / L' ciphertext polys at
+ * L' limbs) in every candidate form: the two-phase kernels (a limb spread
+ * over several workgroups) and one workgroup per limb in each thread
+ * layout of he_ntt_layouts (words per thread and pass radix).  From then on
+ * each launch of plain transforms runs in the form that won for its size
+ * (rounded up to the next J; larger launches follow the largest J), and
+ * the fused key-switch transforms use the two-phase form where it won.
+ * *split_jobs: the largest J won by the two-phase form (0: none).  The
+ * choice changes timing only, never results.
+ * table (nullable) receives rows (J, us two-phase, us layout 0, us layout
+ * 1, ...) of 2 + layouts doubles each, at most table_cap doubles.
+ * Synchronises; not allowed during a capture.  HE_NTT_LAYOUT=k in the
+ * environment at context creation forces layout k for every plain
+ * one-workgroup launch of that context (a test and tuning aid). */
+/* The one-workgroup-per-limb thread layouts of the context's ring degree:
+ * log2 words per thread and log2 pass radix of layout i (layout 0 is the
+ * default), up to cap of them; *count: how many there are. */
+he_status he_ntt_layouts(he_ctx* ctx, int32_t* loge, int32_t* logr, size_t cap, size_t* count);
 he_status he_tune_ntt(he_ctx* ctx, int32_t max_jobs, int32_t* split_jobs, double* table,
                       size_t table_cap);
 
@@ -347,8 +357,9 @@ he_status he_plan_apply_many(he_ctx* ctx, const he_plan* const* plans,
 
 /* ---- raw transforms (batched negacyclic NTT on caller device buffers) ---- */
 /* data: device pointer to n_polys polynomials of n_limbs limbs, layout
- * [n_polys][n_limbs][N] u64, limb i under data prime i, residues in [0, q_i).
- * In place, enqueued on the context stream. */
+ * [n_polys][n_limbs][N] u64, limb i under data prime i, residues in [0, q_i),
+ * 16-byte aligned (HE_EINVAL otherwise).  In place, enqueued on the context
+ * stream. */
 he_status he_ntt_forward(he_ctx* ctx, uint64_t* data, size_t n_polys,
                          int32_t n_limbs);
 he_status he_ntt_inverse(he_ctx* ctx, uint64_t* data, size_t n_polys,

@@ -80,6 +80,7 @@ _SIGS = {
     "he_ct_copy": (C.c_int32, [_vp, _vp, _vp]),
     "he_rotate_many": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
     "he_queue_run": (C.c_int32, [_vp, _vp, C.c_size_t, _pvp]),
+    "he_ntt_layouts": (C.c_int32, [_vp, _i32p, _i32p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "he_mul_relin_across": (C.c_int32, [_vp, _pvp, _pvp, C.c_size_t, _pvp]),
     "he_rotate_across": (C.c_int32, [_vp, _pvp, _i32p, C.c_size_t, _pvp]),
     "he_sum_slots": (C.c_int32, [_vp, _vp, C.c_uint32, _pvp]),
@@ -443,14 +444,24 @@ def he_polyval(ctx, a, coeffs):
     return _new(Ct, ctx, lib().he_polyval, "he_polyval", ctx.ptr, a.ptr, _ptr(cs, C.c_double), cs.size)
 
 
+def he_ntt_layouts(ctx):
+    """[(log2 words per thread, log2 pass radix)] of the one-workgroup layouts."""
+    e, r = (C.c_int32 * 8)(), (C.c_int32 * 8)()
+    cnt = C.c_size_t()
+    _chk(lib().he_ntt_layouts(ctx.ptr, e, r, 8, C.byref(cnt)), "he_ntt_layouts")
+    return [(e[i], r[i]) for i in range(min(8, cnt.value))]
+
+
 def he_tune_ntt(ctx, max_jobs=1024):
-    """Returns (split_jobs chosen, rows of (J, us one-workgroup, us two-phase))."""
+    """Returns (split_jobs chosen, rows of (J, us two-phase, us layout 0,
+    us layout 1, ...)) for forward + inverse pairs."""
     chosen = C.c_int32()
-    cap = 3 * 16
+    width = 2 + len(he_ntt_layouts(ctx))
+    cap = width * 16
     table = np.zeros(cap, dtype=np.float64)
     _chk(lib().he_tune_ntt(ctx.ptr, int(max_jobs), C.byref(chosen), _ptr(table, C.c_double), cap),
          "he_tune_ntt")
-    rows = [tuple(table[i:i + 3]) for i in range(0, cap, 3) if table[i] > 0]
+    rows = [tuple(table[i:i + width]) for i in range(0, cap, width) if table[i] > 0]
     return chosen.value, rows
 
 

@@ -277,17 +277,19 @@ struct Prof {
   hipEvent_t a{}, b{};
   bool on;
   double units, bytes;
-  Prof(he_ctx* c_, const char* f, double units_ = 0, double bytes_ = 0)
-      : c(c_), fam(f), on(c_->prof && !c_->capturing && !c_->arena), units(units_), bytes(bytes_) {
+  hipStream_t st;  // the stream the timed launches go on (default: the context's)
+  Prof(he_ctx* c_, const char* f, double units_ = 0, double bytes_ = 0, hipStream_t st_ = nullptr)
+      : c(c_), fam(f), on(c_->prof && !c_->capturing && !c_->arena), units(units_), bytes(bytes_),
+        st(st_ ? st_ : c_->st) {
     if (on) {
       (void)hipEventCreate(&a);
       (void)hipEventCreate(&b);
-      (void)hipEventRecord(a, c->st);
+      (void)hipEventRecord(a, st);
     }
   }
   ~Prof() {
     if (on) {
-      (void)hipEventRecord(b, c->st);
+      (void)hipEventRecord(b, st);
       c->prof_recs.push_back({fam, a, b, units, bytes});
     }
   }
@@ -1162,6 +1164,8 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
   if (const char* env = getenv("HE_NTT_SPLIT_JOBS")) split_jobs = atoi(env);
   if (const char* env = getenv("HE_FUSE_MAX")) c->fuse_max = atoi(env);
   if (const char* env = getenv("HE_HOIST_SPLIT_WGS")) c->hoist_split_wgs = atoi(env);
+  int forced_shape = -1;
+  if (const char* env = getenv("HE_NTT_LAYOUT")) forced_shape = atoi(env);
   u64* tmp = nullptr;
   if (split_jobs > 0) {
     tmp = (u64*)c->pool.get((size_t)split_jobs * n * sizeof(u64));
@@ -1171,7 +1175,11 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
     }
   }
   c->tabs = NttTables{c->d_fwd, c->d_inv, c->d_fwd_fp, c->d_inv_fp, tmp, (long long)split_jobs * n, split_jobs,
-                      0, 0u, 0};
+                      0, 0u, 0, {0}, 0};
+  if (forced_shape > 0) {
+    NttShape shapes[8];
+    if (forced_shape < std::min(8, ntt_shapes(c->log_n, shapes, 8))) c->tabs.layout = forced_shape;
+  }
   c->rd_inv.assign((size_t)np * np, 0);
   c->rd_inv_sh.assign((size_t)np * np, 0);
   c->rd_hq.assign((size_t)np * np, 0);
@@ -2657,46 +2665,20 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       TRY(modup(c, coef.p, 1, Lp, ext.p));
       extp = ext.p;
     }
-    {
-      HoistInner I{};
-      I.ext = extp;
-      I.c1 = c1;
-      I.c0 = x->d;
-      for (int t = 0; t < Lp; t++) {
-        I.pq[t] = c->q[c->L] % c->q[t];
-        I.pq_sh[t] = h_shoup(I.pq[t], c->q[t]);
-      }
-      I.items = items;
-      I.u = u.p;
-      I.R = R;
-      I.n_dig = Lp;
-      I.nm = nm;
-      I.t_begin = 0;
-      I.t_end = nm;
-      I.special_prime = c->L;
-      // algorithmic bytes: the keys of the R items and the shared digits
-      // once (the u written for the ModDown is an intermediate of this
-      // design, not of the key switch)
-      Prof pr(c, "hoisted_inner", (double)R, 8.0 * n * (2.0 * R * Lp * nm + Lp * nm));
-      hipError_t e = launch_inner_hoisted(c->log_n, I, c->d_primes, c->st);
-      if (e != hipSuccess) return fail(HE_EHIP, "hoisted inner: %s", hipGetErrorString(e));
+    HoistInner I{};
+    I.ext = extp;
+    I.c1 = c1;
+    I.c0 = x->d;
+    for (int t = 0; t < Lp; t++) {
+      I.pq[t] = c->q[c->L] % c->q[t];
+      I.pq_sh[t] = h_shoup(I.pq[t], c->q[t]);
     }
+    I.n_dig = Lp;
+    I.nm = nm;
+    I.t_begin = 0;
+    I.t_end = nm;
+    I.special_prime = c->L;
     const bool split = c->hoist_split_wgs > 0;
-    if (!split) {
-      // the special-prime limbs to coefficient form (the two-phase form's
-      // column phase runs this transform itself)
-      NttJob J{};
-      J.src = u.p + (size_t)Lp * n;
-      J.sa = (long long)nm * n;
-      J.dst = ucoef.p;
-      J.da = n;
-      J.na = 2 * R;
-      J.nb = 1;
-      J.dst_prime[0] = (unsigned char)c->L;
-      Prof pr(c, "ntt_inv", 2.0 * R, 16.0 * n * 2 * R);
-      hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
-      if (e != hipSuccess) return fail(HE_EHIP, "hoisted intt: %s", hipGetErrorString(e));
-    }
     // chunks of rotations so that the multiply-accumulate's workgroups fill
     // the chip: chunks x 2 x Lp of the one-kernel form (one per compute
     // unit), chunks x 2 x Lp x blocks of the two-phase form (several per
@@ -2728,6 +2710,32 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       M.hq[t] = c->rd_hq[c->L * np + t];
       M.inv[t] = c->rd_inv[c->L * np + t];
       M.inv_sh[t] = c->rd_inv_sh[c->L * np + t];
+    }
+    {
+      I.items = items;
+      I.u = u.p;
+      I.R = R;
+      // algorithmic bytes: the keys of the R items and the shared digits
+      // once (the u written for the ModDown is an intermediate of this
+      // design, not of the key switch)
+      Prof pr(c, "hoisted_inner", (double)R, 8.0 * n * (2.0 * R * Lp * nm + Lp * nm));
+      hipError_t e = launch_inner_hoisted(c->log_n, I, c->d_primes, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "hoisted inner: %s", hipGetErrorString(e));
+    }
+    if (!split) {
+      // the special-prime limbs to coefficient form (the two-phase form's
+      // column phase runs this transform itself)
+      NttJob J{};
+      J.src = u.p + (size_t)Lp * n;
+      J.sa = (long long)nm * n;
+      J.dst = ucoef.p;
+      J.da = n;
+      J.na = 2 * R;
+      J.nb = 1;
+      J.dst_prime[0] = (unsigned char)c->L;
+      Prof pr(c, "ntt_inv", 2.0 * R, 16.0 * n * 2 * R);
+      hipError_t e = launch_ntt_inv(c->log_n, J, c->d_primes, c->tabs, c->st);
+      if (e != hipSuccess) return fail(HE_EHIP, "hoisted intt: %s", hipGetErrorString(e));
     }
     // work units: limb-NTT equivalents of butterflies (the two-phase form's
     // column phase runs the first log N - K stages, its block phase the
@@ -2930,11 +2938,13 @@ he_status he_pack(he_ctx* c, he_ct* const* parts, uint32_t n_parts, uint32_t wid
 // ---------------------------------------------------------------- raw transforms
 he_status he_ntt_forward(he_ctx* c, uint64_t* data, size_t n_polys, int32_t n_limbs) {
   if (!c || !data) return fail(HE_EINVAL, "NULL argument");
+  if ((uintptr_t)data % 16) return fail(HE_EINVAL, "data must be 16-byte aligned");
   if (n_limbs < 1 || n_limbs > c->L) return fail(HE_EINVAL, "n_limbs %d outside 1..%d", n_limbs, c->L);
   return ntt_rows(c, true, data, data, (int)n_polys, n_limbs, (long long)n_limbs * c->n, (long long)n_limbs * c->n);
 }
 he_status he_ntt_inverse(he_ctx* c, uint64_t* data, size_t n_polys, int32_t n_limbs) {
   if (!c || !data) return fail(HE_EINVAL, "NULL argument");
+  if ((uintptr_t)data % 16) return fail(HE_EINVAL, "data must be 16-byte aligned");
   if (n_limbs < 1 || n_limbs > c->L) return fail(HE_EINVAL, "n_limbs %d outside 1..%d", n_limbs, c->L);
   return ntt_rows(c, false, data, data, (int)n_polys, n_limbs, (long long)n_limbs * c->n, (long long)n_limbs * c->n);
 }
@@ -2994,6 +3004,8 @@ he_status he_tune_ntt(he_ctx* c, int32_t max_jobs, int32_t* split_jobs, double* 
   std::vector<int> cand;
   for (int j = 16; j <= max_jobs && cand.size() < 16; j *= 2) cand.push_back(j);
   const int jmax = cand.back();
+  NttShape shapes[8];
+  const int n_shapes = std::min(8, ntt_shapes(c->log_n, shapes, 8));
   DBuf buf;
   TRY(dalloc(c, buf, (size_t)jmax * n));
   HIPC(hipMemsetAsync(buf.p, 0, (size_t)jmax * n * sizeof(u64), c->st));
@@ -3005,18 +3017,27 @@ he_status he_tune_ntt(he_ctx* c, int32_t max_jobs, int32_t* split_jobs, double* 
   HIPC(hipEventCreate(&eb));
   he_status s = HE_OK;
   unsigned mask = 0;
+  unsigned char best_shape[16] = {0};
   int largest = 0;  // largest J that chose the two-phase form
   size_t row = 0;
   for (size_t ci = 0; ci < cand.size() && s == HE_OK; ci++) {
     const int J = cand[ci];
     const int nb = std::min(L, J), na = J / nb;
-    float ms[2] = {0, 0};
-    for (int mode = 0; mode < 2 && s == HE_OK; mode++) {
+    // candidate 0: the two-phase form; 1 + k: one workgroup per limb in layout k
+    std::vector<float> ms(1 + n_shapes, 0.f);
+    for (int cnd = 0; cnd < 1 + n_shapes && s == HE_OK; cnd++) {
       c->tabs = saved;
       c->tabs.tmp = tmp;
       c->tabs.tmp_words = (long long)jmax * n;
-      c->tabs.tuned = 0;
-      c->tabs.split_jobs = mode ? jmax : 0;
+      if (cnd == 0) {
+        c->tabs.tuned = 0;
+        c->tabs.split_jobs = jmax;
+      } else {
+        c->tabs.tuned = 1;
+        c->tabs.split_mask = 0;
+        c->tabs.n_buckets = 1;
+        c->tabs.shape[0] = (unsigned char)(cnd - 1);
+      }
       for (int rep = 0; rep < 6 && s == HE_OK; rep++) {  // the first repetition warms up
         if (rep == 1) (void)hipEventRecord(ea, c->st);
         s = ntt_rows(c, true, buf.p, buf.p, na, nb, (long long)nb * n, (long long)nb * n);
@@ -3024,17 +3045,21 @@ he_status he_tune_ntt(he_ctx* c, int32_t max_jobs, int32_t* split_jobs, double* 
       }
       (void)hipEventRecord(eb, c->st);
       (void)hipEventSynchronize(eb);
-      (void)hipEventElapsedTime(&ms[mode], ea, eb);
+      (void)hipEventElapsedTime(&ms[cnd], ea, eb);
     }
     if (s != HE_OK) break;
-    if (table && row + 3 <= table_cap) {
+    int win = 0;
+    for (int cnd = 1; cnd < 1 + n_shapes; cnd++)
+      if (ms[cnd] < ms[win]) win = cnd;
+    if (table && row + 2 + n_shapes <= table_cap) {
       table[row++] = J;
-      table[row++] = ms[0] / 5 * 1e3;  // us per forward + inverse pair
-      table[row++] = ms[1] / 5 * 1e3;
+      for (int cnd = 0; cnd < 1 + n_shapes; cnd++) table[row++] = ms[cnd] / 5 * 1e3;  // us per forward + inverse
     }
-    if (ms[1] < ms[0]) {
+    if (win == 0) {
       mask |= 1u << ci;
       largest = J;
+    } else {
+      best_shape[ci] = (unsigned char)(win - 1);
     }
   }
   (void)hipEventDestroy(ea);
@@ -3054,6 +3079,7 @@ he_status he_tune_ntt(he_ctx* c, int32_t max_jobs, int32_t* split_jobs, double* 
   c->tabs.tuned = 1;
   c->tabs.split_mask = mask;
   c->tabs.n_buckets = (int)cand.size();
+  for (size_t ci = 0; ci < 16; ci++) c->tabs.shape[ci] = best_shape[ci];
   if (largest > 0) {
     c->tabs.tmp = (u64*)c->pool.get((size_t)largest * n * sizeof(u64));
     if (!c->tabs.tmp) {
@@ -3066,6 +3092,19 @@ he_status he_tune_ntt(he_ctx* c, int32_t max_jobs, int32_t* split_jobs, double* 
   if (split_jobs) *split_jobs = largest;
   return HE_OK;
 }
+
+he_status he_ntt_layouts(he_ctx* c, int32_t* loge, int32_t* logr, size_t cap, size_t* count) {
+  if (!c || !count) return fail(HE_EINVAL, "NULL argument");
+  NttShape shapes[8];
+  const int k = std::min(8, ntt_shapes(c->log_n, shapes, 8));
+  *count = (size_t)k;
+  for (int i = 0; i < k && (size_t)i < cap; i++) {
+    if (loge) loge[i] = shapes[i].loge;
+    if (logr) logr[i] = shapes[i].logr;
+  }
+  return HE_OK;
+}
+
 
 // ---------------------------------------------------------------- graphs
 struct he_graph {

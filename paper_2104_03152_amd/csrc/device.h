@@ -71,7 +71,18 @@ struct NttTables {
   int tuned;
   unsigned split_mask;
   int n_buckets;
+  // plain one-workgroup-per-limb transforms: thread layout (words per
+  // thread, radix) chosen per bucket of launch size by the tuner, 0 the
+  // default layout; ntt_shapes() lists the layouts of a ring degree
+  unsigned char shape[16];
+  int layout;  // > 0: every plain one-workgroup launch uses this layout (not tuned)
 };
+// one-workgroup-per-limb thread layouts of ring degree 2^log_n: words per
+// thread (log2) and pass radix (log2) of layout i; layout 0 is the default
+struct NttShape {
+  int loge, logr, threads;
+};
+int ntt_shapes(int log_n, NttShape* out, int cap);
 hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job,
                           const PrimeDev* primes, const NttTables& tabs, hipStream_t st);
 hipError_t launch_ntt_inv(int log_n, const NttJob& job, const PrimeDev* primes,

@@ -64,13 +64,16 @@ __device__ __forceinline__ void decode_job(const NttJob& J, int w, int& a, int& 
 // 2^(LOGS - 1 - lb) + ((toff + l) >> (lb + 1)), where LOGS and toff place
 // the local array in the limb (LOGS = LOGN, toff = the workgroup's first
 // element, for contiguous blocks; LOGS = LOGM, toff = 0, for columns).
-template <int LOGM, int BLO, int BHI, int LOGE = 4>
+// LOGR caps the bits of one pass (the radix): with LOGR < LOGE a thread
+// runs E / 2^R butterfly groups per pass.
+template <int LOGM, int BLO, int BHI, int LOGE = 4, int LOGR = LOGE>
 struct Sched {
+  static_assert(LOGR <= LOGE, "a pass cannot span more words than a thread holds");
   static constexpr int M = 1 << LOGM;
   static constexpr int E = 1 << LOGE;  // words per thread
   static constexpr int T = M / E;
   static constexpr int NB = BHI - BLO;
-  static constexpr int NP = (NB + LOGE - 1) / LOGE;
+  static constexpr int NP = (NB + LOGR - 1) / LOGR;
   static constexpr int bits(int p) { return NB / NP + (p < NB % NP ? 1 : 0); }
   static constexpr int consumed(int p) {
     int s = 0;
@@ -308,16 +311,27 @@ __device__ __forceinline__ void fwd_body(const NttJob& J, const PrimeDev* __rest
 #pragma unroll
     for (int u = 0; u < G; u++) {
       const int gi = tid + C::T * u;
+      if constexpr (EPI == EPI_STORE && R >= 1) {
+        // each thread's run of 2^R consecutive words leaves as 16-byte stores
 #pragma unroll
-      for (int c = 0; c < (1 << R); c++) {
-        u64 v = ar.fwd_res(x[u * (1 << R) + c]);
-        const int idx = (gi << R) | c;
-        if (EPI == EPI_ROUNDDIV) {
-          v = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
-          if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
-          if (ad2) v = addmod(v, ad2[idx], q);
+        for (int c = 0; c < (1 << R); c += 2) {
+          ulonglong2 v2;
+          v2.x = ar.fwd_res(x[u * (1 << R) + c]);
+          v2.y = ar.fwd_res(x[u * (1 << R) + c + 1]);
+          *reinterpret_cast<ulonglong2*>(dst + ((gi << R) | c)) = v2;
         }
-        dst[idx] = v;
+      } else {
+#pragma unroll
+        for (int c = 0; c < (1 << R); c++) {
+          u64 v = ar.fwd_res(x[u * (1 << R) + c]);
+          const int idx = (gi << R) | c;
+          if (EPI == EPI_ROUNDDIV) {
+            v = shoup(submod(uu[idx], v, q), inv, inv_sh, q);
+            if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
+            if (ad2) v = addmod(v, ad2[idx], q);
+          }
+          dst[idx] = v;
+        }
       }
     }
   }
@@ -353,10 +367,20 @@ __device__ __forceinline__ void inv_body(const NttJob& J, const typename Ar::TW*
 #pragma unroll
     for (int u = 0; u < G; u++) {
       const int gi = tid + C::T * u;
+      if constexpr (!GATHER && R >= 1) {
+        // each thread's run of 2^R consecutive words arrives as 16-byte loads
 #pragma unroll
-      for (int c = 0; c < (1 << R); c++) {
-        const int idx = (gi << R) | c;
-        x[u * (1 << R) + c] = ar.from_res(src[GATHER ? gal_src(idx, LOGN, g) : idx]);
+        for (int c = 0; c < (1 << R); c += 2) {
+          const ulonglong2 v2 = *reinterpret_cast<const ulonglong2*>(src + ((gi << R) | c));
+          x[u * (1 << R) + c] = ar.from_res(v2.x);
+          x[u * (1 << R) + c + 1] = ar.from_res(v2.y);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < (1 << R); c++) {
+          const int idx = (gi << R) | c;
+          x[u * (1 << R) + c] = ar.from_res(src[GATHER ? gal_src(idx, LOGN, g) : idx]);
+        }
       }
     }
   }
@@ -386,6 +410,99 @@ k_ntt_inv(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables t
     inv_body<LOGN, GATHER, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)dp * N, P, a, b, lds);
   else
     inv_body<LOGN, GATHER, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)dp * N, P, a, b, lds);
+}
+
+// ---------------- alternative thread layouts (tuned) ----------------
+// The plain transforms (no prologue or epilogue) in other layouts: E = 2^LOGE
+// words per thread, passes of at most 2^LOGR.  Same butterflies in the same
+// order per element, so the results are identical.
+template <int LOGN, int LOGE, int LOGR>
+using Shape = Sched<LOGN, 0, LOGN, LOGE, LOGR>;
+
+template <int LOGN, bool FWD, int LOGE, int LOGR>
+__global__ void __launch_bounds__((Shape<LOGN, LOGE, LOGR>::T))
+k_ntt_shape(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  using S = Shape<LOGN, LOGE, LOGR>;
+  constexpr int N = 1 << LOGN;
+  extern __shared__ u64 lds[];
+  int a, b;
+  decode_job(J, blockIdx.x, a, b);
+  const int dp = J.dst_prime[b];
+  const PrimeDev P = primes[dp];
+  if constexpr (FWD) {
+    if (P.use_fp)
+      fwd_body<LOGN, PRO_PLAIN, EPI_STORE, FpAr, S>(J, primes,
+                                                   reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)dp * N, P,
+                                                   a, b, lds);
+    else
+      fwd_body<LOGN, PRO_PLAIN, EPI_STORE, IntAr, S>(
+          J, primes, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)dp * N, P, a, b, lds);
+  } else {
+    if (P.use_fp)
+      inv_body<LOGN, false, FpAr, S>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)dp * N, P, a, b, lds);
+    else
+      inv_body<LOGN, false, IntAr, S>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)dp * N, P, a, b,
+                                      lds);
+  }
+}
+
+// the alternative layouts per ring degree (index 1.. of ntt_shapes)
+template <int LOGN>
+struct ShapeList;
+template <>
+struct ShapeList<12> {
+  static constexpr int n = 4;
+  static constexpr int e[n] = {2, 3, 4, 4}, r[n] = {2, 2, 4, 3};
+};
+template <>
+struct ShapeList<13> {
+  static constexpr int n = 3;
+  static constexpr int e[n] = {4, 4, 3}, r[n] = {4, 3, 2};
+};
+template <>
+struct ShapeList<14> {
+  static constexpr int n = 3;
+  static constexpr int e[n] = {4, 5, 5}, r[n] = {3, 5, 4};
+};
+
+template <int LOGN, bool FWD, int I>
+hipError_t shape_launch_i(const NttJob& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st,
+                          int jobs) {
+  constexpr int LOGE = ShapeList<LOGN>::e[I], LOGR = ShapeList<LOGN>::r[I];
+  using S = Shape<LOGN, LOGE, LOGR>;
+  const size_t shm = sizeof(u64) * S::lds_words();
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ntt_shape<LOGN, FWD, LOGE, LOGR>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_ntt_shape<LOGN, FWD, LOGE, LOGR>), dim3(jobs), dim3(S::T), shm, st, J, primes, tabs);
+  return hipGetLastError();
+}
+
+template <int LOGN, bool FWD>
+hipError_t shape_launch(int id, const NttJob& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st,
+                        int jobs) {
+  switch (id) {
+    case 1: return shape_launch_i<LOGN, FWD, 0>(J, primes, tabs, st, jobs);
+    case 2: return shape_launch_i<LOGN, FWD, 1>(J, primes, tabs, st, jobs);
+    case 3: return shape_launch_i<LOGN, FWD, 2>(J, primes, tabs, st, jobs);
+    case 4:
+      if constexpr (ShapeList<LOGN>::n > 3) return shape_launch_i<LOGN, FWD, 3>(J, primes, tabs, st, jobs);
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// the tuned layout of a plain launch of `jobs` limbs (0: the default)
+int tuned_shape(const NttTables& tabs, int jobs) {
+  if (tabs.layout > 0) return tabs.layout;
+  if (!tabs.tuned) return 0;
+  int b = 0;
+  while (b + 1 < tabs.n_buckets && jobs > (16 << b)) b++;
+  return tabs.shape[b];
 }
 
 // ---------------- two-phase transforms for small batches ----------------
@@ -1388,6 +1505,10 @@ hipError_t fwd_launch(const NttJob& J, const PrimeDev* primes, const NttTables& 
     hipLaunchKernelGGL((k_ntt_fwd_b<LOGN, PRO, EPI>), dim3(jobs * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
     return hipGetLastError();
   }
+  if constexpr (PRO == PRO_PLAIN && EPI == EPI_STORE && LOGN >= 12) {
+    const int id = tuned_shape(tabs, jobs);
+    if (id > 0) return shape_launch<LOGN, true>(id, J, primes, tabs, st, jobs);
+  }
   const size_t shm = sizeof(u64) * C::lds_words();
   static bool attr = false;
   hipError_t e = set_lds(k_ntt_fwd<LOGN, PRO, EPI>, shm, attr);
@@ -1408,6 +1529,10 @@ hipError_t inv_launch(const NttJob& J, const PrimeDev* primes, const NttTables& 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ntt_inv_2<LOGN>), dim3(jobs * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes, tabs);
     return hipGetLastError();
+  }
+  if constexpr (!GATHER && LOGN >= 12) {
+    const int id = tuned_shape(tabs, jobs);
+    if (id > 0) return shape_launch<LOGN, false>(id, J, primes, tabs, st, jobs);
   }
   const size_t shm = sizeof(u64) * C::lds_words();
   static bool attr = false;
@@ -1833,4 +1958,24 @@ hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
+}
+
+int ntt_shapes(int log_n, NttShape* out, int cap) {
+  auto fill = [&](auto list, int loge0) {
+    using Lst = decltype(list);
+    int k = 0;
+    if (k < cap) out[k] = NttShape{loge0, loge0, 1 << (log_n - loge0)};
+    k++;
+    for (int i = 0; i < Lst::n; i++, k++)
+      if (k < cap) out[k] = NttShape{Lst::e[i], Lst::r[i], 1 << (log_n - Lst::e[i])};
+    return k;
+  };
+  switch (log_n) {
+    case 12: return fill(ShapeList<12>{}, single_loge(12));
+    case 13: return fill(ShapeList<13>{}, single_loge(13));
+    case 14: return fill(ShapeList<14>{}, single_loge(14));
+    default:
+      if (cap > 0) out[0] = NttShape{single_loge(log_n), single_loge(log_n), 1 << (log_n - single_loge(log_n))};
+      return 1;
+  }
 }
