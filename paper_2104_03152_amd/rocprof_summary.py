@@ -4,6 +4,7 @@ profiles/ (kernel-trace statistics, HBM traffic from PMC counters).
     python -m paper_2104_03152_amd.rocprof_summary trace <results.db> <out.md> "<command>" [bench.out]
     python -m paper_2104_03152_amd.rocprof_summary traffic <fetch.db> <write.db> \\
         <copy_fetch.db> <copy_write.db> <out.json> <out.md> "<command>"
+    python -m paper_2104_03152_amd.rocprof_summary counters <pmc.db> <out.md> "<command>" "<title>"
 
 A launch family of the library (the unit its HIP-event profile reports) is
 one kernel, or, for small batches of NTTs, a block-phase and a column-phase
@@ -178,8 +179,55 @@ def traffic(fetch_db, write_db, cfetch_db, cwrite_db, out_json, out_md, command)
         f.write("\n".join(lines) + "\n")
 
 
+def counters(db_path, out_md, command, title, top=14):
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select dispatch_id, kernel_name, counter_name, value, duration, vgpr_count, "
+                      "lds_block_size, workgroup_size from counters_collection").fetchall()
+    disp = collections.defaultdict(dict)
+    meta = {}
+    for did, name, cn, v, dur, vg, lds, wg in rows:
+        disp[did][cn] = float(v)
+        meta[did] = (name, float(dur), vg, lds, wg)
+    marks = sorted(d for d in disp if MARKER in meta[d][0])
+    lo, hi = (marks[0], marks[1]) if len(marks) >= 2 else (-1, 1 << 62)
+    per = collections.defaultdict(list)
+    for d in disp:
+        if lo < d < hi and MARKER not in meta[d][0]:
+            per[short(meta[d][0])].append(d)
+    lines = ["# %s" % title, "", "Command (run from the repository root):", "", "    " + command, "",
+             "Per kernel over the profiled dispatches: VALUBusy (% of the time the vector ALUs issue), "
+             "VALUUtilization (% of active lanes when they do), OccupancyPercent (% of the wave slots "
+             "held), LDSBankConflict (% of the time LDS is stalled by bank conflicts), and VALU, LDS "
+             "instructions and LDS wait cycles per wave (SQ_INSTS_VALU, SQ_INSTS_LDS, SQ_WAIT_INST_LDS "
+             "over SQ_WAVES); duration-weighted means.", "",
+             "| kernel | calls | avg us | VGPRs | LDS KiB | VALUBusy % | VALUUtil % | Occupancy % | "
+             "LDS conflict % | VALU/wave | LDS/wave | LDS wait/wave |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    order = sorted(per.items(), key=lambda kv: -sum(meta[d][1] for d in kv[1]))[:top]
+    for k, ds in order:
+        tw = sum(meta[d][1] for d in ds) or 1.0
+
+        def wavg(c):
+            return sum(disp[d].get(c, 0.0) * meta[d][1] for d in ds) / tw
+
+        waves = sum(disp[d].get("SQ_WAVES", 0.0) for d in ds) or 1.0
+
+        def pw(c):
+            return sum(disp[d].get(c, 0.0) for d in ds) / waves
+
+        _, _, vg, lds, _ = meta[ds[0]]
+        lines.append("| `%s` | %d | %.2f | %d | %.1f | %.1f | %.1f | %.1f | %.2f | %.0f | %.0f | %.0f |" % (
+            k.split("(")[0][:60], len(ds), tw / len(ds) / 1e3, vg, lds / 1024.0, wavg("VALUBusy"),
+            wavg("VALUUtilization"), wavg("OccupancyPercent"), wavg("LDSBankConflict"), pw("SQ_INSTS_VALU"),
+            pw("SQ_INSTS_LDS"), pw("SQ_WAIT_INST_LDS")))
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5] if len(sys.argv) > 5 else None)
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     else:
         traffic(*sys.argv[2:9])
