@@ -2650,7 +2650,9 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     DBuf coef, ext, u, ucoef;
     KsJob K;
     KsBufs bufs;
-    TRY(dalloc(c, u, (size_t)R * 2 * nm * n));
+    const bool split = c->hoist_split_wgs > 0;
+    // the two-phase form computes the inner products where it uses them
+    if (!split) TRY(dalloc(c, u, (size_t)R * 2 * nm * n));
     TRY(dalloc(c, ucoef, (size_t)R * 2 * n));
     const u64* c1 = x->d + (size_t)Lp * n;
     const u64* extp = nullptr;
@@ -2678,7 +2680,6 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     I.t_begin = 0;
     I.t_end = nm;
     I.special_prime = c->L;
-    const bool split = c->hoist_split_wgs > 0;
     // chunks of rotations so that the multiply-accumulate's workgroups fill
     // the chip: chunks x 2 x Lp of the one-kernel form (one per compute
     // unit), chunks x 2 x Lp x blocks of the two-phase form (several per
@@ -2704,6 +2705,13 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     M.chunk = chunk;
     M.n_units = n_chunks * Lp;
     M.special_prime = c->L;
+    M.ext = extp;
+    M.c1 = c1;
+    M.c0 = x->d;
+    for (int t = 0; t < Lp; t++) {
+      M.pq[t] = I.pq[t];
+      M.pq_sh[t] = I.pq_sh[t];
+    }
     M.h_src = (c->q[c->L] - 1) / 2;
     const size_t np = c->q.size();
     for (int t = 0; t < Lp; t++) {
@@ -2711,7 +2719,7 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
       M.inv[t] = c->rd_inv[c->L * np + t];
       M.inv_sh[t] = c->rd_inv_sh[c->L * np + t];
     }
-    {
+    if (!split) {
       I.items = items;
       I.u = u.p;
       I.R = R;
@@ -2743,18 +2751,20 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     const double nt = 2.0 * R * Lp;
     const int kb = (c->log_n + 1) / 2;
     if (split) {
-      // the inverse transform of every (item, poly) special limb, the column
-      // stages of every (item, poly, limb); the special limbs read, every
-      // (item, poly, limb) written
-      Prof pa(c, "hoisted_cols", 2.0 * R + nt * (c->log_n - kb) / c->log_n, 8.0 * n * (2.0 * R + nt));
+      // the inner product and inverse transform of every (item, poly)
+      // special limb, the column stages of every (item, poly, limb): the
+      // keys' special-prime rows (R x 2 x Lp limbs) read, every (item,
+      // poly, limb) written
+      Prof pa(c, "hoisted_cols", 2.0 * R + nt * (c->log_n - kb) / c->log_n, 8.0 * n * (2.0 * R * Lp + nt));
       hipError_t e = launch_hoisted_cols(c->log_n, M, c->d_primes, c->tabs, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted columns: %s", hipGetErrorString(e));
     }
     // per (item, poly, limb): the special limb's transform (its column-phase
-    // output in the two-phase form), u limb and diagonal read, and the
-    // partial sums written once per chunk
+    // output in the two-phase form), the u limb (in the two-phase form the
+    // key's Lp words of the inner product instead) and the diagonal read,
+    // and the partial sums written once per chunk
     Prof pr(c, diags ? "hoisted_moddown" : "hoisted_replication", split ? nt * kb / c->log_n : nt,
-            8.0 * n * ((diags ? 3.0 : 2.0) * nt + 2.0 * n_chunks * Lp));
+            8.0 * n * ((split ? 1.0 + Lp : 2.0) * nt + (diags ? nt : 0.0) + 2.0 * n_chunks * Lp));
     hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "hoisted moddown: %s", hipGetErrorString(e));
   }

@@ -286,13 +286,22 @@ hipError_t launch_inner_hoisted(int log_n, const HoistInner& job, const PrimeDev
 // two-phase NTTs do: the column phase (the special limb's inverse transform,
 // then for every modulus the lift and the forward column stages, into mid),
 // then a block kernel whose workgroups (chunk, poly, modulus, block) finish
-// their block's stages item after item and accumulate.
+// their block's stages item after item and accumulate.  The two-phase form
+// computes u itself where it is used (the special limb in the kernel before
+// the column phase, the data limbs in the block kernel), from the shared
+// digits and the keys: u is never stored.
 struct HoistMac {
   // [R][2][N] special-prime limb of u: coefficient form (one-kernel form);
   // the two-phase form's column phase writes there the inverse transform's
   // block-phase output
   const u64* ucoef;
-  const u64* u;      // [R][2][nm][N]
+  const u64* u;      // [R][2][nm][N] (one-kernel form)
+  // two-phase form: the ModUp digits [n_dig][nm][N] shared by the items,
+  // the input's polys [n_dig][N] (NTT domain) and p mod q_t (+ Shoup)
+  const u64* ext;
+  const u64* c1;
+  const u64* c0;
+  u64 pq[HE_MAXM], pq_sh[HE_MAXM];
   const u64* diags;  // [n_diag][n_dig][N] plaintext diagonals (NTT domain)
   const HoistItem* items;
   u64* partial;      // [n_chunks][2][n_dig][N]

@@ -762,8 +762,7 @@ k_ntt_fwd_b(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables
 }
 
 // TAG names the launch family: 0 plain inverse, 1 the first kernel of a
-// fused key-switch ModUp, 2 that of a fused rescale, 3 that of the hoisted
-// multiply-accumulate's column phase
+// fused key-switch ModUp, 2 that of a fused rescale
 template <int LOGN, bool GATHER, int TAG>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ntt_inv_1(const NttJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
@@ -1258,6 +1257,110 @@ k_hoist_mac(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTabl
 }
 
 // ---------------- hoisted multiply-accumulate, two-phase form ----------------
+// u[r][k][t] at the words idx[] (the hoisted inner product, computed where
+// it is consumed): sum_j D_{j,t}[src_r(i)] * key_r[j][k][t][i], with D_{j,t}
+// the shared ModUp digit (the input's c1 itself for j = t), plus
+// p * c0[t][src_r(i)] for poly 0 of a data limb.  t = n_dig is the special
+// prime's slot.  Key words pass once (non-temporal); the digits stay in L2.
+template <int LOGN, int E, int UNROLL = 1>
+__device__ __forceinline__ void hoist_inner_at(const HoistMac& J, const HoistItem& it, const PrimeDev& P, int k,
+                                               int t, const int (&idx)[E], u64 (&r)[E]) {
+  constexpr size_t N = (size_t)1 << LOGN;
+  const bool special = t >= J.n_dig;
+  const int kt = special ? it.km - 1 : t;
+  const u64* __restrict__ kp = it.key + ((size_t)k * it.km + kt) * N;
+  const size_t ks_j = 2 * (size_t)it.km * N;
+  int src[E];
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    src[e] = gal_src(idx[e], LOGN, it.g);
+    r[e] = 0;
+  }
+  for (int j0 = 0; j0 < J.n_dig; j0 += 8) {
+    U128 acc[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) acc[e] = U128{0, 0};
+    const int j1 = min(J.n_dig, j0 + 8);
+#pragma unroll UNROLL
+    for (int j = j0; j < j1; j++) {
+      const u64* __restrict__ dj = (j == t) ? J.c1 + (size_t)t * N : J.ext + ((size_t)j * J.nm + t) * N;
+      u64 d[E], kv[E];
+#pragma unroll
+      for (int e = 0; e < E; e++) {
+        d[e] = dj[src[e]];
+        kv[e] = __builtin_nontemporal_load(kp + j * ks_j + idx[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < E; e++) acc[e] = add128(acc[e], mul_wide(d[e], kv[e]));
+    }
+#pragma unroll
+    for (int e = 0; e < E; e++) r[e] = addmod(r[e], mont_reduce(acc[e], P), P.q);
+  }
+  if (!special && k == 0) {
+    const u64* __restrict__ c0 = J.c0 + (size_t)t * N;
+#pragma unroll
+    for (int e = 0; e < E; e++) r[e] = addmod(r[e], shoup(c0[src[e]], J.pq[t], J.pq_sh[t], P.q), P.q);
+  }
+}
+
+// Special-prime limb of item a / 2, poly a % 2: its inner product on block
+// sub and the inverse transform's block stages, into ucoef (the column
+// phase below finishes the transform).
+template <int LOGN, class Ar>
+__device__ __forceinline__ void hoist_special_body(const HoistMac& J, const typename Ar::TW* __restrict__ W,
+                                                   const PrimeDev& P, int a, int sub, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  constexpr int E = S::E;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const int toff = sub << Sp::LOGMB;
+  PassTw<S, LOGN, 0, false, Ar> tw0;
+  tw0.load(W, tid, toff);
+  typename Ar::T x[E];
+  {
+    constexpr int R = S::bits(0), G = E >> R;
+    int idx[E];
+    u64 v[E];
+#pragma unroll
+    for (int u = 0; u < G; u++)
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) idx[u * (1 << R) + c] = toff + (((tid + S::T * u) << R) | c);
+    hoist_inner_at<LOGN, E, 2>(J, J.items[a >> 1], P, a & 1, J.n_dig, idx, v);
+#pragma unroll
+    for (int i = 0; i < E; i++) x[i] = ar.from_res(v[i]);
+  }
+  inv_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = E >> R;
+    u64* __restrict__ t = const_cast<u64*>(J.ucoef) + ((size_t)a << LOGN) + toff;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) t[gidx(gi, c, LO, R)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+k_hoist_special(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  using Sp = Split<LOGN>;
+  __shared__ u64 lds[Sp::SB::lds_words()];
+  const int a = blockIdx.x / Sp::WB;
+  const int sub = blockIdx.x - a * Sp::WB;
+  const int sp = J.special_prime;
+  const PrimeDev P = primes[sp];
+  if (P.use_fp)
+    hoist_special_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)sp * N, P, a, sub,
+                                   lds);
+  else
+    hoist_special_body<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)sp * N, P, a, sub,
+                                    lds);
+}
+
 // Column phase, workgroup (a, sub) for item a / 2, poly a % 2 and the 16
 // columns of group sub: the inverse transform's column stages finish the
 // special-prime limb's coefficients in these columns (its block stages ran
@@ -1400,33 +1503,41 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
   }
   for (int r = rb; r < re; r++) {
     const HoistItem it = J.items[r];
+    // the thread index, opaque to the compiler inside each iteration: the
+    // per-thread addresses are recomputed per item instead of being held
+    // in registers across the loop (which spills)
+    int tr = tid;
+    asm volatile("" : "+v"(tr));
     typename Ar::T x[S::E];
 #pragma unroll
     for (int e = 0; e < S::E; e++) x[e] = Ar::unbits(nx[e]);
-    if (r + 1 < re) {
-      const u64* __restrict__ src = J.mid + (((size_t)(r + 1) * 2 + k) * J.n_dig + t) * N + toff;
-#pragma unroll
-      for (int u = 0; u < G0; u++) {
-        const int gi = tid + S::T * u;
-#pragma unroll
-        for (int c = 0; c < (1 << R0); c++) nx[u * (1 << R0) + c] = src[gidx(gi, c, LO0, R0)];
-      }
-    }
-    // the epilogue's operands, all loads issued together
-    const u64* __restrict__ uw = J.u + (((size_t)r * 2 + k) * J.nm + t) * N;
+    // the epilogue's operands: the diagonal words, and this item's inner
+    // product at the thread's output words
     const u64* __restrict__ dg = DIAG ? J.diags + ((size_t)it.diag * J.n_dig + t) * N : nullptr;
+    int oidx[S::E];
     u64 uv[S::E], dv[S::E];
 #pragma unroll
     for (int u = 0; u < GF; u++) {
 #pragma unroll
       for (int c = 0; c < (1 << RF); c++) {
         const int e = u * (1 << RF) + c;
-        const int idx = toff + (((tid + S::T * u) << RF) | c);
-        uv[e] = uw[idx];
-        dv[e] = DIAG ? dg[idx] : 0;
+        oidx[e] = toff + (((tr + S::T * u) << RF) | c);
+        dv[e] = DIAG ? dg[oidx[e]] : 0;
       }
     }
-    fwd_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+    hoist_inner_at<LOGN, S::E>(J, it, P, k, t, oidx, uv);
+    // the next item's column-phase output, in flight during the transform
+    asm volatile("" : "+v"(tr));
+    if (r + 1 < re) {
+      const u64* __restrict__ src = J.mid + (((size_t)(r + 1) * 2 + k) * J.n_dig + t) * N + toff;
+#pragma unroll
+      for (int u = 0; u < G0; u++) {
+        const int gi = tr + S::T * u;
+#pragma unroll
+        for (int c = 0; c < (1 << R0); c++) nx[u * (1 << R0) + c] = src[gidx(gi, c, LO0, R0)];
+      }
+    }
+    fwd_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tr, toff, &tw0);
 #pragma unroll
     for (int e = 0; e < S::E; e++) {
       u64 ks = shoup(submod(uv[e], ar.fwd_res(x[e]), q), inv, inv_sh, q);
@@ -1563,16 +1674,10 @@ hipError_t hoist_launch_as(const HoistMac& J, const PrimeDev* primes, const NttT
 template <int LOGN>
 hipError_t hoist_cols_launch(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
   using Sp = Split<LOGN>;
-  if (J.R <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || J.nm != J.n_dig + 1 || !J.mid || !J.ucoef)
+  if (J.R <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || J.nm != J.n_dig + 1 || !J.mid || !J.ucoef || !J.ext ||
+      !J.c1 || !J.c0 || !J.items)
     return hipErrorInvalidValue;
-  NttJob I{};
-  I.src = J.u + ((size_t)J.n_dig << LOGN);
-  I.sa = (long long)J.nm << LOGN;
-  I.na = 2 * J.R;
-  I.nb = 1;
-  I.dst_prime[0] = (unsigned char)J.special_prime;
-  I.mid = const_cast<u64*>(J.ucoef);
-  hipLaunchKernelGGL((k_ntt_inv_1<LOGN, false, 3>), dim3(I.na * Sp::WB), dim3(Sp::SB::T), 0, st, I, primes, tabs);
+  hipLaunchKernelGGL((k_hoist_special<LOGN>), dim3(2 * J.R * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes, tabs);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_hoist_cols<LOGN>), dim3(2 * J.R * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes, tabs);
@@ -1584,7 +1689,8 @@ template <int LOGN, bool DIAG>
 hipError_t hoist_split_launch_as(const HoistMac& J, const PrimeDev* primes, const NttTables& tabs, hipStream_t st) {
   using Sp = Split<LOGN>;
   const int n_chunks = J.chunk > 0 ? (J.R + J.chunk - 1) / J.chunk : 0;
-  if (n_chunks <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || !J.mid) return hipErrorInvalidValue;
+  if (n_chunks <= 0 || J.n_dig <= 0 || J.n_dig > HE_MAXM || !J.mid || !J.ext || !J.c1 || !J.c0 || !J.items)
+    return hipErrorInvalidValue;
   HoistMac B = J;
   B.n_units = n_chunks * J.n_dig * Sp::WB;
   const int blocks = ((B.n_units + 7) / 8) * 16;
