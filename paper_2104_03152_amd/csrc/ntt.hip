@@ -1466,6 +1466,14 @@ k_hoist_cols(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTab
   }
 }
 
+// waves per SIMD of the block kernel (four: at most 128 VGPRs), and the
+// digits of one item's inner product whose loads are in flight together
+#ifndef HE_HOIST_B_WAVES
+#define HE_HOIST_B_WAVES 4
+#endif
+#ifndef HE_HOIST_B_UNROLL
+#define HE_HOIST_B_UNROLL 1
+#endif
 // Block phase: workgroup (chunk, k, t, sub) finishes block sub of every
 // item's transform in modulus t, poly k, and keeps the running sums of its
 // E words in registers.
@@ -1525,7 +1533,7 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
         dv[e] = DIAG ? dg[oidx[e]] : 0;
       }
     }
-    hoist_inner_at<LOGN, S::E>(J, it, P, k, t, oidx, uv);
+    hoist_inner_at<LOGN, S::E, HE_HOIST_B_UNROLL>(J, it, P, k, t, oidx, uv);
     // the next item's column-phase output, in flight during the transform
     asm volatile("" : "+v"(tr));
     if (r + 1 < re) {
@@ -1558,9 +1566,9 @@ __device__ __forceinline__ void hoist_b_body(const HoistMac& J, const typename A
 
 // unit = (chunk * n_dig + t) * WB + sub; block b runs on XCD b % 8, and
 // blocks b and b + 8 are the two polys of one unit (the diagonal block is
-// read twice from that XCD's L2).  Four waves per SIMD: at most 128 VGPRs.
+// read twice from that XCD's L2).
 template <int LOGN, bool DIAG>
-__global__ void __launch_bounds__(Split<LOGN>::SB::T, 4)
+__global__ void __launch_bounds__(Split<LOGN>::SB::T, HE_HOIST_B_WAVES)
 k_hoist_mac_b(const HoistMac J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   using Sp = Split<LOGN>;
   constexpr int N = 1 << LOGN;
