@@ -481,8 +481,10 @@ def main():
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 BUTTERFLY_INSTR = 11
 SINGLE_KERNEL_FAMILIES = ("hoisted_moddown", "hoisted_replication", "hoisted_inner", "keyswitch_inner")
-NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale", "hoisted_cols", "hoisted_moddown",
-                "hoisted_replication")
+NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "modup", "moddown", "rescale")
+# key-switch inner products fused with transforms (the two-phase hoisted
+# product): their algorithmic bytes are the key words they read
+FUSED_FAMILIES = ("hoisted_cols", "hoisted_moddown", "hoisted_replication")
 
 
 def cnn_step_algorithmic_bytes(n):
@@ -529,28 +531,63 @@ def roofline_entry(fam, p, n):
                 "hbm_gbs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS,
                 "avg_launch_us": p["avg_launch_us"], "units_per_launch": p["units_per_launch"],
                 "algorithmic_bytes_per_launch": p["bytes_per_launch"]}
+    if fam in FUSED_FAMILIES:
+        # both roofs: the key reads against HBM, the measured VALU issue
+        # (counters of the committed profile, when it matches the source)
+        valu = pmc_valu(fam)
+        bfly = p["units_per_launch"] * (n // 2) * (n.bit_length() - 1)
+        return {"bound": "hbm", "family": fam, "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm / HBM_PEAK_GBS, "traffic": traffic, "traffic_over_algorithmic": ratio,
+                "valu_busy_pct": valu,
+                "binding": None if valu is None else ("valu" if valu / 100 > hbm / HBM_PEAK_GBS else "hbm"),
+                "butterfly_frac": bfly / (p["avg_launch_us"] * 1e-6) / (VALU_LANE_OPS / BUTTERFLY_INSTR),
+                "avg_launch_us": p["avg_launch_us"], "algorithmic_bytes_per_launch": p["bytes_per_launch"],
+                "algorithmic": "the key words of the launch's rotations and the diagonals, read once (the "
+                               "column-phase output and the partial sums are intermediates of this design)"}
     return {"bound": "hbm", "family": fam, "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": hbm / HBM_PEAK_GBS, "traffic": traffic, "traffic_over_algorithmic": ratio,
             "avg_launch_us": p["avg_launch_us"], "algorithmic_bytes_per_launch": p["bytes_per_launch"],
             "algorithmic": "the keys of the launch's rotations and their shared ModUp digits, read once"}
 
 
-def pmc_traffic(fam):
-    """HBM bytes per launch measured by rocprofv3 PMC counters (FETCH_SIZE,
-    WRITE_SIZE, calibrated by a copy kernel), valid only while the kernel
-    source is unchanged since the counters were taken."""
+def source_hash():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
     src = os.path.join(ROOT, "paper_2104_03152_amd", "csrc")
     h = hashlib.sha256()
     for name in ("ntt.hip", "kernels.hip", "modarith.h", "butterfly.h", "device.h"):
         with open(os.path.join(src, name), "rb") as f:
             h.update(f.read())
-    if rec.get("source_sha256") != h.hexdigest():
+    return h.hexdigest()
+
+
+def pmc_valu(fam):
+    """Duration-weighted VALUBusy (%) of a family's kernels from the committed
+    counter profile of the CNN step, or None when the kernel source changed
+    since it was taken."""
+    from paper_2104_03152_amd.rocprof_summary import FAMILIES
+    path = os.path.join(ROOT, "profiles", "cnn_n8192_valu_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != source_hash():
+        return None
+    frags = [fr for name, first, rest in FAMILIES if name == fam for fr in first + rest]
+    ks = [v for k, v in rec.get("kernels", {}).items() if any(fr.split("(")[0] in k for fr in frags)]
+    w = sum(v["calls"] * v["avg_us"] for v in ks)
+    return sum(v["valu_busy_pct"] * v["calls"] * v["avg_us"] for v in ks) / w if w else None
+
+
+def pmc_traffic(fam):
+    """HBM bytes per launch measured by rocprofv3 PMC counters (FETCH_SIZE,
+    WRITE_SIZE, calibrated by a copy kernel), valid only while the kernel
+    source is unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != source_hash():
         return None
     return rec.get("families", {}).get(fam)
 

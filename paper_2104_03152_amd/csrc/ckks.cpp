@@ -2752,19 +2752,23 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     const int kb = (c->log_n + 1) / 2;
     if (split) {
       // the inner product and inverse transform of every (item, poly)
-      // special limb, the column stages of every (item, poly, limb): the
-      // keys' special-prime rows (R x 2 x Lp limbs) read, every (item,
-      // poly, limb) written
-      Prof pa(c, "hoisted_cols", 2.0 * R + nt * (c->log_n - kb) / c->log_n, 8.0 * n * (2.0 * R * Lp + nt));
+      // special limb, the column stages of every (item, poly, limb).
+      // Algorithmic bytes: the keys' special-prime rows (R x 2 x Lp limbs)
+      // and the shared digits' special limbs (the column-phase output is an
+      // intermediate of this design)
+      Prof pa(c, "hoisted_cols", 2.0 * R + nt * (c->log_n - kb) / c->log_n, 8.0 * n * (2.0 * R * Lp + Lp));
       hipError_t e = launch_hoisted_cols(c->log_n, M, c->d_primes, c->tabs, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "hoisted columns: %s", hipGetErrorString(e));
     }
-    // per (item, poly, limb): the special limb's transform (its column-phase
-    // output in the two-phase form), the u limb (in the two-phase form the
-    // key's Lp words of the inner product instead) and the diagonal read,
-    // and the partial sums written once per chunk
+    // algorithmic bytes per (item, poly, limb): the two-phase form reads the
+    // key's Lp words of the inner product and the diagonal (the column-phase
+    // output and the partial sums are intermediates of this design, and the
+    // shared digits are read once: Lp x Lp limbs); the one-kernel form reads
+    // the u limb, the special limb's coefficients and the diagonal, and
+    // writes the partial sums
     Prof pr(c, diags ? "hoisted_moddown" : "hoisted_replication", split ? nt * kb / c->log_n : nt,
-            8.0 * n * ((split ? 1.0 + Lp : 2.0) * nt + (diags ? nt : 0.0) + 2.0 * n_chunks * Lp));
+            split ? 8.0 * n * (Lp * nt + (diags ? nt : 0.0) + (double)Lp * Lp)
+                  : 8.0 * n * (2.0 * nt + (diags ? nt : 0.0) + 2.0 * n_chunks * Lp));
     hipError_t e = launch_hoisted_moddown_mac(c->log_n, M, c->d_primes, c->tabs, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "hoisted moddown: %s", hipGetErrorString(e));
   }

@@ -44,7 +44,7 @@ FAMILIES = [
     ("rescale", ["k_ntt_inv_1<13, false, 2>"], ["k_ks_moddown_cols<13, 1>", "k_ntt_fwd_b<13, 3, 1>"]),
     ("moddown+rescale (one workgroup per limb)", ["k_ntt_fwd_a<13, 2>", "k_ntt_fwd<13, 2, 1>"],
      ["k_ntt_fwd_b<13, 2, 1>"]),
-    ("hoisted_cols", ["k_ntt_inv_1<13, false, 3>"], ["k_hoist_cols<13>"]),
+    ("hoisted_cols", ["k_hoist_special<13>"], ["k_hoist_cols<13>"]),
     ("hoisted_moddown", ["k_hoist_mac<13, true>", "k_hoist_mac_b<13, true>"], []),
     ("hoisted_replication", ["k_hoist_mac<13, false>", "k_hoist_mac_b<13, false>"], []),
     ("hoisted_inner", ["k_inner_hoisted"], []),
@@ -204,6 +204,7 @@ def counters(db_path, out_md, command, title, top=14):
              "LDS conflict % | VALU/wave | LDS/wave | LDS wait/wave |",
              "|---|---|---|---|---|---|---|---|---|---|---|---|"]
     order = sorted(per.items(), key=lambda kv: -sum(meta[d][1] for d in kv[1]))[:top]
+    kernels = {}
     for k, ds in order:
         tw = sum(meta[d][1] for d in ds) or 1.0
 
@@ -216,12 +217,19 @@ def counters(db_path, out_md, command, title, top=14):
             return sum(disp[d].get(c, 0.0) for d in ds) / waves
 
         _, _, vg, lds, _ = meta[ds[0]]
+        kernels[k.split("(")[0]] = {"calls": len(ds), "avg_us": tw / len(ds) / 1e3, "valu_busy_pct": wavg("VALUBusy"),
+                                    "valu_util_pct": wavg("VALUUtilization"),
+                                    "occupancy_pct": wavg("OccupancyPercent"),
+                                    "valu_insts_per_wave": pw("SQ_INSTS_VALU")}
         lines.append("| `%s` | %d | %.2f | %d | %.1f | %.1f | %.1f | %.1f | %.2f | %.0f | %.0f | %.0f |" % (
             k.split("(")[0][:60], len(ds), tw / len(ds) / 1e3, vg, lds / 1024.0, wavg("VALUBusy"),
             wavg("VALUUtilization"), wavg("OccupancyPercent"), wavg("LDSBankConflict"), pw("SQ_INSTS_VALU"),
             pw("SQ_INSTS_LDS"), pw("SQ_WAIT_INST_LDS")))
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
+    rec = {"source_sha256": source_sha(), "command": command, "kernels": kernels}
+    with open(os.path.splitext(out_md)[0] + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
 
 
 if __name__ == "__main__":
