@@ -641,23 +641,71 @@ static he_status moddown_fused(he_ctx* c, KsJob& K, const Addend& add, u64* out)
   return HE_OK;
 }
 
+// ModDown fused with the rescale that follows it: out [B][2][l][N] =
+// Rescale(ModDown(inner products) + addends), l = Lp - 1 (the division by p
+// and by q_l with both roundings of the two separate steps, in three
+// launches instead of six)
+static he_status moddown_rescale_fused(he_ctx* c, KsJob& K, const Addend& add, u64* out) {
+  const int n = c->n, B = K.B, Lp = K.Lp, nm = K.nm, l = Lp - 1;
+  K.out = out;
+  K.oa = (long long)l * n;
+  K.add = add.p;
+  K.aa = add.aa;
+  K.add_even_only = add.even_only;
+  K.add_gather = add.gals ? 1 : 0;
+  K.add2 = add.p2;
+  K.a2a = add.a2a;
+  K.resc = 1;
+  const size_t np = c->q.size();
+  K.pl = c->q[c->L] % c->q[l];
+  K.pl_sh = h_shoup(K.pl, c->q[l]);
+  K.h_l = (c->q[l] - 1) / 2;
+  for (int t = 0; t < l; t++) {
+    K.hq2[t] = c->rd_hq[l * np + t];
+    K.inv2[t] = c->rd_inv[l * np + t];
+    K.inv2_sh[t] = c->rd_inv_sh[l * np + t];
+  }
+  const double adds = (add.p ? (add.even_only ? 1.0 : 2.0) : 0.0) + (add.p2 ? 2.0 : 0.0);
+  int distinct = 0;
+  for (int b = 0; b < B; b++) {
+    bool seen = false;
+    for (int a = 0; a < b; a++) seen |= K.key[a] == K.key[b];
+    distinct += seen ? 0 : 1;
+  }
+  // as the ModDown (keys, digits, addends) with l limbs written per poly
+  Prof pr(c, "moddown", 2.0 * B * (1 + Lp),
+          8.0 * n * (2.0 * distinct * Lp * nm + B * (Lp * nm + 2.0 * l + adds * Lp)));
+  hipError_t e = launch_ks_special_blocks(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e == hipSuccess) e = launch_ks_moddown_resc_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e == hipSuccess) e = launch_ks_moddown_resc_blocks(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "fused moddown + rescale: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
 // Key switch of B polynomials at level l: item b's input d + b*ds (NTT domain
 // [l+1][N]), read at the Galois source of gals[b] when gals is given (the
 // rotated poly without materialising it), with keys[b];
-// out [B][2][l+1][N] = KeySwitch(d_b) + addends.
+// out [B][2][l+1][N] = KeySwitch(d_b) + addends, or with resc (only where
+// ks_fusable(c, B, l + 1) and l >= 1) out [B][2][l][N] = that rescaled.
 he_status key_switch(he_ctx* c, int B, const u64* d, long long ds, int l, const Key* const* keys,
-                     const u64* gals, Addend add, u64* out) {
+                     const u64* gals, Addend add, u64* out, bool resc = false) {
   const int n = c->n, Lp = l + 1, nm = Lp + 1;
   if (B < 1 || B > HE_MAX_BATCH) return fail(HE_EINVAL, "key-switch batch of %d", B);
   for (int b = 0; b < B; b++)
     if (keys[b]->ml < l)
       return fail(HE_ENOKEY, "key valid up to level %d, ciphertext at level %d", keys[b]->ml, l);
+  if (resc && (l < 1 || !ks_fusable(c, B, Lp))) return fail(HE_EINVAL, "fused rescale outside the fused form");
   if (ks_fusable(c, B, Lp)) {
     KsJob K;
     KsBufs bufs;
     TRY(ks_prepare(c, B, d, ds, l, keys, gals, K, bufs, true));
+    DBuf t3b;
+    if (resc) {
+      TRY(dalloc(c, t3b, (size_t)2 * B * n));
+      K.t3b = t3b.p;
+    }
     TRY(modup_fused(c, K, gals != nullptr));
-    return moddown_fused(c, K, add, out);
+    return resc ? moddown_rescale_fused(c, K, add, out) : moddown_fused(c, K, add, out);
   }
   DBuf coef, ext, u, ucoef;
   TRY(dalloc(c, coef, (size_t)B * Lp * n));
@@ -1539,12 +1587,17 @@ he_status he_mul_plain(he_ctx* c, const he_ct* a, const he_pt* p, he_ct** out) {
   return maybe_rescale(c, r, out);
 }
 
-static he_status mul_relin_raw(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
+// the product, relinearised; with resc where the fused key switch applies,
+// also rescaled (*rescaled says whether it was)
+static he_status mul_relin_raw(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out, bool resc = false,
+                               bool* rescaled = nullptr) {
   if (!c->have_keys) return fail(HE_ENOKEY, "no relinearisation key");
   const he_ct *x, *y;
   CtGuard gx, gy;
   TRY(align2(c, a, b, &x, &y, gx, gy));
   const int l = x->level, Lp = l + 1, n = c->n;
+  const bool fuse = resc && l >= 1 && ks_fusable(c, 1, Lp);
+  if (rescaled) *rescaled = fuse;
   he_ct* r = nullptr;
   TRY(new_ct(c, l, a->scale * b->scale, &r));
   DBuf d2;
@@ -1554,18 +1607,26 @@ static he_status mul_relin_raw(he_ctx* c, const he_ct* a, const he_ct* b, he_ct*
     hipError_t e = launch_tensor(c->log_n, x->d, y->d, r->d, d2.p, mods_range(Lp), c->d_primes, c->st);
     if (e != hipSuccess) s = fail(HE_EHIP, "tensor: %s", hipGetErrorString(e));
   }
+  he_ct* f = nullptr;
+  if (s == HE_OK && fuse) s = new_ct(c, l - 1, a->scale * b->scale / (double)c->q[l], &f);
   if (s == HE_OK) {
     const Key* kp = &c->relin;
     Addend add;
     add.p = r->d;
     add.aa = (long long)Lp * n;
-    s = key_switch(c, 1, d2.p, 0, l, &kp, nullptr, add, r->d);
+    s = key_switch(c, 1, d2.p, 0, l, &kp, nullptr, add, fuse ? f->d : r->d, fuse);
   }
   if (s != HE_OK) {
+    he_ct_free(f);
     he_ct_free(r);
     return s;
   }
-  *out = r;
+  if (fuse) {
+    he_ct_free(r);
+    *out = f;
+  } else {
+    *out = r;
+  }
   return HE_OK;
 }
 
@@ -1575,7 +1636,12 @@ he_status he_mul_relin(he_ctx* c, const he_ct* a, const he_ct* b, he_ct** out) {
   if (!c || !a || !b || !out) return fail(HE_EINVAL, "NULL argument");
   *out = nullptr;
   he_ct* r = nullptr;
-  TRY(mul_relin_raw(c, a, b, &r));
+  bool rescaled = false;
+  TRY(mul_relin_raw(c, a, b, &r, c->auto_rescale, &rescaled));
+  if (rescaled) {
+    *out = r;
+    return HE_OK;
+  }
   return maybe_rescale(c, r, out);
 }
 
@@ -1864,8 +1930,16 @@ static he_status mul_relin_many_impl(he_ctx* c, const he_ct* const* a, const he_
       Bl.p[k] = b[i0 + k]->d;
       keys[k] = &a[i0 + k]->ctx->relin;
     }
+    // with automatic rescaling, the fused key switch rescales in its last
+    // kernels where it applies
+    const bool fuse = c->auto_rescale && ks_fusable(c, B, Lp);
     u64* R = (u64*)c->pool.get((size_t)B * ct_words(c, l) * sizeof(u64));
     if (!R) return fail(HE_EOOM, "batch allocation failed");
+    u64* F = fuse ? (u64*)c->pool.get((size_t)B * ct_words(c, l - 1) * sizeof(u64)) : nullptr;
+    if (fuse && !F) {
+      c->pool.put(R);
+      return fail(HE_EOOM, "batch allocation failed");
+    }
     DBuf d2;
     he_status s = dalloc(c, d2, (size_t)B * Lp * nn);
     if (s == HE_OK) {
@@ -1877,11 +1951,16 @@ static he_status mul_relin_many_impl(he_ctx* c, const he_ct* const* a, const he_
       Addend add;
       add.p = R;
       add.aa = (long long)Lp * nn;
-      s = key_switch(c, B, d2.p, (long long)Lp * nn, l, keys, nullptr, add, R);
+      s = key_switch(c, B, d2.p, (long long)Lp * nn, l, keys, nullptr, add, fuse ? F : R, fuse);
     }
     u64* O = R;
     int lo = l;
-    if (s == HE_OK && c->auto_rescale) {
+    if (fuse) {
+      c->pool.put(R);
+      O = F;
+      lo = l - 1;
+      if (s != HE_OK) c->pool.put(F);
+    } else if (s == HE_OK && c->auto_rescale) {
       O = (u64*)c->pool.get((size_t)B * ct_words(c, l - 1) * sizeof(u64));
       s = O ? rescale_multi(c, R, B, l, O) : fail(HE_EOOM, "batch allocation failed");
       c->pool.put(R);

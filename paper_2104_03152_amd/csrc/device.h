@@ -126,6 +126,18 @@ struct KsJob {
   long long a2a;
   u64 h_src;                      // (p - 1) / 2
   u64 hq[HE_MAXM], inv[HE_MAXM], inv_sh[HE_MAXM];  // per data prime t: h mod q_t, p^-1 mod q_t
+  // ModDown fused with the rescale that follows it (resc = 1): the top data
+  // limb l = Lp - 1 is dropped.  The special-limb launch also forms
+  // v_l = u_l + p * addends (NTT domain) and its inverse block phase
+  // (-> t3b); the column kernel (job a * l + t, t < l) finishes both inverse
+  // transforms, forms out_l's coefficients (v_l - lift_l(u_p)) p^-1, and
+  // transforms lift_t(u_p) p^-1 + lift_t(out_l) (-> t4); the block kernel
+  // writes ((u_t p^-1 + addends) - NTT(that)) q_l^-1, l limbs per poly.
+  int resc;
+  u64* t3b;                       // [2B][N]
+  u64 pl, pl_sh;                  // p mod q_l and its Shoup companion
+  u64 h_l;                        // (q_l - 1) / 2
+  u64 hq2[HE_MAXM], inv2[HE_MAXM], inv2_sh[HE_MAXM];  // per t < l: h_l mod q_t, q_l^-1 mod q_t (+ Shoup)
 };
 // ModUp columns (t1 -> t2), ModDown inner + blocks (ext -> t3, and the
 // data-limb inner products ext -> t5 by extra workgroups of the same
@@ -142,6 +154,12 @@ hipError_t launch_ks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* p
 hipError_t launch_ks_moddown_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                     hipStream_t st);
 // the ModDown column kernel run for a rescale
+// ModDown fused with a rescale (resc = 1): the column and block kernels
+// (the special-limb launch is launch_ks_special_blocks)
+hipError_t launch_ks_moddown_resc_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                       hipStream_t st);
+hipError_t launch_ks_moddown_resc_blocks(int log_n, const KsJob& job, const PrimeDev* primes,
+                                         const NttTables& tabs, hipStream_t st);
 hipError_t launch_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                hipStream_t st);
 

@@ -919,6 +919,119 @@ k_ks_moddown_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttT
                                                tabs, J.h_src, J.hq[t], sub, lds);
 }
 
+// Column phase of a ModDown fused with a rescale: one limb's inverse
+// column stages under P (canonical residues, in the last inverse pass's
+// layout), and values in that layout through the forward column stages
+// under P into tout.
+template <int LOGN, class Ar>
+__device__ __forceinline__ void inv_cols_to(const u64* __restrict__ tin, const PrimeDev& P,
+                                            const typename Ar::TW* __restrict__ W, int sub, u64* lds,
+                                            u64 (&out)[Split<LOGN>::SA::E]) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  PassTw<S, Sp::LOGMA, 0, false, Ar> tw;
+  tw.load(W, tid, 0);
+  typename Ar::T x[S::E];
+  {
+    constexpr int R = S::bits(0), LO = S::ilo(0), G = S::E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) x[u * (1 << R) + c] = Ar::unbits(tin[col_g<LOGN>(gidx(gi, c, LO, R), sub)]);
+    }
+  }
+  inv_passes<S, Sp::LOGMA, 0, Ar, true>(x, lds, W, ar, tid, 0, &tw);
+#pragma unroll
+  for (int i = 0; i < S::E; i++) out[i] = ar.inv_res(x[i], P);
+}
+
+template <int LOGN, class Ar>
+__device__ __forceinline__ void fwd_cols_from(u64 (&v)[Split<LOGN>::SA::E], const PrimeDev& P,
+                                              const typename Ar::TW* __restrict__ W, int sub, u64* lds,
+                                              u64* __restrict__ tout) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  constexpr int E = S::E;
+  constexpr int RI = S::bits(S::NP - 1), LOI = S::ilo(S::NP - 1);
+  constexpr int RF = S::bits(0), LOF = S::flo(0);
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  PassTw<S, Sp::LOGMA, 0, true, Ar> tw;
+  tw.load(W, tid, 0);
+  __syncthreads();  // the inverse passes' last reads of LDS are done
+  if constexpr (RI != RF || LOI != LOF) {
+    exchange<S, LOI, RI, LOF, RF, IntAr>(v, lds, tid);
+    __syncthreads();
+  }
+  typename Ar::T y[E];
+#pragma unroll
+  for (int i = 0; i < E; i++) y[i] = ar.from_res(v[i]);
+  fwd_passes<S, Sp::LOGMA, 0, Ar, true>(y, lds, W, ar, tid, 0, &tw);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::flo(S::NP - 1), G = E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) tout[col_g<LOGN>(gidx(gi, c, LO, R), sub)] = Ar::bits(y[u * (1 << R) + c]);
+    }
+  }
+}
+
+// job w = a * l + t (t < l = Lp - 1): the special limb's and v_l's inverse
+// column stages, out_l = (v_l - lift_l(u_p)) p^-1 in coefficient form, and
+// lift_t(u_p) p^-1 + lift_t(out_l) through the forward column stages (both
+// lifts round: x + h, reduced, minus h)
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_ks_moddown_resc_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  using Sp = Split<LOGN>;
+  constexpr int E = Sp::SA::E;
+  __shared__ u64 lds[Sp::SA::lds_words()];
+  const int l = J.Lp - 1;
+  const int w = blockIdx.x / Sp::WA;
+  const int sub = blockIdx.x - w * Sp::WA;
+  const int a = w / l, t = w - a * l;
+  const int sp = J.special;
+  const PrimeDev Ps = primes[sp], Pl = primes[l], Pt = primes[t];
+  u64 cs[E], cv[E], v[E];
+  if (Ps.use_fp)
+    inv_cols_to<LOGN, FpAr>(J.t3 + (size_t)a * N, Ps, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)sp * N,
+                            sub, lds, cs);
+  else
+    inv_cols_to<LOGN, IntAr>(J.t3 + (size_t)a * N, Ps,
+                             reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)sp * N, sub, lds, cs);
+  __syncthreads();  // the first transform's last LDS reads are done
+  if (Pl.use_fp)
+    inv_cols_to<LOGN, FpAr>(J.t3b + (size_t)a * N, Pl, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)l * N,
+                            sub, lds, cv);
+  else
+    inv_cols_to<LOGN, IntAr>(J.t3b + (size_t)a * N, Pl,
+                             reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)l * N, sub, lds, cv);
+  const u64 qs = Ps.q, ql = Pl.q, qt = Pt.q;
+#pragma unroll
+  for (int i = 0; i < E; i++) {
+    u64 r = cs[i] + J.h_src;
+    r = r >= qs ? r - qs : r;
+    const u64 sl = submod(red64(r, Pl), J.hq[l], ql);
+    const u64 st = submod(red64(r, Pt), J.hq[t], qt);
+    u64 o = shoup(submod(cv[i], sl, ql), J.inv[l], J.inv_sh[l], ql);
+    o += J.h_l;
+    o = o >= ql ? o - ql : o;
+    const u64 rt = submod(red64(o, Pt), J.hq2[t], qt);
+    v[i] = addmod(shoup(st, J.inv[t], J.inv_sh[t], qt), rt, qt);
+  }
+  u64* __restrict__ tout = J.t4 + (size_t)w * N;
+  if (Pt.use_fp)
+    fwd_cols_from<LOGN, FpAr>(v, Pt, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, sub, lds, tout);
+  else
+    fwd_cols_from<LOGN, IntAr>(v, Pt, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, sub, lds, tout);
+}
+
 // inner products of item b's digits with its key at modulus t for poly k, at
 // the E limb indices idx[] (Montgomery form keys: a lazy 128-bit sum of at
 // most 8 products, one reduction per group).  The E elements advance
@@ -999,6 +1112,56 @@ __device__ __forceinline__ void special_blocks_body(const KsJob& J, const typena
   }
 }
 
+// ModDown fused with a rescale: the dropped limb l of poly a = 2b + k,
+// v_l = u_l + p * (addends), and its inverse block phase -> t3b
+template <int LOGN, class Ar>
+__device__ __forceinline__ void resc_top_body(const KsJob& J, const typename Ar::TW* __restrict__ W,
+                                              const PrimeDev& P, int a, int t, int sub, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  constexpr int E = S::E;
+  constexpr size_t N = (size_t)1 << LOGN;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const int toff = sub << Sp::LOGMB;
+  const int b = a >> 1;
+  const u64 q = P.q;
+  PassTw<S, LOGN, 0, false, Ar> tw0;
+  tw0.load(W, tid, toff);
+  typename Ar::T x[E];
+  {
+    constexpr int R = S::bits(0), G = E >> R;
+    int idx[E];
+    u64 v[E];
+#pragma unroll
+    for (int u = 0; u < G; u++)
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) idx[u * (1 << R) + c] = toff + (((tid + S::T * u) << R) | c);
+    ks_inner<E>(J, P, LOGN, b, a & 1, t, t, idx, true, v);
+    const u64* __restrict__ ad =
+        (J.add && !(J.add_even_only && (a & 1))) ? J.add + a * J.aa + (size_t)t * N : nullptr;
+    const u64* __restrict__ ad2 = J.add2 ? J.add2 + a * J.a2a + (size_t)t * N : nullptr;
+    const u64 ag = J.add_gather ? J.gal[b] : 1;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      u64 sum = ad ? ad[ag != 1 ? gal_src(idx[e], LOGN, ag) : idx[e]] : 0;
+      if (ad2) sum = addmod(sum, ad2[idx[e]], q);
+      x[e] = ar.from_res(addmod(v[e], shoup(sum, J.pl, J.pl_sh, q), q));
+    }
+  }
+  inv_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = E >> R;
+    u64* __restrict__ tt = J.t3b + ((size_t)a << LOGN) + toff;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) tt[gidx(gi, c, LO, R)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
 template <int LOGN>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ks_special_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
@@ -1014,6 +1177,16 @@ k_ks_special_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Nt
     const int w = (blockIdx.x - n_special) / Sp::WB;
     const int sub = blockIdx.x - n_special - w * Sp::WB;
     const int a = w / J.Lp, t = w - a * J.Lp;
+    if (J.resc && t == J.Lp - 1) {
+      const PrimeDev P = primes[t];
+      if (P.use_fp)
+        resc_top_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)t * N, P, a, t, sub,
+                                  lds);
+      else
+        resc_top_body<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)t * N, P, a, t, sub,
+                                   lds);
+      return;
+    }
     const int toff = sub << Sp::LOGMB;
     int idx[S::E];
     u64 v[S::E];
@@ -1038,7 +1211,7 @@ k_ks_special_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Nt
 
 // ModDown, data limb t of poly a = 2b + k: forward block phase of the lifted
 // divisor, then (inner product - NTT(r - h)) * p^-1 + addends -> out
-template <int LOGN, class Ar>
+template <int LOGN, class Ar, bool RESC>
 __device__ __forceinline__ void moddown_blocks_body(const KsJob& J, const typename Ar::TW* __restrict__ W,
                                                     const PrimeDev& P, int w, int a, int t, int sub, u64* lds) {
   using Sp = Split<LOGN>;
@@ -1066,7 +1239,7 @@ __device__ __forceinline__ void moddown_blocks_body(const KsJob& J, const typena
   // by the special-limb launch), loaded before the transform
   constexpr int RL = S::bits(S::NP - 1), GL = E >> RL;
   u64 uu[E];
-  const u64* __restrict__ tu = J.t5 + ((size_t)w << LOGN);
+  const u64* __restrict__ tu = J.t5 + ((size_t)(RESC ? a * J.Lp + t : w) << LOGN);
 #pragma unroll
   for (int u = 0; u < GL; u++)
 #pragma unroll
@@ -1086,30 +1259,43 @@ __device__ __forceinline__ void moddown_blocks_body(const KsJob& J, const typena
 #pragma unroll
       for (int c = 0; c < (1 << R); c++) {
         const int idx = toff + ((gi << R) | c);
-        u64 v = shoup(submod(uu[u * (1 << R) + c], ar.fwd_res(x[u * (1 << R) + c]), q), inv, inv_sh, q);
-        if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
-        if (ad2) v = addmod(v, ad2[idx], q);
+        const int e = u * (1 << R) + c;
+        u64 v;
+        if constexpr (RESC) {
+          // ((u_t p^-1 + addends) - NTT(lift_t(u_p) p^-1 + lift_t(out_l))) q_l^-1
+          v = shoup(uu[e], inv, inv_sh, q);
+          if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
+          if (ad2) v = addmod(v, ad2[idx], q);
+          v = shoup(submod(v, ar.fwd_res(x[e]), q), J.inv2[t], J.inv2_sh[t], q);
+        } else {
+          v = shoup(submod(uu[e], ar.fwd_res(x[e]), q), inv, inv_sh, q);
+          if (ad) v = addmod(v, ad[ag != 1 ? gal_src(idx, LOGN, ag) : idx], q);
+          if (ad2) v = addmod(v, ad2[idx], q);
+        }
         dst[idx] = v;
       }
     }
   }
 }
 
-template <int LOGN>
+// RESC: the ModDown fused with a rescale (l = Lp - 1 limbs out per poly,
+// job w = a * l + t)
+template <int LOGN, bool RESC>
 __global__ void __launch_bounds__(Split<LOGN>::SB::T)
 k_ks_moddown_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = 1 << LOGN;
   __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
   const int w = blockIdx.x / Split<LOGN>::WB;
   const int sub = blockIdx.x - w * Split<LOGN>::WB;
-  const int a = w / J.Lp, t = w - a * J.Lp;
+  const int lo = RESC ? J.Lp - 1 : J.Lp;
+  const int a = w / lo, t = w - a * lo;
   const PrimeDev P = primes[t];
   if (P.use_fp)
-    moddown_blocks_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P, w, a, t,
-                                    sub, lds);
+    moddown_blocks_body<LOGN, FpAr, RESC>(J, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)t * N, P, w, a,
+                                          t, sub, lds);
   else
-    moddown_blocks_body<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P, w, a, t,
-                                     sub, lds);
+    moddown_blocks_body<LOGN, IntAr, RESC>(J, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, P, w,
+                                           a, t, sub, lds);
 }
 
 // ---------------- hoisted rotations: ModDown + multiply-accumulate ----------------
@@ -1792,9 +1978,19 @@ hipError_t ks_launch(int which, const KsJob& J, const PrimeDev* primes, const Nt
       hipLaunchKernelGGL((k_ks_moddown_cols<LOGN, 1>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
                          tabs);
       break;
+    case 5:
+      if (Lp < 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_ks_moddown_resc_cols<LOGN>), dim3(2 * B * (Lp - 1) * Sp::WA), dim3(Sp::SA::T), 0, st, J,
+                         primes, tabs);
+      break;
+    case 6:
+      if (Lp < 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_ks_moddown_blocks<LOGN, true>), dim3(2 * B * (Lp - 1) * Sp::WB), dim3(Sp::SB::T), 0, st,
+                         J, primes, tabs);
+      break;
     default:
-      hipLaunchKernelGGL((k_ks_moddown_blocks<LOGN>), dim3(2 * B * Lp * Sp::WB), dim3(Sp::SB::T), 0, st, J, primes,
-                         tabs);
+      hipLaunchKernelGGL((k_ks_moddown_blocks<LOGN, false>), dim3(2 * B * Lp * Sp::WB), dim3(Sp::SB::T), 0, st, J,
+                         primes, tabs);
   }
   return hipGetLastError();
 }
@@ -1955,6 +2151,14 @@ hipError_t launch_ks_moddown_blocks(int log_n, const KsJob& job, const PrimeDev*
 hipError_t launch_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                hipStream_t st) {
   return ks_any(4, log_n, job, primes, tabs, st);
+}
+hipError_t launch_ks_moddown_resc_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                       hipStream_t st) {
+  return ks_any(5, log_n, job, primes, tabs, st);
+}
+hipError_t launch_ks_moddown_resc_blocks(int log_n, const KsJob& job, const PrimeDev* primes,
+                                         const NttTables& tabs, hipStream_t st) {
+  return ks_any(6, log_n, job, primes, tabs, st);
 }
 
 hipError_t launch_ntt_fwd(int log_n, int pro, int epi, const NttJob& job, const PrimeDev* primes,
