@@ -131,7 +131,8 @@ he_status he_pt_import(he_ctx* ctx, const int64_t* coeffs, double scale,
 he_status he_pt_export(he_ctx* ctx, const he_pt* pt, uint64_t* coeff_form,
                        size_t cap, int32_t* level, double* scale);
 
-/* ---- encryption ---- */
+/* ---- encryption (section 2.1: the context's public key encrypts, its secret
+ * key decrypts; section 2.3's encrypted tensors hold these ciphertexts) ---- */
 
 /* Public-key encryption (use_secret_key = 0): (v*pk0 + e0 + m, v*pk1 + e1);
  * secret-key: (-a*s + e + m, a).  enc_index selects the sampler streams, so
@@ -205,7 +206,9 @@ he_status he_power(he_ctx* ctx, const he_ct* a, uint32_t k, he_ct** out);
 he_status he_polyval(he_ctx* ctx, const he_ct* a, const double* coeffs, size_t n_coeffs,
                      he_ct** out);
 
-/* ---- NTT autotuner ----
+/* ---- NTT autotuner (the ring products under every section 3 operation;
+ * section 2.1's thread pool sizes its work to the machine, this picks the
+ * launch form per size) ----
  * Times batched forward + inverse NTTs of J limb-transforms (J = 16, 32, ...
  * up to max_jobs; J limbs are the data limbs of J / L' ciphertext polys at
  * L' limbs) in every candidate form: the two-phase kernels (a limb spread
@@ -228,7 +231,8 @@ he_status he_ntt_layouts(he_ctx* ctx, int32_t* loge, int32_t* logr, size_t cap, 
 he_status he_tune_ntt(he_ctx* ctx, int32_t max_jobs, int32_t* split_jobs, double* table,
                       size_t table_cap);
 
-/* ---- captured graphs (a fixed op sequence replayed with one launch) ----
+/* ---- captured graphs (a fixed op sequence replayed with one launch: the
+ * batch-1 inference of section 5, table 2) ----
  * Everything the library enqueues on the context's stream between
  * he_graph_begin and he_graph_end is captured (HIP stream capture, relaxed
  * mode) into a graph; he_graph_launch replays it.  Ciphertexts created
@@ -355,7 +359,8 @@ he_status he_plan_apply(he_ctx* ctx, const he_plan* plan, const he_ct* x,
 he_status he_plan_apply_many(he_ctx* ctx, const he_plan* const* plans,
                              uint32_t n, const he_ct* x, he_ct** outs);
 
-/* ---- raw transforms (batched negacyclic NTT on caller device buffers) ---- */
+/* ---- raw transforms (batched negacyclic NTT on caller device buffers: the
+ * ring arithmetic of the CKKS scheme that section 2 builds on) ---- */
 /* data: device pointer to n_polys polynomials of n_limbs limbs, layout
  * [n_polys][n_limbs][N] u64, limb i under data prime i, residues in [0, q_i),
  * 16-byte aligned (HE_EINVAL otherwise).  In place, enqueued on the context
@@ -365,7 +370,8 @@ he_status he_ntt_forward(he_ctx* ctx, uint64_t* data, size_t n_polys,
 he_status he_ntt_inverse(he_ctx* ctx, uint64_t* data, size_t n_polys,
                          int32_t n_limbs);
 
-/* ---- keys for parity checks ---- */
+/* ---- keys for parity checks (section 2.1's secret, relinearisation and
+ * Galois keys) ---- */
 he_status he_export_secret(he_ctx* ctx, int64_t* s); /* N ternary coeffs */
 /* kind 0: relinearisation key, kind 1: Galois key of `step`.  Coefficient
  * form, layout [digit j][poly k][modulus t][N], t = 0..max_level then the
@@ -421,7 +427,8 @@ he_status he_tensor_dot(he_ctx* ctx, const he_tensor* a, const he_tensor* b, he_
 he_status he_tensor_dot_plain(he_ctx* ctx, const he_tensor* a, const double* w, he_tensor** out);
 void he_tensor_free(he_tensor* t);
 
-/* ---- housekeeping ---- */
+/* ---- housekeeping (section 2.1: the context owns keys and device memory;
+ * section 3.2's client-side im2col) ---- */
 void he_ct_free(he_ct* ct);
 void he_pt_free(he_pt* pt);
 void he_plan_free(he_plan* plan);
@@ -436,13 +443,15 @@ void he_im2col(const double* img, uint32_t h, uint32_t w, uint32_t k,
                uint32_t stride, double* out);
 
 /* ---- kernel timing: HIP events around each launch of a named kernel
- * family while enabled (adds no work to the kernels themselves). ---- */
+ * family while enabled (adds no work to the kernels themselves; the
+ * per-stage times of section 5, table 2). ---- */
 he_status he_profile_enable(he_ctx* ctx, int32_t enable);
 /* launches, summed milliseconds, summed work units (limb-NTTs for the NTT
  * families, items for the inner products) and summed algorithmic HBM bytes
  * of a kernel family since enabling (synchronises).  Families: "ntt_fwd",
  * "ntt_inv", "modup", "moddown", "rescale", "keyswitch_inner",
- * "hoisted_inner", "hoisted_moddown", "pointwise", "sample". */
+ * "hoisted_inner", "hoisted_cols", "hoisted_moddown", "hoisted_replication",
+ * "pointwise", "sample". */
 he_status he_profile_read(he_ctx* ctx, const char* family, uint64_t* launches,
                           double* total_ms, double* units, double* bytes);
 
