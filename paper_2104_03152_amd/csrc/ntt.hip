@@ -1032,6 +1032,10 @@ k_ks_moddown_resc_cols(const KsJob J, const PrimeDev* __restrict__ primes, const
     fwd_cols_from<LOGN, IntAr>(v, Pt, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)t * N, sub, lds, tout);
 }
 
+// digits of the key-switch inner product whose loads are in flight together
+#ifndef HE_KS_UNROLL
+#define HE_KS_UNROLL 2
+#endif
 // inner products of item b's digits with its key at modulus t for poly k, at
 // the E limb indices idx[] (Montgomery form keys: a lazy 128-bit sum of at
 // most 8 products, one reduction per group).  The E elements advance
@@ -1057,7 +1061,7 @@ __device__ __forceinline__ void ks_inner(const KsJob& J, const PrimeDev& P, int 
     for (int e = 0; e < E; e++) acc[e] = U128{0, 0};
     const int j1 = min(J.Lp, j0 + 8);
     // unrolled so that the key loads of several digits are in flight at once
-#pragma unroll 2
+#pragma unroll HE_KS_UNROLL
     for (int j = j0; j < j1; j++) {
       u64 dj[E], kj[E];
 #pragma unroll
