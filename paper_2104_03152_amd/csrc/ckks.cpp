@@ -192,6 +192,9 @@ struct he_ctx {
   NttTables tabs{};
   bool capturing = false;  // a graph capture of st is open
   int fuse_max = 256;      // fused key switch when B*Lp^2 <= this, fused rescale when 2*n_ct*l <= this
+  // rotate-and-sum chains in coefficient form (HE_COEF_ROT=0: in the
+  // transform domain)
+  int coef_rot = 1;
   int hoist_split_wgs = 1536;  // two-phase hoisted multiply-accumulate, about this many workgroups (0: one kernel)
   bool have_keys = false;
   u64* d_s = nullptr;   // [L+1][N]
@@ -799,6 +802,93 @@ he_status rotate_multi(he_ctx* c, const u64* in, int B, int l, const int* steps,
   return key_switch(c, B, in + (size_t)Lp * n, 2LL * Lp * n, l, keys, gals, add, out);
 }
 
+// Left rotations of B coefficient-form ciphertexts ([B][2][l+1][N] at in) by
+// steps[b] into coefficient form at out; with add_in, out = in + rot(in).
+// Only in the fused form (ks_fusable): four launches per rotation (ModUp
+// from the automorphism's source coefficients, its block stages, inner
+// products + inverse block stages, inverse column stages + division +
+// addends), the residues those of rotate_multi on the transformed input.
+static bool coef_rotations(const he_ctx* c, int B, int Lp) { return c->coef_rot && ks_fusable(c, B, Lp); }
+
+he_status rotate_multi_coef(he_ctx* c, const u64* in, int B, int l, const int* steps, u64* out, bool add_in) {
+  const int n = c->n, Lp = l + 1, nm = Lp + 1;
+  if (B < 1 || B > HE_MAX_BATCH) return fail(HE_EINVAL, "rotation batch of %d", B);
+  if (!coef_rotations(c, B, Lp)) return fail(HE_EINVAL, "coefficient-form rotations outside the fused form");
+  KsJob K{};
+  K.B = B;
+  K.Lp = Lp;
+  K.nm = nm;
+  K.special = c->L;
+  for (int b = 0; b < B; b++) {
+    auto it = c->gal.find(steps[b]);
+    if (it == c->gal.end()) return fail(HE_ENOKEY, "no Galois key for step %d", steps[b]);
+    if (it->second.ml < l)
+      return fail(HE_ENOKEY, "Galois key for step %d cut at level %d, ciphertext at %d", steps[b], it->second.ml, l);
+    K.key[b] = it->second.d;
+    K.km[b] = it->second.ml + 2;
+    const u64 g = galois_elt(c, steps[b]);
+    K.gal[b] = g;
+    K.ginv[b] = h_powm(g, (u64)n - 1, 2 * (u64)n);  // the group of odd residues mod 2N has order N
+  }
+  DBuf t2, ext, t3;
+  TRY(dalloc(c, t2, (size_t)B * Lp * nm * n));
+  TRY(dalloc(c, ext, (size_t)B * Lp * nm * n));
+  TRY(dalloc(c, t3, (size_t)2 * B * nm * n));
+  K.cin = in;
+  K.t2 = t2.p;
+  K.ext = ext.p;
+  K.t3 = t3.p;
+  K.out = out;
+  K.oa = (long long)Lp * n;
+  K.add = in;
+  K.aa = (long long)Lp * n;
+  K.add_even_only = 1;
+  K.add_gather = 1;
+  if (add_in) {
+    K.add2 = in;
+    K.a2a = (long long)Lp * n;
+  }
+  const size_t np = c->q.size();
+  K.h_src = (c->q[c->L] - 1) / 2;
+  for (int t = 0; t < Lp; t++) {
+    K.hq[t] = c->rd_hq[c->L * np + t];
+    K.inv[t] = c->rd_inv[c->L * np + t];
+    K.inv_sh[t] = c->rd_inv_sh[c->L * np + t];
+  }
+  NttJob F{};
+  F.dst = ext.p;
+  F.da = (long long)nm * n;
+  F.db = n;
+  F.na = B * Lp;
+  F.nb = nm;
+  F.mid = t2.p;
+  for (int t = 0; t < nm; t++) F.dst_prime[t] = (unsigned char)(t < Lp ? t : c->L);
+  int distinct = 0;
+  for (int b = 0; b < B; b++) {
+    bool seen = false;
+    for (int a = 0; a < b; a++) seen |= K.key[a] == K.key[b];
+    distinct += seen ? 0 : 1;
+  }
+  hipError_t e;
+  {
+    // the digits read, every (item, digit, modulus) written
+    Prof pr(c, "modup", (double)B * Lp * nm, 8.0 * n * B * Lp * (1 + nm));
+    e = launch_cks_modup_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+    if (e == hipSuccess)
+      e = launch_ntt_fwd_blocks(c->log_n, PRO_CENTRED_LIFT, EPI_STORE, F, c->d_primes, c->tabs, c->st);
+  }
+  if (e == hipSuccess) {
+    // as the ModDown: keys (each distinct one once), digits, addends, output
+    const double adds = 1.0 + (add_in ? 2.0 : 0.0);
+    Prof pr(c, "moddown", 2.0 * B * (1 + Lp),
+            8.0 * n * (2.0 * distinct * Lp * nm + B * (Lp * nm + 2.0 * Lp + adds * Lp)));
+    e = launch_cks_inner_blocks(c->log_n, K, c->d_primes, c->tabs, c->st);
+    if (e == hipSuccess) e = launch_cks_moddown_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+  }
+  if (e != hipSuccess) return fail(HE_EHIP, "coefficient-form rotation: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
 // rescale of n_ct contiguous ciphertexts [n_ct][2][l+1][N] -> [n_ct][2][l][N]
 // add0 (nullable, n_ct = 1): a plaintext added to poly 0 of the result
 he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out, const u64* add0 = nullptr) {
@@ -1212,6 +1302,7 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
   if (const char* env = getenv("HE_NTT_SPLIT_JOBS")) split_jobs = atoi(env);
   if (const char* env = getenv("HE_FUSE_MAX")) c->fuse_max = atoi(env);
   if (const char* env = getenv("HE_HOIST_SPLIT_WGS")) c->hoist_split_wgs = atoi(env);
+  if (const char* env = getenv("HE_COEF_ROT")) c->coef_rot = atoi(env);
   int forced_shape = -1;
   if (const char* env = getenv("HE_NTT_LAYOUT")) forced_shape = atoi(env);
   u64* tmp = nullptr;
@@ -2605,17 +2696,25 @@ static he_status conv_apply_many(he_ctx* c, const he_plan* const* plans, int nb,
   int steps = 0;
   while ((1u << steps) < plans[0]->kk) steps++;
   std::vector<int> st(nb);
+  // the chain in coefficient form where the fused key switch applies: one
+  // inverse transform before it and one forward transform after it
+  const bool coef = steps > 0 && coef_rotations(c, nb, l);
+  if (coef) TRY(ntt_rows(c, false, Y.p, Y.p, 2 * nb, l, (long long)l * n, (long long)l * n));
   for (int j = 0; j < steps; j++) {
     for (int b = 0; b < nb; b++) st[b] = norm_step(c, (long long)plans[0]->windows << j);
-    if (st[0] == 0) {  // rotation by a multiple of N/2: x + x
+    if (st[0] == 0) {  // rotation by a multiple of N/2: x + x (in either form)
       Prof pr(c, "pointwise");
       hipError_t e = launch_addsub(c->log_n, 0, Y.p, Y.p, Y.p, 2 * nb, mods_range(l), c->d_primes, c->st);
       if (e != hipSuccess) return fail(HE_EHIP, "add: %s", hipGetErrorString(e));
       continue;
     }
-    TRY(rotate_multi(c, Y.p, nb, l - 1, st.data(), R.p, true));
+    if (coef)
+      TRY(rotate_multi_coef(c, Y.p, nb, l - 1, st.data(), R.p, true));
+    else
+      TRY(rotate_multi(c, Y.p, nb, l - 1, st.data(), R.p, true));
     std::swap(Y.p, R.p);
   }
+  if (coef) TRY(ntt_rows(c, true, Y.p, Y.p, 2 * nb, l, (long long)l * n, (long long)l * n));
   CtList in{}, bp{};
   OutList ol{};
   for (int b = 0; b < nb; b++) {

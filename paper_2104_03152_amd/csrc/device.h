@@ -135,6 +135,11 @@ struct KsJob {
   // writes ((u_t p^-1 + addends) - NTT(that)) q_l^-1, l limbs per poly.
   int resc;
   u64* t3b;                       // [2B][N]
+  // rotations of coefficient-form ciphertexts (k_cks_*): input [B][2][Lp][N]
+  // in coefficient form, the automorphism applied by the inverse Galois
+  // element; out is in coefficient form too
+  const u64* cin;
+  u64 ginv[HE_MAX_BATCH];
   u64 pl, pl_sh;                  // p mod q_l and its Shoup companion
   u64 h_l;                        // (q_l - 1) / 2
   u64 hq2[HE_MAXM], inv2[HE_MAXM], inv2_sh[HE_MAXM];  // per t < l: h_l mod q_t, q_l^-1 mod q_t (+ Shoup)
@@ -160,6 +165,17 @@ hipError_t launch_ks_moddown_resc_cols(int log_n, const KsJob& job, const PrimeD
                                        hipStream_t st);
 hipError_t launch_ks_moddown_resc_blocks(int log_n, const KsJob& job, const PrimeDev* primes,
                                          const NttTables& tabs, hipStream_t st);
+// rotation of coefficient-form ciphertexts: ModUp (lift + forward column
+// stages from the automorphism's source coefficients -> t2; the forward
+// block stages run as a plain two-phase block launch into ext), inner
+// products + inverse block stages for every modulus (-> t3 [2B][nm][N]),
+// inverse column stages + division + addends (-> out, coefficient form)
+hipError_t launch_cks_modup_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                 hipStream_t st);
+hipError_t launch_cks_inner_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                   hipStream_t st);
+hipError_t launch_cks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                   hipStream_t st);
 hipError_t launch_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                hipStream_t st);
 

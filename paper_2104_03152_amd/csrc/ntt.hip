@@ -1302,6 +1302,214 @@ k_ks_moddown_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Nt
                                            a, t, sub, lds);
 }
 
+// ---------------- rotations of coefficient-form ciphertexts ----------------
+// A rotate-and-sum chain keeps its ciphertext in coefficient form between
+// steps: the automorphism X -> X^g is then a signed permutation of
+// coefficients, the digits need no inverse transform, and the ModDown's
+// inverse transforms leave the result in coefficient form.  Four launches
+// per step instead of six; the residues are those of the transform-domain
+// path (every map is exact), so results are bit-identical.
+
+// coefficient m of a(X^g): +-a[i], i = m g^-1 mod 2N (negated when i >= N)
+__device__ __forceinline__ int cauto_src(int m, int log_n, u64 ginv, bool& neg) {
+  const u32 i = ((u32)m * (u32)ginv) & ((2u << log_n) - 1u);
+  neg = (i >> log_n) != 0;
+  return (int)(i & ((1u << log_n) - 1u));
+}
+
+// ModUp, job w = (b Lp + j) nm + t: digit j (poly 1, limb j, read at the
+// automorphism's source) lifted (centred) to modulus t (t = Lp: the special
+// prime; t = j: the digit itself) through the forward column stages -> t2
+template <int LOGN, class Ar>
+__device__ __forceinline__ void cks_modup_body(const KsJob& J, const typename Ar::TW* __restrict__ W,
+                                               const PrimeDev& P, const PrimeDev& Pj, int w, int b, int j, int sub,
+                                               u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  constexpr size_t N = (size_t)1 << LOGN;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const u64 q = P.q, qj = Pj.q, hj = (qj - 1) >> 1;
+  const u64 ginv = J.ginv[b];
+  const u64* __restrict__ src = J.cin + ((size_t)(2 * b + 1) * J.Lp + j) * N;
+  typename Ar::T x[S::E];
+  PassTw<S, Sp::LOGMA, 0, true, Ar> tw0;
+  tw0.load(W, tid, 0);
+  {
+    constexpr int R = S::bits(0), LO = S::flo(0), G = S::E >> R;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) {
+        const int m = col_g<LOGN>(gidx(gi, c, LO, R), sub);
+        bool neg = false;
+        const int si = ginv != 1 ? cauto_src(m, LOGN, ginv, neg) : m;
+        u64 v = src[si];
+        if (neg) v = v ? qj - v : 0;
+        if (v > hj) {
+          const u64 r = red64(qj - v, P);
+          v = r ? q - r : 0;
+        } else {
+          v = red64(v, P);
+        }
+        x[u * (1 << R) + c] = ar.from_res(v);
+      }
+    }
+  }
+  fwd_passes<S, Sp::LOGMA, 0, Ar, true>(x, lds, W, ar, tid, 0, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::flo(S::NP - 1), G = S::E >> R;
+    u64* __restrict__ t = J.t2 + (size_t)w * N;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) t[col_g<LOGN>(gidx(gi, c, LO, R), sub)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_cks_modup_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Split<LOGN>::SA::lds_words()];
+  const int w = blockIdx.x / Split<LOGN>::WA;
+  const int sub = blockIdx.x - w * Split<LOGN>::WA;
+  const int a = w / J.nm, t = w - a * J.nm;
+  const int b = a / J.Lp, j = a - b * J.Lp;
+  const int pt = t < J.Lp ? t : J.special;
+  const PrimeDev P = primes[pt], Pj = primes[j];
+  if (P.use_fp)
+    cks_modup_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.fwd_fp) + (size_t)pt * N, P, Pj, w, b, j,
+                               sub, lds);
+  else
+    cks_modup_body<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.fwd) + (size_t)pt * N, P, Pj, w, b, j,
+                                sub, lds);
+}
+
+// inner product of poly a = 2b + k at modulus t (every modulus, the special
+// one at t = Lp) on block sub, and its inverse block stages -> t3[a nm + t]
+template <int LOGN, class Ar>
+__device__ __forceinline__ void cks_inner_body(const KsJob& J, const typename Ar::TW* __restrict__ W,
+                                               const PrimeDev& P, int a, int t, int kt, int sub, u64* lds) {
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SB;
+  constexpr int E = S::E;
+  const Ar ar(P);
+  const int tid = threadIdx.x;
+  const int toff = sub << Sp::LOGMB;
+  PassTw<S, LOGN, 0, false, Ar> tw0;
+  tw0.load(W, tid, toff);
+  typename Ar::T x[E];
+  {
+    constexpr int R = S::bits(0), G = E >> R;
+    int idx[E];
+    u64 v[E];
+#pragma unroll
+    for (int u = 0; u < G; u++)
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) idx[u * (1 << R) + c] = toff + (((tid + S::T * u) << R) | c);
+    ks_inner<E>(J, P, LOGN, a >> 1, a & 1, t, kt, idx, false, v);
+#pragma unroll
+    for (int i = 0; i < E; i++) x[i] = ar.from_res(v[i]);
+  }
+  inv_passes<S, LOGN, 0, Ar, true>(x, lds, W, ar, tid, toff, &tw0);
+  {
+    constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = E >> R;
+    u64* __restrict__ tt = J.t3 + ((size_t)(a * J.nm + t) << LOGN) + toff;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int gi = tid + S::T * u;
+#pragma unroll
+      for (int c = 0; c < (1 << R); c++) tt[gidx(gi, c, LO, R)] = Ar::bits(x[u * (1 << R) + c]);
+    }
+  }
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SB::T)
+k_cks_inner_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[Split<LOGN>::SB::lds_words()];
+  const int w = blockIdx.x / Split<LOGN>::WB;
+  const int sub = blockIdx.x - w * Split<LOGN>::WB;
+  const int a = w / J.nm, t = w - a * J.nm;
+  const bool sp = t >= J.Lp;
+  const int pt = sp ? J.special : t;
+  const int kt = sp ? J.km[a >> 1] - 1 : t;
+  const PrimeDev P = primes[pt];
+  if (P.use_fp)
+    cks_inner_body<LOGN, FpAr>(J, reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)pt * N, P, a, t, kt, sub,
+                               lds);
+  else
+    cks_inner_body<LOGN, IntAr>(J, reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)pt * N, P, a, t, kt,
+                                sub, lds);
+}
+
+// ModDown, job w = a Lp + t: the inverse column stages of the special limb
+// and of limb t, (u_t - lift_t(u_p)) p^-1 plus the addends (poly 0 of the
+// input at the automorphism's source; the input itself with add2) -> out
+template <int LOGN>
+__global__ void __launch_bounds__(Split<LOGN>::SA::T)
+k_cks_moddown_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
+  constexpr int N = 1 << LOGN;
+  using Sp = Split<LOGN>;
+  using S = typename Sp::SA;
+  constexpr int E = S::E;
+  __shared__ u64 lds[S::lds_words()];
+  const int w = blockIdx.x / Sp::WA;
+  const int sub = blockIdx.x - w * Sp::WA;
+  const int a = w / J.Lp, t = w - a * J.Lp;
+  const int b = a >> 1;
+  const int sp = J.special;
+  const PrimeDev Ps = primes[sp], Pt = primes[t];
+  u64 cs[E], ct[E];
+  if (Ps.use_fp)
+    inv_cols_to<LOGN, FpAr>(J.t3 + (size_t)(a * J.nm + J.Lp) * N, Ps,
+                            reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)sp * N, sub, lds, cs);
+  else
+    inv_cols_to<LOGN, IntAr>(J.t3 + (size_t)(a * J.nm + J.Lp) * N, Ps,
+                             reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)sp * N, sub, lds, cs);
+  __syncthreads();  // the first transform's last LDS reads are done
+  if (Pt.use_fp)
+    inv_cols_to<LOGN, FpAr>(J.t3 + (size_t)(a * J.nm + t) * N, Pt,
+                            reinterpret_cast<const double2*>(tabs.inv_fp) + (size_t)t * N, sub, lds, ct);
+  else
+    inv_cols_to<LOGN, IntAr>(J.t3 + (size_t)(a * J.nm + t) * N, Pt,
+                             reinterpret_cast<const ulonglong2*>(tabs.inv) + (size_t)t * N, sub, lds, ct);
+  const u64 qs = Ps.q, qt = Pt.q;
+  const u64* __restrict__ ad =
+      (J.add && !(J.add_even_only && (a & 1))) ? J.add + a * J.aa + (size_t)t * N : nullptr;
+  const u64* __restrict__ ad2 = J.add2 ? J.add2 + a * J.a2a + (size_t)t * N : nullptr;
+  const u64 ginv = J.add_gather ? J.ginv[b] : 1;
+  u64* __restrict__ dst = J.out + a * J.oa + (size_t)t * N;
+  constexpr int R = S::bits(S::NP - 1), LO = S::ilo(S::NP - 1), G = E >> R;
+#pragma unroll
+  for (int u = 0; u < G; u++) {
+    const int gi = threadIdx.x + S::T * u;
+#pragma unroll
+    for (int c = 0; c < (1 << R); c++) {
+      const int e = u * (1 << R) + c;
+      const int m = col_g<LOGN>(gidx(gi, c, LO, R), sub);
+      u64 r = cs[e] + J.h_src;
+      r = r >= qs ? r - qs : r;
+      const u64 st = submod(red64(r, Pt), J.hq[t], qt);
+      u64 o = shoup(submod(ct[e], st, qt), J.inv[t], J.inv_sh[t], qt);
+      if (ad) {
+        bool neg = false;
+        const int si = ginv != 1 ? cauto_src(m, LOGN, ginv, neg) : m;
+        u64 v = ad[si];
+        if (neg) v = v ? qt - v : 0;
+        o = addmod(o, v, qt);
+      }
+      if (ad2) o = addmod(o, ad2[m], qt);
+      dst[m] = o;
+    }
+  }
+}
+
 // ---------------- hoisted rotations: ModDown + multiply-accumulate ----------------
 // ModDown of each item (an NTT of its special-prime limb, lifted) with the
 // plaintext multiply-accumulate of the vector-matrix product in the
@@ -1992,6 +2200,18 @@ hipError_t ks_launch(int which, const KsJob& J, const PrimeDev* primes, const Nt
       hipLaunchKernelGGL((k_ks_moddown_blocks<LOGN, true>), dim3(2 * B * (Lp - 1) * Sp::WB), dim3(Sp::SB::T), 0, st,
                          J, primes, tabs);
       break;
+    case 7:
+      hipLaunchKernelGGL((k_cks_modup_cols<LOGN>), dim3(B * Lp * (Lp + 1) * Sp::WA), dim3(Sp::SA::T), 0, st, J,
+                         primes, tabs);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_cks_inner_blocks<LOGN>), dim3(2 * B * (Lp + 1) * Sp::WB), dim3(Sp::SB::T), 0, st, J,
+                         primes, tabs);
+      break;
+    case 9:
+      hipLaunchKernelGGL((k_cks_moddown_cols<LOGN>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
+                         tabs);
+      break;
     default:
       hipLaunchKernelGGL((k_ks_moddown_blocks<LOGN, false>), dim3(2 * B * Lp * Sp::WB), dim3(Sp::SB::T), 0, st, J,
                          primes, tabs);
@@ -2155,6 +2375,18 @@ hipError_t launch_ks_moddown_blocks(int log_n, const KsJob& job, const PrimeDev*
 hipError_t launch_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                hipStream_t st) {
   return ks_any(4, log_n, job, primes, tabs, st);
+}
+hipError_t launch_cks_modup_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                 hipStream_t st) {
+  return ks_any(7, log_n, job, primes, tabs, st);
+}
+hipError_t launch_cks_inner_blocks(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                   hipStream_t st) {
+  return ks_any(8, log_n, job, primes, tabs, st);
+}
+hipError_t launch_cks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                   hipStream_t st) {
+  return ks_any(9, log_n, job, primes, tabs, st);
 }
 hipError_t launch_ks_moddown_resc_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                        hipStream_t st) {
