@@ -889,6 +889,50 @@ he_status rotate_multi_coef(he_ctx* c, const u64* in, int B, int l, const int* s
   return HE_OK;
 }
 
+// rescale of n_ct ciphertexts [n_ct][2][l+1][N] (transform domain) into
+// coefficient form [n_ct][2][l][N]: the inverse block stages of every limb,
+// then per kept limb t the inverse column stages of limb t and of the
+// dropped limb l and (x_t - lift_t(x_l)) q_l^-1 -- the column kernel of the
+// coefficient-form rotations with the dropped limb in the special prime's
+// place and no addends (two launches; the residues are those of the
+// rescale followed by an inverse transform)
+he_status rescale_to_coef(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
+  const int n = c->n, nm = l + 1;
+  if (l < 1) return fail(HE_ELEVEL, "no level left to rescale");
+  if (n_ct < 1 || n_ct > HE_MAX_BATCH) return fail(HE_EINVAL, "rescale of %d ciphertexts", n_ct);
+  DBuf t3;
+  TRY(dalloc(c, t3, (size_t)2 * n_ct * nm * n));
+  NttJob J{};
+  J.src = in;
+  J.sa = (long long)nm * n;
+  J.sb = n;
+  J.na = 2 * n_ct;
+  J.nb = nm;
+  for (int t = 0; t < nm; t++) J.dst_prime[t] = (unsigned char)t;
+  J.mid = t3.p;
+  KsJob K{};
+  K.B = n_ct;
+  K.Lp = l;
+  K.nm = nm;
+  K.special = l;
+  K.t3 = t3.p;
+  K.out = out;
+  K.oa = (long long)l * n;
+  const size_t np = c->q.size();
+  K.h_src = (c->q[l] - 1) / 2;
+  for (int t = 0; t < l; t++) {
+    K.hq[t] = c->rd_hq[l * np + t];
+    K.inv[t] = c->rd_inv[l * np + t];
+    K.inv_sh[t] = c->rd_inv_sh[l * np + t];
+  }
+  // every limb read once, the kept limbs written
+  Prof pr(c, "rescale", 2.0 * n_ct * nm, 8.0 * n * 2 * n_ct * (2.0 * l + 1));
+  hipError_t e = launch_ntt_inv_blocks(c->log_n, J, c->d_primes, c->tabs, 2, c->st);
+  if (e == hipSuccess) e = launch_cks_moddown_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e != hipSuccess) return fail(HE_EHIP, "rescale into coefficient form: %s", hipGetErrorString(e));
+  return HE_OK;
+}
+
 // rescale of n_ct contiguous ciphertexts [n_ct][2][l+1][N] -> [n_ct][2][l][N]
 // add0 (nullable, n_ct = 1): a plaintext added to poly 0 of the result
 he_status rescale_multi(he_ctx* c, const u64* in, int n_ct, int l, u64* out, const u64* add0 = nullptr) {
@@ -2691,15 +2735,18 @@ static he_status conv_apply_many(he_ctx* c, const he_plan* const* plans, int nb,
     hipError_t e = launch_mul_plain_many(c->log_n, in, kp, nb, Lp, M.p, c->d_primes, c->st);
     if (e != hipSuccess) return fail(HE_EHIP, "mul_plain: %s", hipGetErrorString(e));
   }
-  TRY(rescale_multi(c, M.p, nb, l, Y.p));
   const double scale = x->scale * plans[0]->kernel->scale / (double)c->q[l];
   int steps = 0;
   while ((1u << steps) < plans[0]->kk) steps++;
   std::vector<int> st(nb);
-  // the chain in coefficient form where the fused key switch applies: one
-  // inverse transform before it and one forward transform after it
+  // the chain in coefficient form where the fused key switch applies: the
+  // rescale leaves its result in coefficient form, one forward transform
+  // follows the chain
   const bool coef = steps > 0 && coef_rotations(c, nb, l);
-  if (coef) TRY(ntt_rows(c, false, Y.p, Y.p, 2 * nb, l, (long long)l * n, (long long)l * n));
+  if (coef)
+    TRY(rescale_to_coef(c, M.p, nb, l, Y.p));
+  else
+    TRY(rescale_multi(c, M.p, nb, l, Y.p));
   for (int j = 0; j < steps; j++) {
     for (int b = 0; b < nb; b++) st[b] = norm_step(c, (long long)plans[0]->windows << j);
     if (st[0] == 0) {  // rotation by a multiple of N/2: x + x (in either form)
