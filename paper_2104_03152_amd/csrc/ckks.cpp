@@ -2580,6 +2580,34 @@ he_status he_rotate_across(he_ctx* run, const he_ct* const* a, const int32_t* st
 static he_status rotate_and_sum(he_ctx* c, he_ct* x, uint32_t count, uint32_t stride, he_ct** out) {
   int steps = 0;
   while ((1u << steps) < count) steps++;
+  // three or more steps in coefficient form (where the fused key switch
+  // applies and no step is a rotation by a multiple of N/2): one inverse
+  // and one forward transform around the chain
+  const int l = x->level, n = c->n;
+  bool coef = steps >= 3 && coef_rotations(c, 1, l + 1);
+  for (int j = 0; j < steps && coef; j++) coef = norm_step(c, (long long)stride << j) != 0;
+  if (coef) {
+    he_ct* y = nullptr;
+    he_status s = new_ct(c, l, x->scale, &y);
+    DBuf A, B;
+    const size_t w = 2 * (size_t)(l + 1) * n;
+    if (s == HE_OK) s = dalloc(c, A, w);
+    if (s == HE_OK) s = dalloc(c, B, w);
+    if (s == HE_OK) s = ntt_rows(c, false, x->d, A.p, 2, l + 1, (long long)(l + 1) * n, (long long)(l + 1) * n);
+    for (int j = 0; j < steps && s == HE_OK; j++) {
+      const int st = norm_step(c, (long long)stride << j);
+      s = rotate_multi_coef(c, A.p, 1, l, &st, B.p, true);
+      std::swap(A.p, B.p);
+    }
+    if (s == HE_OK) s = ntt_rows(c, true, A.p, y->d, 2, l + 1, (long long)(l + 1) * n, (long long)(l + 1) * n);
+    he_ct_free(x);
+    if (s != HE_OK) {
+      he_ct_free(y);
+      return s;
+    }
+    *out = y;
+    return HE_OK;
+  }
   for (int j = 0; j < steps; j++) {
     he_ct* y = nullptr;
     const int st = norm_step(c, (long long)stride << j);
