@@ -928,7 +928,7 @@ he_status rescale_to_coef(he_ctx* c, const u64* in, int n_ct, int l, u64* out) {
   // every limb read once, the kept limbs written
   Prof pr(c, "rescale", 2.0 * n_ct * nm, 8.0 * n * 2 * n_ct * (2.0 * l + 1));
   hipError_t e = launch_ntt_inv_blocks(c->log_n, J, c->d_primes, c->tabs, 2, c->st);
-  if (e == hipSuccess) e = launch_cks_moddown_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
+  if (e == hipSuccess) e = launch_cks_rescale_cols(c->log_n, K, c->d_primes, c->tabs, c->st);
   if (e != hipSuccess) return fail(HE_EHIP, "rescale into coefficient form: %s", hipGetErrorString(e));
   return HE_OK;
 }

@@ -176,6 +176,10 @@ hipError_t launch_cks_inner_blocks(int log_n, const KsJob& job, const PrimeDev* 
                                    hipStream_t st);
 hipError_t launch_cks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                    hipStream_t st);
+// the same column kernel as the last launch of a rescale into coefficient
+// form (t3: the inverse block stages of every limb; special: the dropped limb)
+hipError_t launch_cks_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                   hipStream_t st);
 hipError_t launch_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                hipStream_t st);
 

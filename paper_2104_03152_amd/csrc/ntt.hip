@@ -1450,8 +1450,10 @@ k_cks_inner_blocks(const KsJob J, const PrimeDev* __restrict__ primes, const Ntt
 
 // ModDown, job w = a Lp + t: the inverse column stages of the special limb
 // and of limb t, (u_t - lift_t(u_p)) p^-1 plus the addends (poly 0 of the
-// input at the automorphism's source; the input itself with add2) -> out
-template <int LOGN>
+// input at the automorphism's source; the input itself with add2) -> out.
+// TAG names the launch family: 0 a rotation, 1 a rescale into coefficient
+// form (the dropped limb in the special limb's place, no addends)
+template <int LOGN, int TAG>
 __global__ void __launch_bounds__(Split<LOGN>::SA::T)
 k_cks_moddown_cols(const KsJob J, const PrimeDev* __restrict__ primes, const NttTables tabs) {
   constexpr int N = 1 << LOGN;
@@ -2209,8 +2211,13 @@ hipError_t ks_launch(int which, const KsJob& J, const PrimeDev* primes, const Nt
                          primes, tabs);
       break;
     case 9:
-      hipLaunchKernelGGL((k_cks_moddown_cols<LOGN>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J, primes,
-                         tabs);
+    case 10:
+      if (which == 9)
+        hipLaunchKernelGGL((k_cks_moddown_cols<LOGN, 0>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J,
+                           primes, tabs);
+      else
+        hipLaunchKernelGGL((k_cks_moddown_cols<LOGN, 1>), dim3(2 * B * Lp * Sp::WA), dim3(Sp::SA::T), 0, st, J,
+                           primes, tabs);
       break;
     default:
       hipLaunchKernelGGL((k_ks_moddown_blocks<LOGN, false>), dim3(2 * B * Lp * Sp::WB), dim3(Sp::SB::T), 0, st, J,
@@ -2387,6 +2394,10 @@ hipError_t launch_cks_inner_blocks(int log_n, const KsJob& job, const PrimeDev* 
 hipError_t launch_cks_moddown_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                    hipStream_t st) {
   return ks_any(9, log_n, job, primes, tabs, st);
+}
+hipError_t launch_cks_rescale_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
+                                   hipStream_t st) {
+  return ks_any(10, log_n, job, primes, tabs, st);
 }
 hipError_t launch_ks_moddown_resc_cols(int log_n, const KsJob& job, const PrimeDev* primes, const NttTables& tabs,
                                        hipStream_t st) {

@@ -34,14 +34,20 @@ MARKER = "FillFunctor"
 # family -> (kernels that start a launch, kernels that complete it), as
 # name fragments of the N=8192 instantiations.  Small batches run the fused
 # forms (two-phase NTTs; the key switch's ModUp and ModDown in three kernels
-# each; rescale in three), large batches one workgroup per limb.
+# each, two each for rotations of coefficient-form ciphertexts; a ModDown
+# fused with its rescale in three; rescale in three, or two into
+# coefficient form), large batches one workgroup per limb.
 FAMILIES = [
     ("ntt_inv", ["k_ntt_inv_1<13, false, 0>", "k_ntt_inv_1<13, true, 0>", "k_ntt_inv<13"], ["k_ntt_inv_2<13>"]),
     ("ntt_fwd", ["k_ntt_fwd_a<13, 0>", "k_ntt_fwd<13, 0, 0>"], ["k_ntt_fwd_b<13, 0, 0>"]),
-    ("modup", ["k_ntt_inv_1<13, true, 1>", "k_ntt_inv_1<13, false, 1>", "k_ntt_fwd_a<13, 1>", "k_ntt_fwd<13, 1, 0>"],
+    ("modup", ["k_ntt_inv_1<13, true, 1>", "k_ntt_inv_1<13, false, 1>", "k_cks_modup_cols<13>",
+               "k_ntt_fwd_a<13, 1>", "k_ntt_fwd<13, 1, 0>"],
      ["k_ks_modup_cols<13>", "k_ntt_fwd_b<13, 1, 0>"]),
-    ("moddown", ["k_ks_special_blocks<13>"], ["k_ks_moddown_cols<13, 0>", "k_ks_moddown_blocks<13>"]),
-    ("rescale", ["k_ntt_inv_1<13, false, 2>"], ["k_ks_moddown_cols<13, 1>", "k_ntt_fwd_b<13, 3, 1>"]),
+    ("moddown", ["k_ks_special_blocks<13>", "k_cks_inner_blocks<13>"],
+     ["k_ks_moddown_cols<13, 0>", "k_ks_moddown_blocks<13, false>", "k_ks_moddown_resc_cols<13>",
+      "k_ks_moddown_blocks<13, true>", "k_cks_moddown_cols<13, 0>"]),
+    ("rescale", ["k_ntt_inv_1<13, false, 2>"],
+     ["k_ks_moddown_cols<13, 1>", "k_ntt_fwd_b<13, 3, 1>", "k_cks_moddown_cols<13, 1>"]),
     ("moddown+rescale (one workgroup per limb)", ["k_ntt_fwd_a<13, 2>", "k_ntt_fwd<13, 2, 1>"],
      ["k_ntt_fwd_b<13, 2, 1>"]),
     ("hoisted_cols", ["k_hoist_special<13>"], ["k_hoist_cols<13>"]),
