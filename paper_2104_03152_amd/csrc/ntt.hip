@@ -1036,6 +1036,7 @@ k_ks_moddown_resc_cols(const KsJob J, const PrimeDev* __restrict__ primes, const
 #ifndef HE_KS_UNROLL
 #define HE_KS_UNROLL 2
 #endif
+constexpr int kKsUnroll = HE_KS_UNROLL;
 // inner products of item b's digits with its key at modulus t for poly k, at
 // the E limb indices idx[] (Montgomery form keys: a lazy 128-bit sum of at
 // most 8 products, one reduction per group).  The E elements advance
@@ -1061,7 +1062,7 @@ __device__ __forceinline__ void ks_inner(const KsJob& J, const PrimeDev& P, int 
     for (int e = 0; e < E; e++) acc[e] = U128{0, 0};
     const int j1 = min(J.Lp, j0 + 8);
     // unrolled so that the key loads of several digits are in flight at once
-#pragma unroll HE_KS_UNROLL
+#pragma unroll kKsUnroll
     for (int j = j0; j < j1; j++) {
       u64 dj[E], kj[E];
 #pragma unroll
