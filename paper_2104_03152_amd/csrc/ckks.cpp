@@ -3275,7 +3275,16 @@ he_status he_tune_ntt(he_ctx* c, int32_t max_jobs, int32_t* split_jobs, double* 
   const int n_shapes = std::min(8, ntt_shapes(c->log_n, shapes, 8));
   DBuf buf;
   TRY(dalloc(c, buf, (size_t)jmax * n));
-  HIPC(hipMemsetAsync(buf.p, 0, (size_t)jmax * n * sizeof(u64), c->st));
+  {
+    // uniform residues (a stream of the tuner's own): the timing of
+    // all-zero data is not that of real data (the part draws less power on
+    // it and runs at a higher clock)
+    const int nbf = std::min(L, jmax);
+    ModList mods;
+    mods.n = nbf;
+    for (int i = 0; i < nbf; i++) mods.p[i] = (unsigned char)i;
+    HIPC(launch_sample_uniform(c->log_n, c->seed, 0x7e, 0, jmax / nbf, mods, mods, buf.p, c->d_primes, c->st));
+  }
   u64* tmp = (u64*)c->pool.get((size_t)jmax * n * sizeof(u64));
   if (!tmp) return fail(HE_EOOM, "tuning scratch");
   const NttTables saved = c->tabs;
