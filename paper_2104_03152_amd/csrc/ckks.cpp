@@ -202,6 +202,11 @@ struct he_ctx {
   Key relin;
   std::map<int, Key> gal;
   EncodeTables enc;
+  // the encoder's cosine table (double-double) and 5^j mod 2N on the device,
+  // for the exact recomputation of the coefficients the FFT cannot round
+  double* d_chi = nullptr;
+  double* d_clo = nullptr;
+  uint32_t* d_rot5 = nullptr;
   std::map<std::pair<int, int>, he_pt*> masks;
   bool prof = false;
   hipEvent_t ev_cross = nullptr;  // orders this stream against another context's (batches across contexts)
@@ -1101,33 +1106,34 @@ he_status galois_key(he_ctx* c, int step, int ml) {
 }
 
 // ---------------------------------------------------------------- encode helpers
-he_status upload_coeffs(he_ctx* c, const int64_t* co, int level, double scale, he_pt** out) {
+// z, nz, amb (nullable): the encoded values and the indices of the
+// coefficients left for the exact recomputation on the device
+he_status upload_coeffs(he_ctx* c, const int64_t* co, int level, double scale, he_pt** out,
+                        const double* z = nullptr, size_t nz = 0, const std::vector<int>* amb = nullptr) {
   const int n = c->n, Lp = level + 1;
-  std::vector<u64> h((size_t)Lp * n);
-  for (int i = 0; i < Lp; i++) {
-    const u64 q = c->q[i];
-    for (int k = 0; k < n; k++) {
-      int64_t v = co[k];
-      u64 r;
-      if (v >= 0) {
-        r = (u64)v % q;
-      } else {
-        u64 m = (u64)(-(v + 1)) + 1u;
-        r = m % q;
-        r = r ? q - r : 0;
-      }
-      h[(size_t)i * n + k] = r;
-    }
-  }
+  const size_t na = amb ? amb->size() : 0;
+  // the N signed coefficients go up once (with the values and indices the
+  // exact recomputation needs); the device finishes, reduces them into every
+  // limb and transforms
   he_pt* pt = nullptr;
   TRY(new_pt(c, level, scale, &pt));
-  hipError_t e = hipMemcpyAsync(pt->d, h.data(), h.size() * sizeof(u64), hipMemcpyHostToDevice, c->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (e != hipSuccess) {
-    he_pt_free(pt);
-    return fail(HE_EHIP, "plaintext upload: %s", hipGetErrorString(e));
+  DBuf raw;
+  he_status s = dalloc(c, raw, (size_t)n + (na ? nz + (na + 1) / 2 : 0));
+  hipError_t e = hipSuccess;
+  if (s == HE_OK) {
+    double* dz = (double*)(raw.p + n);
+    int* damb = (int*)(raw.p + n + nz);
+    e = hipMemcpyAsync(raw.p, co, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess && na) e = hipMemcpyAsync(dz, z, nz * sizeof(double), hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess && na) e = hipMemcpyAsync(damb, amb->data(), na * sizeof(int), hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);  // the sources are the caller's (pageable) memory
+    if (e == hipSuccess && na)
+      e = launch_encode_exact(c->log_n, dz, (int)nz, c->d_rot5, c->d_chi, c->d_clo, damb, (int)na,
+                              2.0 * scale / (double)n, (int64_t*)raw.p, c->st);
+    if (e == hipSuccess) e = launch_coeffs_to_limbs(c->log_n, (const int64_t*)raw.p, pt->d, Lp, c->d_primes, c->st);
+    if (e != hipSuccess) s = fail(HE_EHIP, "plaintext upload: %s", hipGetErrorString(e));
   }
-  he_status s = ntt_rows(c, true, pt->d, pt->d, 1, Lp, 0, 0);
+  if (s == HE_OK) s = ntt_rows(c, true, pt->d, pt->d, 1, Lp, 0, 0);
   if (s != HE_OK) {
     he_pt_free(pt);
     return s;
@@ -1141,9 +1147,10 @@ he_status encode_impl(he_ctx* c, const double* v, size_t n, double scale, int le
   if (n > (size_t)c->n / 2) return fail(HE_ERANGE, "%zu values exceed N/2 = %d slots", n, c->n / 2);
   if (!(scale > 0) || !std::isfinite(scale)) return fail(HE_EINVAL, "bad scale");
   std::vector<int64_t> co(c->n);
-  if (encode_coeffs(c->enc, v, n, scale, co.data()) != 0)
+  std::vector<int> amb;
+  if (encode_coeffs(c->enc, v, n, scale, co.data(), &amb) != 0)
     return fail(HE_ERANGE, "encoded coefficient reaches 2^62 (or a value is not finite)");
-  return upload_coeffs(c, co.data(), level, scale, out);
+  return upload_coeffs(c, co.data(), level, scale, out, v, n, &amb);
 }
 
 // coefficient form of rows (INTT on a copy) copied to the host
@@ -1375,6 +1382,23 @@ he_status he_ctx_create(const he_params* P, he_alloc_fn alloc, he_free_fn free_f
       c->rd_hq[i] = ((q[a] - 1) / 2) % q[t];
     }
   encode_tables_init(c->enc, c->log_n);
+  c->d_chi = (double*)c->pool.get(c->enc.chi.size() * sizeof(double));
+  c->d_clo = (double*)c->pool.get(c->enc.clo.size() * sizeof(double));
+  c->d_rot5 = (uint32_t*)c->pool.get(c->enc.rot5.size() * sizeof(uint32_t));
+  if (!c->d_chi || !c->d_clo || !c->d_rot5) {
+    he_ctx_destroy(c);
+    return fail(HE_EOOM, "encoder table allocation failed");
+  }
+  if (hipMemcpyAsync(c->d_chi, c->enc.chi.data(), c->enc.chi.size() * sizeof(double), hipMemcpyHostToDevice,
+                     c->st) != hipSuccess ||
+      hipMemcpyAsync(c->d_clo, c->enc.clo.data(), c->enc.clo.size() * sizeof(double), hipMemcpyHostToDevice,
+                     c->st) != hipSuccess ||
+      hipMemcpyAsync(c->d_rot5, c->enc.rot5.data(), c->enc.rot5.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                     c->st) != hipSuccess ||
+      hipStreamSynchronize(c->st) != hipSuccess) {
+    he_ctx_destroy(c);
+    return fail(HE_EHIP, "encoder table upload failed");
+  }
   *out = c;
   return HE_OK;
 }

@@ -365,6 +365,15 @@ hipError_t launch_mac_finish(int log_n, const u64* partial, int n_chunks, const 
                              const u64* diag0, u64* out, int n_dig, const PrimeDev* primes,
                              hipStream_t st);
 // Montgomery form of plaintext rows
+// encoding: the coefficients amb[0..n_amb) recomputed exactly (double-double
+// sums of z_j cos(pi t / N), chi + clo the cosine table as double-double,
+// rot5[j] = 5^j mod 2N) and rounded into co[k]; twice = 2 scale / N
+hipError_t launch_encode_exact(int log_n, const double* z, int nz, const uint32_t* rot5, const double* chi,
+                               const double* clo, const int* amb, int n_amb, double twice, int64_t* co,
+                               hipStream_t st);
+// signed coefficients co[N] (|v| < 2^62) reduced into limbs 0..n_limbs-1: out[i][k] = co[k] mod q_i
+hipError_t launch_coeffs_to_limbs(int log_n, const int64_t* co, u64* out, int n_limbs, const PrimeDev* primes,
+                                  hipStream_t st);
 hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods,
                           const PrimeDev* primes, hipStream_t st);
 

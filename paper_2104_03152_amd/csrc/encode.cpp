@@ -192,7 +192,8 @@ void encode_tables_init(EncodeTables& T, int log_n) {
   }
 }
 
-int encode_coeffs(const EncodeTables& T, const double* z, size_t nz, double scale, int64_t* out) {
+int encode_coeffs(const EncodeTables& T, const double* z, size_t nz, double scale, int64_t* out,
+                  std::vector<int>* amb_out) {
   const int n = T.n;
   if (nz > (size_t)n / 2) return -2;
   double sumabs = 0;
@@ -230,6 +231,12 @@ int encode_coeffs(const EncodeTables& T, const double* z, size_t nz, double scal
       continue;
     }
     amb.push_back(k);
+    out[k] = 0;
+  }
+  if (amb_out) {
+    // the range check above covers them too: |exact - v| stays within the bound
+    amb_out->swap(amb);
+    return 0;
   }
   // double-double recomputation of the ambiguous coefficients, split over
   // host threads when there are many (a full vector at scale 2^40 leaves a

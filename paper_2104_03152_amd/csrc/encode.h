@@ -14,7 +14,11 @@ struct EncodeTables {
 };
 
 void encode_tables_init(EncodeTables& T, int log_n);
-// integer coefficients round(scale * m_k); 0 or -2 (range) on failure
-int encode_coeffs(const EncodeTables& T, const double* z, size_t nz, double scale, int64_t* out);
+// integer coefficients round(scale * m_k); 0 or -2 (range) on failure.
+// amb (nullable): the indices whose FP64 value the error bound cannot round
+// are listed there and left 0 in out, for the caller to compute exactly
+// (otherwise they are recomputed here in double-double)
+int encode_coeffs(const EncodeTables& T, const double* z, size_t nz, double scale, int64_t* out,
+                  std::vector<int>* amb = nullptr);
 // slot values from centred coefficients given as doubles
 void decode_values(const EncodeTables& T, const double* m, double scale, double* out, size_t nz);

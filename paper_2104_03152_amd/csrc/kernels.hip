@@ -590,6 +590,111 @@ hipError_t launch_from_mont(int log_n, u64* data, int n_rows, const ModList& mod
   return hipGetLastError();
 }
 
+// ---- exact encoding of the coefficients the FP64 FFT's bound cannot round:
+// 2 scale / N * sum_j z_j cos(pi t_jk / N), t_jk = 5^j k mod 2N, in
+// double-double (error-free sums and FMA products), rounded half away from
+// zero.  One workgroup per coefficient.
+struct DD {
+  double hi, lo;
+};
+__device__ __forceinline__ DD dd_two_sum(double a, double b) {
+  const double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ DD dd_fast_sum(double a, double b) {
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ DD dd_plus(DD a, DD b) {
+  DD s = dd_two_sum(a.hi, b.hi);
+  const DD t = dd_two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = dd_fast_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return dd_fast_sum(s.hi, s.lo);
+}
+// nearest integer of a non-negative double-double, halves up
+__device__ __forceinline__ long long dd_round(DD a) {
+  if (a.hi >= 4503599627370496.0) {  // 2^52: hi is an integer
+    const double fl = floor(a.lo);
+    return (long long)a.hi + (long long)fl + (a.lo - fl >= 0.5 ? 1 : 0);
+  }
+  const double fi = floor(a.hi);
+  const DD s = dd_two_sum(a.hi - fi, a.lo);  // the exact fraction
+  double F = floor(s.hi);
+  if (s.hi == F && s.lo < 0) F -= 1.0;
+  const double d = (s.hi - F) - 0.5;
+  const bool up = d > 0 || (d == 0 && s.lo >= 0);
+  return (long long)fi + (long long)F + (up ? 1 : 0);
+}
+
+constexpr int kEncT = 256;
+__global__ void __launch_bounds__(kEncT) k_encode_exact(int log_n, const double* __restrict__ z, int nz,
+                                                        const uint32_t* __restrict__ rot5,
+                                                        const double* __restrict__ chi,
+                                                        const double* __restrict__ clo, const int* __restrict__ amb,
+                                                        double twice, int64_t* __restrict__ co) {
+  __shared__ double sh[kEncT], sl[kEncT];
+  const int k = amb[blockIdx.x];
+  const uint32_t mask = (2u << log_n) - 1u;
+  DD acc = {0.0, 0.0};
+  for (int j = threadIdx.x; j < nz; j += kEncT) {
+    const double zj = z[j];
+    if (zj == 0.0) continue;
+    const uint32_t t = (uint32_t)(((uint64_t)rot5[j] * (uint64_t)k) & mask);
+    const double ph = zj * chi[t];
+    double pl = fma(zj, chi[t], -ph);
+    pl += zj * clo[t];
+    acc = dd_plus(acc, dd_fast_sum(ph, pl));
+  }
+  sh[threadIdx.x] = acc.hi;
+  sl[threadIdx.x] = acc.lo;
+  __syncthreads();
+  for (int w = kEncT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const DD r = dd_plus(DD{sh[threadIdx.x], sl[threadIdx.x]}, DD{sh[threadIdx.x + w], sl[threadIdx.x + w]});
+      sh[threadIdx.x] = r.hi;
+      sl[threadIdx.x] = r.lo;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    // times 2 scale / N (a power of two times scale: one more product)
+    const double ph = sh[0] * twice;
+    double pl = fma(sh[0], twice, -ph);
+    pl += sl[0] * twice;
+    DD a = dd_fast_sum(ph, pl);
+    const bool neg = a.hi < 0 || (a.hi == 0 && a.lo < 0);
+    if (neg) a = DD{-a.hi, -a.lo};
+    const long long mag = dd_round(a);
+    co[k] = neg ? -mag : mag;
+  }
+}
+
+hipError_t launch_encode_exact(int log_n, const double* z, int nz, const uint32_t* rot5, const double* chi,
+                               const double* clo, const int* amb, int n_amb, double twice, int64_t* co,
+                               hipStream_t st) {
+  if (n_amb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_encode_exact, dim3(n_amb), dim3(kEncT), 0, st, log_n, z, nz, rot5, chi, clo, amb, twice, co);
+  return hipGetLastError();
+}
+
+// signed coefficients (|v| < 2^62) into the residues of limbs 0..n_limbs-1
+__global__ void k_coeffs_to_limbs(int log_n, const int64_t* __restrict__ co, u64* __restrict__ out, long long total,
+                                  const PrimeDev* __restrict__ primes) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  out[e] = red_signed(co[e & ((1LL << log_n) - 1)], primes[e >> log_n]);
+}
+
+hipError_t launch_coeffs_to_limbs(int log_n, const int64_t* co, u64* out, int n_limbs, const PrimeDev* primes,
+                                  hipStream_t st) {
+  const long long total = (long long)n_limbs << log_n;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coeffs_to_limbs, grid_for(total), dim3(BLK), 0, st, log_n, co, out, total, primes);
+  return hipGetLastError();
+}
+
 hipError_t launch_to_mont(int log_n, u64* data, int n_rows, const ModList& mods, const PrimeDev* primes,
                           hipStream_t st) {
   const long long total = (long long)n_rows << log_n;
