@@ -91,7 +91,7 @@ typedef struct {
  * up to this many limbs, default 256), HE_FUSE_MAX (fused key switch while
  * items x digits^2 stays within it, default 256), HE_HOIST_SPLIT_WGS (about
  * this many workgroups for the hoisted multiply-accumulate's block phase,
- * default 1536; 0 selects the one-kernel form), HE_COEF_ROT (rotate-and-sum
+ * at least two rotations each, default 4096; 0 selects the one-kernel form), HE_COEF_ROT (rotate-and-sum
  * chains -- the convolution's, slot sums of three or more steps -- with the
  * ciphertext in coefficient form between steps, default 1; 0: in the
  * transform domain).

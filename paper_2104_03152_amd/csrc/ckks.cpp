@@ -195,7 +195,7 @@ struct he_ctx {
   // rotate-and-sum chains in coefficient form (HE_COEF_ROT=0: in the
   // transform domain)
   int coef_rot = 1;
-  int hoist_split_wgs = 1536;  // two-phase hoisted multiply-accumulate, about this many workgroups (0: one kernel)
+  int hoist_split_wgs = 4096;  // two-phase hoisted multiply-accumulate, about this many workgroups (0: one kernel)
   bool have_keys = false;
   u64* d_s = nullptr;   // [L+1][N]
   u64* d_pk = nullptr;  // [2][L][N]
@@ -2964,7 +2964,10 @@ static he_status hoisted_core(he_ctx* c, const HoistItem* items, int R, const u6
     const int per_chunk = 2 * Lp * (split ? hoist_split_blocks(c->log_n) : 1);
     const int target = split ? c->hoist_split_wgs : 512;
     n_chunks = std::max(1, std::min(R, (target + per_chunk - 1) / per_chunk));
-    const int chunk = (R + n_chunks - 1) / n_chunks;
+    // at least two rotations per chunk in the two-phase form: a chunk of one
+    // leaves the block phase a single item to overlap and the finish one
+    // partial sum per rotation
+    const int chunk = std::max(split ? 2 : 1, (R + n_chunks - 1) / n_chunks);
     n_chunks = (R + chunk - 1) / chunk;
     TRY(dalloc(c, partial, (size_t)n_chunks * 2 * Lp * n));
     DBuf mid;
