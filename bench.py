@@ -797,9 +797,11 @@ def serving_bench(H, I, d, qps_list=(10, 20, 50, 100, 200, 500, 1000, 2000), n_c
     for qps in qps_list:
         n = n_requests or int(max(128, min(1000, 2 * qps)))
         reqs = S.make_requests(H, clients, n, qps, seed + qps)
+        log("serving: %d QPS, %d requests, continuous batching" % (qps, n))
         lat_b = S.serve(H, reqs, budget, batched=True)
         sb = S.summary(lat_b, reqs)
         S.reset(reqs)
+        log("serving: %d QPS, %d requests, one at a time" % (qps, n))
         lat_1 = S.serve(H, reqs, budget, batched=False)
         s1 = S.summary(lat_1, reqs)
         out["points"].append({"qps": qps, "requests": n,
